@@ -1,0 +1,350 @@
+"""Whole-step pins of the CPU oracle (Sec. 2.2 Steps 1-10) against invariants
+and closed forms: uniform states stay bit-exact, conservation, div B held to
+round-off by constrained transport, 1D problems reduce to 1D updates,
+direction permutation, second-order convergence on linear waves (Sec. 3.1.1),
+mirror symmetry, and the B = 0 limit against the exact Euler Riemann solution."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2402_05240_amd import inputs as I
+
+FIELDS = I.FIELDS
+
+
+def _close_state(a, b, rtol):
+    for f in FIELDS:
+        scale = max(1.0, float(np.abs(b[f]).max()))
+        assert np.abs(a[f] - b[f]).max() <= rtol * scale, f
+
+
+# ---------------------------------------------------------------------------
+# uniform states, conservation, div B
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("recon", [1, 2, 3])
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 0, 1), (1, 1, 1)])
+def test_uniform_state_bit_exact(recon, bc):
+    rng = np.random.default_rng(100 + recon)
+    gam = rng.uniform(1.1, 2.0)
+    v = tuple(rng.normal(0, 1, 3))
+    b = tuple(rng.normal(0, 1, 3))
+    g, s0 = I.uniform((7, 6, 5), rho=rng.uniform(0.5, 2), v=v, p=rng.uniform(0.1, 2), b=b,
+                      gamma=gam, recon=recon, bc=bc, length=(1.0, 0.8, 0.7))
+    s = s0
+    dt = ref.cfl_dt(g, s)
+    for _ in range(3):
+        s, dt, st = ref.step(g, s, dt, nthreads=1)
+        assert st == 0
+    for f in FIELDS:
+        assert np.array_equal(s[f], s0[f]), f
+
+
+def test_uniform_state_cfl_closed_form():
+    """Eq. dt with B along x: the fast speed is max(a, c_A) along x and
+    sqrt(a^2 + c_A^2) across it."""
+    rho, p, b, gam = 1.3, 0.7, 0.9, 1.4
+    v = (0.3, -0.2, 0.1)
+    g, s = I.uniform((8, 4, 2), rho=rho, v=v, p=p, b=(b, 0, 0), gamma=gam, cfl=0.35,
+                     length=(1.0, 0.6, 0.5))
+    a = math.sqrt(gam * p / rho)
+    ca = b / math.sqrt(rho)
+    expect = 0.35 * min(g.dx / (abs(v[0]) + max(a, ca)),
+                        g.dy / (abs(v[1]) + math.hypot(a, ca)),
+                        g.dz / (abs(v[2]) + math.hypot(a, ca)))
+    assert abs(ref.cfl_dt(g, s) - expect) <= 1e-15 * expect
+
+
+@pytest.mark.parametrize("recon", [2, 3])
+def test_conservation_and_divb_periodic(recon):
+    g, s0 = I.turbulence((12, 12, 12), recon=recon)
+    assert ref.divb_norm(g, s0) < 1e-13
+    s, dts, st = ref.run(g, s0, 3, nthreads=2)
+    assert st == 0
+    vol = g.dx * g.dy * g.dz
+    for f in ("rho", "E"):
+        a, b = s[f].sum() * vol, s0[f].sum() * vol
+        assert abs(a - b) <= 1e-13 * abs(b), f
+    for f in ("mx", "my", "mz"):
+        a, b = s[f].sum(), s0[f].sum()
+        assert abs(a - b) <= 1e-13 * np.abs(s0[f]).sum(), f
+    # mean field through each face family (faces 0..n-1 on a periodic axis)
+    for f, sl in (("bx", np.s_[:, :, :-1]), ("by", np.s_[:, :-1, :]), ("bz", np.s_[:-1, :, :])):
+        a, b = s[f][sl].sum(), s0[f][sl].sum()
+        assert abs(a - b) <= 1e-13 * np.abs(s0[f][sl]).sum(), f
+    assert ref.divb_norm(g, s) <= 1e-13
+
+
+def test_divb_outflow_blast():
+    g, s0 = I.blast((16, 16, 16), b0=1.0, recon=2)
+    s, _, st = ref.run(g, s0, 3, nthreads=2)
+    assert st == 0
+    assert ref.divb_norm(g, s) <= 1e-13
+
+
+def _div(g, b):
+    bx, by, bz = b
+    return ((bx[:, :, 1:] - bx[:, :, :-1]) / g.dx + (by[:, 1:, :] - by[:, :-1, :]) / g.dy
+            + (bz[1:, :, :] - bz[:-1, :, :]) / g.dz)
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 0)])
+def test_ct_update_preserves_divergence_for_any_emf(bc):
+    """The CT face update (Steps 5/9) changes no cell's divergence, whatever
+    the edge EMFs: div(curl) = 0 on the staggered mesh."""
+    rng = np.random.default_rng(11)
+    g, s = I.uniform((6, 5, 4), bc=bc, length=(1.0, 0.7, 0.9))
+    b = tuple(rng.normal(0, 1, g.field_shape(f)) for f in ("bx", "by", "bz"))
+    if bc[0] == 0:
+        b[0][:, :, -1] = b[0][:, :, 0]
+    if bc[1] == 0:
+        b[1][:, -1, :] = b[1][:, 0, :]
+    if bc[2] == 0:
+        b[2][-1, :, :] = b[2][0, :, :]
+    sh = ref.edge_shapes(g)
+    ex, ey, ez = (rng.normal(0, 1, sh[k]) for k in ("ex", "ey", "ez"))
+    # periodic axes: edges on the last plane equal the first
+    for e, name in ((ex, "ex"), (ey, "ey"), (ez, "ez")):
+        for ax_lab, arr_ax in ((0, 2), (1, 1), (2, 0)):
+            if bc[ax_lab] == 0 and e.shape[arr_ax] == g.field_shape("rho")[arr_ax] + 1:
+                idx0 = [slice(None)] * 3
+                idxn = [slice(None)] * 3
+                idx0[arr_ax] = 0
+                idxn[arr_ax] = -1
+                e[tuple(idxn)] = e[tuple(idx0)]
+    bo = ref.ct_update(g, b, ex, ey, ez, 0.37)
+    d0, d1 = _div(g, b), _div(g, bo)
+    assert np.abs(d1 - d0).max() <= 1e-13 * np.abs(d0).max()
+
+
+# ---------------------------------------------------------------------------
+# 1D problems through the 3D integrator
+# ---------------------------------------------------------------------------
+
+def _prims(g, s):
+    bcx = 0.5 * (s["bx"][:, :, :-1] + s["bx"][:, :, 1:])
+    bcy = 0.5 * (s["by"][:, :-1, :] + s["by"][:, 1:, :])
+    bcz = 0.5 * (s["bz"][:-1, :, :] + s["bz"][1:, :, :])
+    rho = s["rho"]
+    vx, vy, vz = s["mx"] / rho, s["my"] / rho, s["mz"] / rho
+    p = (g.gamma - 1) * (s["E"] - 0.5 * rho * (vx * vx + vy * vy + vz * vz)
+                         - 0.5 * (bcx * bcx + bcy * bcy + bcz * bcz))
+    return rho, vx, vy, vz, p, bcx, bcy, bcz
+
+
+def test_pcm_edge_emf_equals_face_emf_for_1d_problem():
+    """For a state varying along x only, the CT edge EMFs (Eq. emf-edge with
+    the upwinded slopes) reduce to the x-face EMFs of Table emf:
+    E_z = -F_x[B_y], E_y = +F_x[B_z]."""
+    g, s, _ = I.linear_wave((12, 3, 2), "fast", amp=0.05, recon=1)
+    ex, ey, ez = ref.edge_emfs(g, s, 1, nthreads=1)
+    rho, vx, vy, vz, p, bcx, bcy, bcz = _prims(g, s)
+    for i in range(g.nx + 1):
+        il, ir = (i - 1) % g.nx, i % g.nx
+        wl = [rho[0, 0, il], vx[0, 0, il], vy[0, 0, il], vz[0, 0, il], p[0, 0, il], bcy[0, 0, il], bcz[0, 0, il]]
+        wr = [rho[0, 0, ir], vx[0, 0, ir], vy[0, 0, ir], vz[0, 0, ir], p[0, 0, ir], bcy[0, 0, ir], bcz[0, 0, ir]]
+        f = ref.hlld(wl, wr, s["bx"][0, 0, i], g.gamma)
+        assert np.abs(ez[:, :, i] - (-f[5])).max() <= 1e-14
+        assert np.abs(ey[:, :, i] - f[6]).max() <= 1e-14
+    assert np.abs(ex).max() <= 1e-14 * np.abs(ez).max() + 1e-300
+
+
+@pytest.mark.parametrize("recon", [2, 3])
+def test_1d_problem_columns_bitwise_identical(recon):
+    g, s, _ = I.linear_wave((16, 3, 4), "fast", amp=0.05, recon=recon)
+    s, _, _ = ref.run(g, s, 3, nthreads=1)
+    for f in FIELDS:
+        a = s[f]
+        assert np.array_equal(a, np.broadcast_to(a[:1, :1, :], a.shape)), f
+
+
+def _permute_to_x(s, axis):
+    """Map a state whose 1D variation is along `axis` onto an x-problem with
+    the same sweep-frame components."""
+    if axis == 0:
+        return s
+    # lab components: n = axis, t1 = axis+1, t2 = axis+2 -> x, y, z
+    m = {}
+    comp = [(axis + k) % 3 for k in range(3)]
+    mom = ("mx", "my", "mz")
+    bb = ("bx", "by", "bz")
+    arr_ax = [2, 1, 0]   # lab axis -> array axis
+    order = [arr_ax[comp[2]], arr_ax[comp[1]], arr_ax[comp[0]]]  # new (z, y, x) <- old axes
+
+    def tr(a):
+        return np.transpose(a, order)
+    for f in ("rho", "E"):
+        m[f] = tr(s[f])
+    for k in range(3):
+        m[mom[k]] = tr(s[mom[comp[k]]])
+        m[bb[k]] = tr(s[bb[comp[k]]])
+    return m
+
+
+@pytest.mark.parametrize("recon", [2, 3])
+def test_direction_permutation(recon):
+    """The same 1D problem along x, y and z gives the same result (Sec. 3.1.1:
+    identical results in all three directions)."""
+    res = []
+    for axis in range(3):
+        n = [3, 3, 3]
+        n[axis] = 16
+        g, s, _ = I.linear_wave(tuple(n), "alfven", amp=0.05, axis=axis, recon=recon)
+        s, dts, _ = ref.run(g, s, 4, nthreads=1)
+        res.append((_permute_to_x(s, axis), dts))
+    for axis in (1, 2):
+        assert np.allclose(res[axis][1], res[0][1], rtol=1e-14, atol=0)
+        _close_state(res[axis][0], res[0][0], 1e-14)
+
+
+def test_linear_wave_second_order_convergence():
+    """Sec. 3.1.1: L2 norm of the per-variable L1 errors after one period
+    falls at second order; PPMC is more accurate than PLMC."""
+    def err(N, recon):
+        g, s0, T = I.linear_wave((N, 1, 1), "fast", recon=recon)
+        s, _, st = ref.run(g, s0, 0, t_end=T, nthreads=1)
+        assert st == 0
+        e = [np.mean(np.abs(s[f] - s0[f])) for f in FIELDS[:5]]
+        for f, sl0, sl1 in (("bx", np.s_[:, :, :-1], np.s_[:, :, 1:]), ("by", np.s_[:, :-1, :], np.s_[:, 1:, :]),
+                            ("bz", np.s_[:-1, :, :], np.s_[1:, :, :])):
+            e.append(np.mean(np.abs(0.5 * (s[f][sl0] + s[f][sl1]) - 0.5 * (s0[f][sl0] + s0[f][sl1]))))
+        return math.sqrt(sum(x * x for x in e))
+    e32, e64 = err(32, 2), err(64, 2)
+    assert math.log2(e32 / e64) > 1.8
+    assert e64 < 1.5e-8
+    p32 = err(32, 3)
+    assert p32 < 0.7 * e32
+
+
+def _l2_of_l1(s, s0):
+    return math.sqrt(sum(float(np.mean(np.abs(s[f] - s0[f]))) ** 2 for f in FIELDS))
+
+
+@pytest.mark.parametrize("wave", ["fast", "alfven"])
+def test_oblique_linear_wave_second_order(wave):
+    """A grid-oblique wave (k along (1,1,0)) exercises the 2D CT edge EMFs."""
+    errs = []
+    for N in (16, 32):
+        g, s0, T = I.oblique_wave((N, N, 1), wave, recon=2)
+        s, _, st = ref.run(g, s0, 0, t_end=T, nthreads=4)
+        assert st == 0
+        errs.append(_l2_of_l1(s, s0))
+    assert math.log2(errs[0] / errs[1]) > 1.45
+    assert errs[1] < 6e-8
+
+
+def test_field_loop_advection():
+    """Sec. 3.1.3: an advected field loop dissipates slowly and monotonically
+    and keeps div B at round-off.  The upwinded CT slope terms decide this:
+    reversing the upwind side or the sign of the slope terms (Eqs. emf-edge,
+    emf-upwind-slope) makes the magnetic energy grow without bound."""
+    g, s = I.field_loop_2d(32)
+    b2 = lambda st: float(np.mean((0.5 * (st["bx"][:, :, :-1] + st["bx"][:, :, 1:])) ** 2
+                                  + (0.5 * (st["by"][:, :-1, :] + st["by"][:, 1:, :])) ** 2))
+    e0 = b2(s)
+    dt = ref.cfl_dt(g, s)
+    hist = []
+    for _ in range(40):
+        s, dt, st = ref.step(g, s, dt, nthreads=4)
+        assert st == 0
+        hist.append(b2(s) / e0)
+    assert all(b <= a * (1 + 1e-12) for a, b in zip([1.0] + hist[:-1], hist))
+    assert 0.8 < hist[-1] < 0.95
+    assert ref.divb_norm(g, s) <= 1e-13
+
+
+# ---------------------------------------------------------------------------
+# symmetry and the hydrodynamic limit
+# ---------------------------------------------------------------------------
+
+def test_blast_mirror_symmetry_plmc():
+    """z -> -z mirror symmetry of the magnetised blast (B_z = 0)."""
+    g, s = I.blast((16, 16, 16), b0=1.0, recon=2)
+    s, _, st = ref.run(g, s, 3, nthreads=2)
+    assert st == 0
+    m = {f: s[f][::-1].copy() for f in FIELDS}
+    m["mz"] = -m["mz"]
+    m["bz"] = -m["bz"]
+    _close_state(m, s, 1e-13)
+
+
+def _sod_exact(x, t, gam=1.4, rl=1.0, pl=1.0, rr=0.125, pr=0.1, x0=0.5):
+    """Exact solution of the Sod shock tube (Toro, ch. 4): left rarefaction,
+    contact, right shock; u_L = u_R = 0."""
+    cl, cr = math.sqrt(gam * pl / rl), math.sqrt(gam * pr / rr)
+
+    def f(p, rk, pk, ck):
+        if p > pk:
+            A, B = 2 / ((gam + 1) * rk), (gam - 1) / (gam + 1) * pk
+            return (p - pk) * math.sqrt(A / (p + B))
+        return 2 * ck / (gam - 1) * ((p / pk) ** ((gam - 1) / (2 * gam)) - 1)
+    lo, hi = 1e-8, 10.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if f(mid, rl, pl, cl) + f(mid, rr, pr, cr) > 0:
+            hi = mid
+        else:
+            lo = mid
+    ps = 0.5 * (lo + hi)
+    us = 0.5 * (f(ps, rr, pr, cr) - f(ps, rl, pl, cl))
+    rsl = rl * (ps / pl) ** (1 / gam)
+    rsr = rr * ((ps / pr + (gam - 1) / (gam + 1)) / ((gam - 1) / (gam + 1) * ps / pr + 1))
+    ssh = us / (1 - rr / rsr)   # shock speed from mass conservation
+    csl = cl * (ps / pl) ** ((gam - 1) / (2 * gam))
+    out = np.empty_like(x)
+    for k, xx in enumerate(x):
+        xi = (xx - x0) / t
+        if xi < -cl:
+            out[k] = rl
+        elif xi < us - csl:
+            c = 2 / (gam + 1) * (cl - (gam - 1) / 2 * xi)
+            out[k] = rl * (c / cl) ** (2 / (gam - 1))
+        elif xi < us:
+            out[k] = rsl
+        elif xi < ssh:
+            out[k] = rsr
+        else:
+            out[k] = rr
+    return out
+
+
+def test_sod_shock_tube_matches_exact_solution():
+    """With B = 0 the scheme is a hydrodynamic VL scheme with HLLC fluxes; its
+    Sod solution converges to the exact Riemann solution."""
+    errs = []
+    for N in (64, 128):
+        g, s = I.uniform((N, 1, 1), rho=1.0, p=1.0, b=(0, 0, 0), gamma=1.4, bc=(1, 0, 0))
+        xc = (np.arange(N) + 0.5) / N
+        right = xc > 0.5
+        s["rho"][..., right] = 0.125
+        s["E"][..., right] = 0.1 / 0.4
+        s, _, st = ref.run(g, s, 0, t_end=0.2, nthreads=1)
+        assert st == 0
+        errs.append(np.mean(np.abs(s["rho"][0, 0] - _sod_exact(xc, 0.2))))
+    assert errs[0] < 0.02 and errs[1] < 0.7 * errs[0]
+
+
+def test_inplace_and_restart_match_straight_run():
+    """The step is a pure function of (state, dt): in-place equals
+    out-of-place, and a saved-and-reloaded state continues bit-exactly."""
+    g, s0 = I.turbulence((10, 10, 10))
+    dt = ref.cfl_dt(g, s0)
+    a, dta, _ = ref.step(g, s0, dt, nthreads=1)
+    b = I.copy_state(s0)
+    b, dtb, _ = ref.step(g, b, dt, nthreads=1, inplace=True)
+    for f in FIELDS:
+        assert np.array_equal(a[f], b[f])
+    assert dta == dtb
+
+    def advance(s, dt, n):
+        for _ in range(n):
+            s, dt, _ = ref.step(g, s, dt, nthreads=1)
+        return s, dt
+    straight, _ = advance(s0, dt, 4)
+    half, dt_half = advance(s0, dt, 2)
+    saved = {f: np.array(half[f], copy=True) for f in FIELDS}
+    rest, _ = advance(saved, dt_half, 2)
+    for f in FIELDS:
+        assert np.array_equal(rest[f], straight[f])
