@@ -1,0 +1,146 @@
+/*
+ * vlct.h -- C ABI of the MI355X (gfx950) library that advances 3D ideal MHD by
+ * one Van Leer + Constrained Transport (VL+CT) time step, following Caddy &
+ * Schneider, "Cholla-MHD", Sec. 2.2 (Steps 1-10):
+ *
+ *   predictor : PCM interface states + HLLD fluxes (Steps 2-3), CT edge
+ *               electric fields (Step 4), half-step update to t + dt/2 (Step 5);
+ *   corrector : PLMC or PPMC characteristic reconstruction of the half-step
+ *               state (Step 6), HLLD fluxes (Step 7), CT edge fields with the
+ *               half-step reference field (Step 8), full update from t to
+ *               t + dt (Step 9);
+ *   next dt   : CFL condition of the updated state (Step 1, Eq. dt), reduced
+ *               over the grid on the device.
+ *
+ * The problem statement follows the paper: conserved cell-centred variables
+ * plus face-centred magnetic field, gamma, cell widths and dt go in; the
+ * updated state and the next dt come out.
+ *
+ * Memory: every pointer in vlct_state, dt/next_dt/status and the workspace are
+ * DEVICE pointers owned by the caller; the library allocates nothing and never
+ * synchronises with the host inside vlct_step / vlct_cfl_dt.  All work is
+ * enqueued on `stream` (a hipStream_t; NULL = the default stream) and is
+ * stream-ordered, so a call can be captured into a HIP graph.  Arrays are
+ * FP64, C order [k][j][i] with x fastest:
+ *
+ *   rho, mx, my, mz, E : nz*ny*nx        cell averages (density, momentum, total energy)
+ *   bx                 : nz*ny*(nx+1)    B_x on x-face i-1/2 of cell i, i = 0..nx
+ *   by                 : nz*(ny+1)*nx    B_y on y-face j-1/2, j = 0..ny
+ *   bz                 : (nz+1)*ny*nx    B_z on z-face k-1/2, k = 0..nz
+ *
+ * Each face stores only its normal field component (staggered mesh, Sec. 2.2).
+ * Units have mu0 = 1; E = P/(gamma-1) + rho v^2/2 + B^2/2 with the cell-centred
+ * field taken as the average of the two face values (Sec. 2.1, Step 1).
+ *
+ * Boundaries (per axis): periodic, or outflow (zero gradient: cell and
+ * transverse-face indices clamp into the grid, normal-face indices clamp into
+ * [0, n]).  On a periodic axis the last face plane duplicates the first: its
+ * input value is ignored and its output is written equal to face 0.
+ *
+ * Errors: functions return VLCT_OK or a VLCT_E* code and never abort.  Problems
+ * that arise inside kernels (a floor applied, a non-finite result) are OR-ed
+ * into *status_dev as VLCT_STATUS_* bits when status_dev is not NULL.
+ */
+#ifndef VLCT_H
+#define VLCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define VLCT_OK 0
+#define VLCT_EINVAL 1        /* bad grid descriptor, NULL pointer, unknown option */
+#define VLCT_EWORKSPACE 2    /* workspace NULL or smaller than vlct_workspace_bytes() */
+#define VLCT_EHIP 3          /* a HIP launch or runtime call failed */
+#define VLCT_EUNSUPPORTED 4  /* valid request this build does not implement */
+
+/* corrector reconstruction (Sec. 2.2 Step 6) */
+#define VLCT_RECON_PCM 1     /* first order (debugging mode of Step 2) */
+#define VLCT_RECON_PLMC 2    /* piecewise linear, limited in characteristic variables */
+#define VLCT_RECON_PPMC 3    /* piecewise parabolic, limited in characteristic variables */
+
+/* boundary condition per axis */
+#define VLCT_BC_PERIODIC 0
+#define VLCT_BC_OUTFLOW 1
+
+/* bits OR-ed into *status_dev */
+#define VLCT_STATUS_PRESSURE_FLOOR 1u  /* a derived or reconstructed pressure was floored */
+#define VLCT_STATUS_DENSITY_FLOOR 2u   /* a derived or reconstructed density was floored */
+#define VLCT_STATUS_NONFINITE 4u       /* the updated state holds a NaN or Inf */
+
+typedef struct vlct_grid {
+    int32_t nx, ny, nz;  /* interior cells per axis, 1 <= n <= 4096 */
+    double dx, dy, dz;   /* cell widths, > 0 */
+    double gamma;        /* adiabatic index, > 1 */
+    double cfl;          /* Courant number, 0 < cfl <= 0.5 (Sec. 2.2 Step 1) */
+    int32_t recon;       /* VLCT_RECON_* */
+    int32_t bc[3];       /* VLCT_BC_* for x, y, z */
+} vlct_grid;
+
+typedef struct vlct_state {
+    double *rho, *mx, *my, *mz, *E; /* device, nz*ny*nx each */
+    double *bx, *by, *bz;           /* device, face layouts above */
+} vlct_state;
+
+/* Bytes of device workspace vlct_step / vlct_cfl_dt need for this grid
+ * (0 if the descriptor is invalid).  The workspace holds the half-step state,
+ * ghost-padded primitives, face fluxes and edge fields; its contents are
+ * scratch between calls. */
+size_t vlct_workspace_bytes(const vlct_grid *g);
+
+/* CFL time step of state `s` (Sec. 2.2 Step 1, Eq. dt):
+ *   dt = cfl / max_cells max_l (|v_l| + c_f,l) / d_l,
+ * c_f,l the fast magnetosonic speed from cell-centred values with B_l as the
+ * longitudinal field.  Writes one double to dt_dev.  Deterministic. */
+int vlct_cfl_dt(const vlct_grid *g, const vlct_state *s, double *dt_dev, void *ws,
+                size_t ws_bytes, void *stream);
+
+/* One VL+CT step of size *dt_dev from `in` to `out` (Sec. 2.2 Steps 2-9).
+ * `out` may alias `in` (all eight pointers equal) or be disjoint from it;
+ * partial overlap is not allowed.  next_dt_dev (nullable) receives the CFL
+ * step of the result; status_dev (nullable) accumulates VLCT_STATUS_* bits and
+ * is never cleared by the library.  dt is read on the device, so a chain of
+ * steps needs no host round trip: pass the previous call's next_dt_dev as the
+ * next call's dt_dev. */
+int vlct_step(const vlct_grid *g, const vlct_state *in, const vlct_state *out,
+              const double *dt_dev, double *next_dt_dev, uint32_t *status_dev, void *ws,
+              size_t ws_bytes, void *stream);
+
+/* --- diagnostics ----------------------------------------------------------
+ * Launch observer: when set, every vlct_step / vlct_cfl_dt call invokes
+ * cb(user, kernel, phase, stream) on the calling host thread immediately
+ * before (phase 0) and after (phase 1) it enqueues each kernel, with the
+ * stream the kernel goes to, so a profiler can bracket one kernel family with
+ * events on that stream.  `kernel` is a VLCT_KERNEL_* id.  NULL removes the
+ * observer.  The observer is process-wide; set it while no other thread is
+ * inside the library.  Returns VLCT_OK. */
+#define VLCT_KERNEL_PRIMS 0        /* primitive variables (both stages) */
+#define VLCT_KERNEL_FLUX_PCM 1     /* predictor: PCM states + HLLD, one launch per axis */
+#define VLCT_KERNEL_FLUX_RECON 2   /* corrector: PLMC/PPMC states + HLLD, one launch per axis */
+#define VLCT_KERNEL_EDGES 3        /* CT edge electric fields (both stages) */
+#define VLCT_KERNEL_UPDATE_HALF 4  /* half-step cell and face update */
+#define VLCT_KERNEL_UPDATE_FULL 5  /* full-step cell and face update */
+#define VLCT_KERNEL_DT 6           /* CFL reduction (two launches) */
+#define VLCT_KERNEL_COUNT 7
+typedef void (*vlct_launch_observer)(void *user, int kernel, int phase, void *stream);
+int vlct_set_launch_observer(vlct_launch_observer cb, void *user);
+
+/* Name of a VLCT_KERNEL_* id ("?" if unknown). */
+const char *vlct_kernel_name(int kernel);
+
+/* Static description of a return code. */
+const char *vlct_strerror(int code);
+
+/* ABI version of this header (major*100 + minor). */
+int vlct_abi_version(void);
+
+#define VLCT_ABI_VERSION 100
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VLCT_H */

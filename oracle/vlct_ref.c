@@ -1014,10 +1014,15 @@ static double cfl_from_state(const vref_grid *vg, const double *const st[8], uin
         for (int j = 0; j < n[1]; ++j)
             for (int i = 0; i < n[0]; ++i) {
                 size_t c = ic(n, i, j, k);
+                /* the high faces go through the face map: on a periodic axis the
+                 * stored duplicate of face 0 is not read */
+                int ip = map_face(i + 1, n[0], vg->bc[0]);
+                int jp = map_face(j + 1, n[1], vg->bc[1]);
+                int kp = map_face(k + 1, n[2], vg->bc[2]);
                 double bc[3];
-                bc[0] = 0.5 * (st[5][ifc(n, 0, i, j, k)] + st[5][ifc(n, 0, i + 1, j, k)]);
-                bc[1] = 0.5 * (st[6][ifc(n, 1, i, j, k)] + st[6][ifc(n, 1, i, j + 1, k)]);
-                bc[2] = 0.5 * (st[7][ifc(n, 2, i, j, k)] + st[7][ifc(n, 2, i, j, k + 1)]);
+                bc[0] = 0.5 * (st[5][ifc(n, 0, i, j, k)] + st[5][ifc(n, 0, ip, j, k)]);
+                bc[1] = 0.5 * (st[6][ifc(n, 1, i, j, k)] + st[6][ifc(n, 1, i, jp, k)]);
+                bc[2] = 0.5 * (st[7][ifc(n, 2, i, j, k)] + st[7][ifc(n, 2, i, j, kp)]);
                 double rho = st[0][c];
                 if (!(rho >= FLOOR_RHO)) { rho = FLOOR_RHO; stb |= VREF_STATUS_DENSITY_FLOOR; }
                 double v[3] = {st[1][c] / rho, st[2][c] / rho, st[3][c] / rho};

@@ -1,0 +1,926 @@
+// vlct.hip -- one VL+CT step of 3D ideal MHD on gfx950 (Caddy & Schneider,
+// "Cholla-MHD", Sec. 2.2) behind the C ABI of include/vlct.h.
+//
+// Step structure (all kernels on the caller's stream, state resident in HBM):
+//   stage(U^n, PCM)        : prims -> 3 x (HLLD fluxes) -> edge EMFs -> half update
+//   stage(U^{n+1/2}, PLMC) : prims -> 3 x (reconstruction + HLLD) -> edge EMFs
+//                            -> full update from U^n -> next-dt reduction
+// Boundary conditions enter only through the primitive kernel, which fills a
+// ghost-padded primitive array by index mapping (wrap / clamp), and through
+// face-index mapping when the stored normal field is read.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+
+#include "../../include/vlct.h"
+#include "mhd_physics.hpp"
+
+namespace vlct {
+
+constexpr int kGhost = 3;          // ghost layers of the primitive workspace
+constexpr int kBlock = 256;        // threads per block (4 wave64s)
+constexpr int kMaxN = 4096;
+
+using idx_t = long long;
+
+// ---------------------------------------------------------------------------
+// geometry shared by every kernel
+// ---------------------------------------------------------------------------
+struct Geom {
+    int n[3];
+    int bc[3];
+    double dl[3];
+    double gamma, gm1i, cfl;
+    int p[3];  // padded primitive dims n + 2G
+};
+
+__host__ __device__ __forceinline__ int map_cell(int i, int n, int bc)
+{
+    if (bc == VLCT_BC_PERIODIC) {
+        int m = i % n;
+        return m < 0 ? m + n : m;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// normal-face index: periodic faces wrap into [0, n-1], outflow clamps into [0, n]
+__host__ __device__ __forceinline__ int map_face(int i, int n, int bc)
+{
+    if (bc == VLCT_BC_PERIODIC) {
+        int m = i % n;
+        return m < 0 ? m + n : m;
+    }
+    return i < 0 ? 0 : (i > n ? n : i);
+}
+
+// stored face arrays of the state: axis d has n_d + 1 faces along d
+__device__ __forceinline__ idx_t face_store(const Geom &g, int d, int i, int j, int k)
+{
+    const idx_t nx = g.n[0] + (d == 0), ny = g.n[1] + (d == 1);
+    return ((idx_t)k * ny + j) * nx + i;
+}
+
+__device__ __forceinline__ idx_t cell_store(const Geom &g, int i, int j, int k)
+{
+    return ((idx_t)k * g.n[1] + j) * g.n[0] + i;
+}
+
+// padded primitive index, i,j,k in [-G, n+G-1]
+__device__ __forceinline__ idx_t pidx(const Geom &g, int i, int j, int k)
+{
+    return ((idx_t)(k + kGhost) * g.p[1] + (j + kGhost)) * g.p[0] + (i + kGhost);
+}
+
+// flux arrays of axis d: normal index in [0, n_d], transverse in [-1, n_e]
+__host__ __device__ __forceinline__ idx_t flux_dim(const int n[3], int d, int e)
+{
+    return n[e] + (e == d ? 1 : 2);
+}
+__device__ __forceinline__ idx_t fidx(const Geom &g, int d, int i, int j, int k)
+{
+    const idx_t X = flux_dim(g.n, d, 0), Y = flux_dim(g.n, d, 1);
+    return ((idx_t)(k + (d != 2)) * Y + (j + (d != 1))) * X + (i + (d != 0));
+}
+
+// edge arrays of axis a: index in [0, n_e] across a, [0, n_a - 1] along a
+__host__ __device__ __forceinline__ idx_t edge_dim(const int n[3], int a, int e)
+{
+    return n[e] + (e != a ? 1 : 0);
+}
+__device__ __forceinline__ idx_t eidx(const Geom &g, int a, int i, int j, int k)
+{
+    const idx_t X = edge_dim(g.n, a, 0), Y = edge_dim(g.n, a, 1);
+    return ((idx_t)k * Y + j) * X + i;
+}
+
+struct StateP {
+    const double *u[5];
+    const double *b[3];
+};
+struct StateW {
+    double *u[5];
+    double *b[3];
+};
+struct Prims {
+    double *w[8];  // rho, vx, vy, vz, P, Bcx, Bcy, Bcz on padded cells
+};
+struct Flux {
+    double *f[3][8];  // per axis: 7 sweep-frame components + upwind indicator
+};
+struct Edges {
+    double *e[3];
+};
+
+// ---------------------------------------------------------------------------
+// primitive variables on the ghost-padded grid (Sec. 2.1; B_cc = face average,
+// Step 1); the boundary conditions are applied here by index mapping
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_prims(Geom g, StateP s, Prims P, uint32_t *status)
+{
+    const idx_t tot = (idx_t)g.p[0] * g.p[1] * g.p[2];
+    const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= tot) return;
+    const int pi = (int)(t % g.p[0]);
+    const idx_t r = t / g.p[0];
+    const int pj = (int)(r % g.p[1]);
+    const int pk = (int)(r / g.p[1]);
+    const int i = pi - kGhost, j = pj - kGhost, k = pk - kGhost;
+    const int mi = map_cell(i, g.n[0], g.bc[0]);
+    const int mj = map_cell(j, g.n[1], g.bc[1]);
+    const int mk = map_cell(k, g.n[2], g.bc[2]);
+    const idx_t c = cell_store(g, mi, mj, mk);
+    const double bx0 = s.b[0][face_store(g, 0, map_face(i, g.n[0], g.bc[0]), mj, mk)];
+    const double bx1 = s.b[0][face_store(g, 0, map_face(i + 1, g.n[0], g.bc[0]), mj, mk)];
+    const double by0 = s.b[1][face_store(g, 1, mi, map_face(j, g.n[1], g.bc[1]), mk)];
+    const double by1 = s.b[1][face_store(g, 1, mi, map_face(j + 1, g.n[1], g.bc[1]), mk)];
+    const double bz0 = s.b[2][face_store(g, 2, mi, mj, map_face(k, g.n[2], g.bc[2]))];
+    const double bz1 = s.b[2][face_store(g, 2, mi, mj, map_face(k + 1, g.n[2], g.bc[2]))];
+    const double bcx = 0.5 * (bx0 + bx1);
+    const double bcy = 0.5 * (by0 + by1);
+    const double bcz = 0.5 * (bz0 + bz1);
+    double d = s.u[0][c];
+    uint32_t st = 0;
+    if (!(d >= kFloorRho)) { d = kFloorRho; st |= kStatusDensityFloor; }
+    const double id = 1.0 / d;
+    const double vx = s.u[1][c] * id, vy = s.u[2][c] * id, vz = s.u[3][c] * id;
+    const double ke = 0.5 * d * (vx * vx + vy * vy + vz * vz);
+    const double me = 0.5 * (bcx * bcx + bcy * bcy + bcz * bcz);
+    double pr = (g.gamma - 1.0) * (s.u[4][c] - ke - me);
+    if (!(pr >= kFloorP)) { pr = kFloorP; st |= kStatusPressureFloor; }
+    if (st && status) atomicOr(status, st);
+    const idx_t o = t;
+    P.w[0][o] = d;
+    P.w[1][o] = vx;
+    P.w[2][o] = vy;
+    P.w[3][o] = vz;
+    P.w[4][o] = pr;
+    P.w[5][o] = bcx;
+    P.w[6][o] = bcy;
+    P.w[7][o] = bcz;
+}
+
+// sweep-frame state of a padded cell for axis D
+template <int D>
+__device__ __forceinline__ W7 load_w7(const Prims &P, idx_t o)
+{
+    constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
+    return W7{P.w[0][o], P.w[1 + D][o], P.w[1 + t1][o], P.w[1 + t2][o],
+              P.w[4][o], P.w[5 + t1][o], P.w[5 + t2][o]};
+}
+
+// ---------------------------------------------------------------------------
+// interface states + HLLD on every face of axis D (Steps 2-3 and 6-7)
+// ---------------------------------------------------------------------------
+template <int D, int RECON>
+__global__ void __launch_bounds__(kBlock) k_flux(Geom g, StateP s, Prims P, Flux F,
+                                                 uint32_t *status)
+{
+    const idx_t X = flux_dim(g.n, D, 0), Y = flux_dim(g.n, D, 1), Z = flux_dim(g.n, D, 2);
+    const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= X * Y * Z) return;
+    int x[3];
+    x[0] = (int)(t % X) - (D != 0);
+    const idx_t r = t / X;
+    x[1] = (int)(r % Y) - (D != 1);
+    x[2] = (int)(r / Y) - (D != 2);
+    // cells along D around the face x[D] - 1/2
+    auto cell_at = [&](int off) {
+        int c[3] = {x[0], x[1], x[2]};
+        c[D] += off;
+        return pidx(g, c[0], c[1], c[2]);
+    };
+    W7 wl, wr;
+    uint32_t st = 0;
+    if (RECON == VLCT_RECON_PCM) {
+        wl = load_w7<D>(P, cell_at(-1));
+        wr = load_w7<D>(P, cell_at(0));
+    } else if (RECON == VLCT_RECON_PLMC) {
+        const idx_t cm2 = cell_at(-2), cm1 = cell_at(-1), c0 = cell_at(0), cp1 = cell_at(1);
+        const W7 a = load_w7<D>(P, cm2), b = load_w7<D>(P, cm1), c = load_w7<D>(P, c0),
+                 e = load_w7<D>(P, cp1);
+        W7 dummy;
+        plmc(a, b, c, P.w[5 + D][cm1], g.gamma, dummy, wl);
+        plmc(b, c, e, P.w[5 + D][c0], g.gamma, wr, dummy);
+        st |= floor_state(wl);
+        st |= floor_state(wr);
+    } else {
+        const idx_t cm3 = cell_at(-3), cm2 = cell_at(-2), cm1 = cell_at(-1), c0 = cell_at(0),
+                    cp1 = cell_at(1), cp2 = cell_at(2);
+        const W7 a = load_w7<D>(P, cm3), b = load_w7<D>(P, cm2), c = load_w7<D>(P, cm1),
+                 e = load_w7<D>(P, c0), h = load_w7<D>(P, cp1), q = load_w7<D>(P, cp2);
+        W7 dummy;
+        ppmc(a, b, c, e, h, P.w[5 + D][cm1], g.gamma, dummy, wl);
+        ppmc(b, c, e, h, q, P.w[5 + D][c0], g.gamma, wr, dummy);
+        st |= floor_state(wl);
+        st |= floor_state(wr);
+    }
+    // stored normal field of this face (transverse indices mapped like cells)
+    int m[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+        m[e] = e == D ? map_face(x[e], g.n[e], g.bc[e]) : map_cell(x[e], g.n[e], g.bc[e]);
+    const double bn = s.b[D][face_store(g, D, m[0], m[1], m[2])];
+    double f[7], upw;
+    hlld(wl, wr, bn, g.gamma, g.gm1i, f, upw);
+    if (st && status) atomicOr(status, st);
+#pragma unroll
+    for (int c = 0; c < 7; ++c) F.f[D][c][t] = f[c];
+    F.f[D][7][t] = upw;
+}
+
+// ---------------------------------------------------------------------------
+// corrector fluxes without duplicated reconstruction: every cell is
+// reconstructed once per axis and its two interface states feed the faces on
+// either side.
+//
+// x axis: a block of 256 threads reconstructs 256 consecutive cells of one
+// row; the high-face states go through LDS to the right neighbour, which
+// solves the Riemann problem of the face between them (255 faces per block).
+// ---------------------------------------------------------------------------
+constexpr int kRowFaces = kBlock - 1;
+
+template <int RECON>
+__device__ __forceinline__ void recon_cell(const Prims &P, const Geom &g, int D, const int c[3],
+                                           W7 &fm, W7 &fp)
+{
+    (void)g;
+    auto at = [&](int off) {
+        int q[3] = {c[0], c[1], c[2]};
+        q[D] += off;
+        return pidx(g, q[0], q[1], q[2]);
+    };
+    const idx_t c0 = at(0);
+    const double bn = P.w[5 + D][c0];
+    if (D == 0) {
+        if (RECON == VLCT_RECON_PLMC)
+            plmc(load_w7<0>(P, at(-1)), load_w7<0>(P, c0), load_w7<0>(P, at(1)), bn, g.gamma, fm, fp);
+        else
+            ppmc(load_w7<0>(P, at(-2)), load_w7<0>(P, at(-1)), load_w7<0>(P, c0),
+                 load_w7<0>(P, at(1)), load_w7<0>(P, at(2)), bn, g.gamma, fm, fp);
+    }
+}
+
+template <int RECON>
+__global__ void __launch_bounds__(kBlock) k_flux_recon_x(Geom g, StateP s, Prims P, Flux F,
+                                                          uint32_t *status)
+{
+    __shared__ double lds[7][kBlock];
+    const int nx = g.n[0];
+    const int nseg = (nx + 1 + kRowFaces - 1) / kRowFaces;
+    const idx_t row = blockIdx.x / nseg;
+    const int seg = (int)(blockIdx.x % nseg);
+    const int Y = g.n[1] + 2;
+    const int j = (int)(row % Y) - 1;
+    const int k = (int)(row / Y) - 1;
+    const int t = threadIdx.x;
+    const int f0 = seg * kRowFaces;
+    const int c = f0 - 1 + t;                 // cell reconstructed by this thread
+    const bool have = c <= nx;
+    W7 fm{}, fp{};
+    uint32_t st = 0;
+    if (have) {
+        const int cc[3] = {c, j, k};
+        recon_cell<RECON>(P, g, 0, cc, fm, fp);
+        st |= floor_state(fm);
+        st |= floor_state(fp);
+    }
+    lds[0][t] = fp.d; lds[1][t] = fp.u; lds[2][t] = fp.v; lds[3][t] = fp.w;
+    lds[4][t] = fp.p; lds[5][t] = fp.by; lds[6][t] = fp.bz;
+    __syncthreads();
+    if (t >= 1 && have) {
+        const W7 wl{lds[0][t - 1], lds[1][t - 1], lds[2][t - 1], lds[3][t - 1],
+                    lds[4][t - 1], lds[5][t - 1], lds[6][t - 1]};
+        const int mj = map_cell(j, g.n[1], g.bc[1]), mk = map_cell(k, g.n[2], g.bc[2]);
+        const double bn = s.b[0][face_store(g, 0, map_face(c, nx, g.bc[0]), mj, mk)];
+        double f[7], upw;
+        hlld(wl, fm, bn, g.gamma, g.gm1i, f, upw);
+        const idx_t o = fidx(g, 0, c, j, k);
+#pragma unroll
+        for (int q = 0; q < 7; ++q) F.f[0][q][o] = f[q];
+        F.f[0][7][o] = upw;
+    }
+    if (st && status) atomicOr(status, st);
+}
+
+// y and z axes: threads along x (coalesced), each thread marches along the
+// axis through a segment of kMarch faces, keeping the stencil and the previous
+// cell's high-face state in registers (one extra reconstruction per segment).
+constexpr int kMarch = 32;
+constexpr int kMarchX = 64;                 // threads along x per block
+constexpr int kMarchT = kBlock / kMarchX;   // threads along the other transverse axis
+
+template <int D, int RECON>
+__global__ void __launch_bounds__(kBlock) k_flux_recon_march(Geom g, StateP s, Prims P, Flux F,
+                                                              uint32_t *status)
+{
+    constexpr int T = D == 1 ? 2 : 1;         // the transverse axis other than x
+    constexpr int R = RECON == VLCT_RECON_PLMC ? 1 : 2;
+    const int nD = g.n[D];
+    const int nxb = (g.n[0] + 2 + kMarchX - 1) / kMarchX;
+    const int ntb = (g.n[T] + 2 + kMarchT - 1) / kMarchT;
+    const int nseg = (nD + 1 + kMarch - 1) / kMarch;
+    idx_t b = blockIdx.x;
+    const int bx = (int)(b % nxb);
+    b /= nxb;
+    const int bt = (int)(b % ntb);
+    const int seg = (int)(b / ntb);
+    const int i = bx * kMarchX + (threadIdx.x % kMarchX) - 1;
+    const int it = bt * kMarchT + (threadIdx.x / kMarchX) - 1;
+    if (i > g.n[0] || it > g.n[T]) return;
+    const int s0 = seg * kMarch;
+    const int s1 = min(s0 + kMarch, nD + 1);  // faces [s0, s1)
+    int x[3];
+    x[0] = i;
+    x[T] = it;
+    auto pid = [&](int along) {
+        int q[3] = {x[0], x[1], x[2]};
+        q[D] = along;
+        return pidx(g, q[0], q[1], q[2]);
+    };
+    // stencil window of cells c-R .. c+R for c = s0 - 1
+    W7 win[2 * R + 1];
+    double bnc[2 * R + 1];
+#pragma unroll
+    for (int q = 0; q < 2 * R + 1; ++q) {
+        const idx_t o = pid(s0 - 1 - R + q);
+        win[q] = load_w7<D>(P, o);
+        bnc[q] = P.w[5 + D][o];
+    }
+    uint32_t st = 0;
+    W7 prev{};
+    const int mt = map_cell(it, g.n[T], g.bc[T]);
+    const int mi = map_cell(i, g.n[0], g.bc[0]);
+    for (int c = s0 - 1; c < s1; ++c) {
+        W7 fm, fp;
+        if (RECON == VLCT_RECON_PLMC)
+            plmc(win[0], win[1], win[2], bnc[1], g.gamma, fm, fp);
+        else
+            ppmc(win[0], win[1], win[2], win[3], win[4], bnc[2], g.gamma, fm, fp);
+        st |= floor_state(fm);
+        st |= floor_state(fp);
+        if (c >= s0) {
+            int m[3];
+            m[0] = mi;
+            m[T] = mt;
+            m[D] = map_face(c, nD, g.bc[D]);
+            const double bn = s.b[D][face_store(g, D, m[0], m[1], m[2])];
+            double f[7], upw;
+            hlld(prev, fm, bn, g.gamma, g.gm1i, f, upw);
+            int q[3] = {x[0], x[1], x[2]};
+            q[D] = c;
+            const idx_t o = fidx(g, D, q[0], q[1], q[2]);
+#pragma unroll
+            for (int v = 0; v < 7; ++v) F.f[D][v][o] = f[v];
+            F.f[D][7][o] = upw;
+        }
+        prev = fp;
+        if (c + 1 < s1) {
+#pragma unroll
+            for (int q = 0; q < 2 * R; ++q) {
+                win[q] = win[q + 1];
+                bnc[q] = bnc[q + 1];
+            }
+            const idx_t o = pid(c + 1 + R);
+            win[2 * R] = load_w7<D>(P, o);
+            bnc[2 * R] = P.w[5 + D][o];
+        }
+    }
+    if (st && status) atomicOr(status, st);
+}
+
+// ---------------------------------------------------------------------------
+// CT edge EMFs (Step 4 / Step 8; Eqs. emf-edge, emf-upwind-slope, emf-slope)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double ref_emf(const Prims &P, int a, idx_t o)
+{
+    const double vx = P.w[1][o], vy = P.w[2][o], vz = P.w[3][o];
+    const double bx = P.w[5][o], by = P.w[6][o], bz = P.w[7][o];
+    if (a == 0) return -(vy * bz - vz * by);
+    if (a == 1) return -(vz * bx - vx * bz);
+    return -(vx * by - vy * bx);
+}
+
+__device__ __forceinline__ double upwind(double s, double lo, double hi)
+{
+    return s > 0.0 ? lo : (s < 0.0 ? hi : 0.5 * (lo + hi));
+}
+
+template <int A>
+__device__ __forceinline__ double edge_emf(const Geom &g, const Prims &P, const Flux &F, int i,
+                                           int j, int k)
+{
+    constexpr int B = (A + 1) % 3, C = (A + 2) % 3;
+    int x0[3] = {i, j, k};
+    int xb[3] = {i, j, k};
+    xb[B] -= 1;
+    int xc[3] = {i, j, k};
+    xc[C] -= 1;
+    int xbc[3] = {i, j, k};
+    xbc[B] -= 1;
+    xbc[C] -= 1;
+    const idx_t fb_c = fidx(g, B, x0[0], x0[1], x0[2]);
+    const idx_t fb_cm = fidx(g, B, xc[0], xc[1], xc[2]);
+    const idx_t fc_b = fidx(g, C, x0[0], x0[1], x0[2]);
+    const idx_t fc_bm = fidx(g, C, xb[0], xb[1], xb[2]);
+    // B-face EMF component A = -F_B[B_t1]; C-face EMF component A = +F_C[B_t2]
+    const double eb_c = -F.f[B][5][fb_c], eb_cm = -F.f[B][5][fb_cm];
+    const double ec_b = F.f[C][6][fc_b], ec_bm = F.f[C][6][fc_bm];
+    const double r00 = ref_emf(P, A, pidx(g, x0[0], x0[1], x0[2]));
+    const double r10 = ref_emf(P, A, pidx(g, xb[0], xb[1], xb[2]));
+    const double r01 = ref_emf(P, A, pidx(g, xc[0], xc[1], xc[2]));
+    const double r11 = ref_emf(P, A, pidx(g, xbc[0], xbc[1], xbc[2]));
+    const double sb_c = F.f[B][7][fb_c], sb_cm = F.f[B][7][fb_cm];
+    const double sc_b = F.f[C][7][fc_b], sc_bm = F.f[C][7][fc_bm];
+    const double avg = 0.25 * (eb_c + eb_cm + ec_b + ec_bm);
+    const double t1 = upwind(sb_c, ec_bm - r10, ec_b - r00);
+    const double t2 = upwind(sb_cm, ec_bm - r11, ec_b - r01);
+    const double t3 = upwind(sc_b, eb_cm - r01, eb_c - r00);
+    const double t4 = upwind(sc_bm, eb_cm - r11, eb_c - r10);
+    return avg + 0.25 * (t1 + t2 + t3 + t4);
+}
+
+__global__ void __launch_bounds__(kBlock) k_edges(Geom g, Prims P, Flux F, Edges E)
+{
+    const idx_t X = g.n[0] + 1, Y = g.n[1] + 1, Z = g.n[2] + 1;
+    const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= X * Y * Z) return;
+    const int i = (int)(t % X);
+    const idx_t r = t / X;
+    const int j = (int)(r % Y);
+    const int k = (int)(r / Y);
+    if (i < g.n[0]) E.e[0][eidx(g, 0, i, j, k)] = edge_emf<0>(g, P, F, i, j, k);
+    if (j < g.n[1]) E.e[1][eidx(g, 1, i, j, k)] = edge_emf<1>(g, P, F, i, j, k);
+    if (k < g.n[2]) E.e[2][eidx(g, 2, i, j, k)] = edge_emf<2>(g, P, F, i, j, k);
+}
+
+// ---------------------------------------------------------------------------
+// conservative cell update and CT face update (Steps 5 and 9)
+// ---------------------------------------------------------------------------
+template <bool FULL>
+__global__ void __launch_bounds__(kBlock) k_update(Geom g, StateP base, StateW out, Flux F,
+                                                   Edges E, const double *dt_dev, uint32_t *status)
+{
+    const idx_t X = g.n[0] + 1, Y = g.n[1] + 1, Z = g.n[2] + 1;
+    const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= X * Y * Z) return;
+    const int i = (int)(t % X);
+    const idx_t r = t / X;
+    const int j = (int)(r % Y);
+    const int k = (int)(r / Y);
+    const double dt = FULL ? dt_dev[0] : 0.5 * dt_dev[0];
+    const double cx = dt / g.dl[0], cy = dt / g.dl[1], cz = dt / g.dl[2];
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    bool bad = false;
+    if (i < nx && j < ny && k < nz) {
+        const idx_t c = cell_store(g, i, j, k);
+        const idx_t fx0 = fidx(g, 0, i, j, k), fx1 = fidx(g, 0, i + 1, j, k);
+        const idx_t fy0 = fidx(g, 1, i, j, k), fy1 = fidx(g, 1, i, j + 1, k);
+        const idx_t fz0 = fidx(g, 2, i, j, k), fz1 = fidx(g, 2, i, j, k + 1);
+        // lab components of the sweep-frame fluxes: x (x,y,z), y (y,z,x), z (z,x,y)
+        const double dxr = F.f[0][0][fx1] - F.f[0][0][fx0];
+        const double dyr = F.f[1][0][fy1] - F.f[1][0][fy0];
+        const double dzr = F.f[2][0][fz1] - F.f[2][0][fz0];
+        const double dxe = F.f[0][4][fx1] - F.f[0][4][fx0];
+        const double dye = F.f[1][4][fy1] - F.f[1][4][fy0];
+        const double dze = F.f[2][4][fz1] - F.f[2][4][fz0];
+        const double dxmx = F.f[0][1][fx1] - F.f[0][1][fx0];
+        const double dxmy = F.f[0][2][fx1] - F.f[0][2][fx0];
+        const double dxmz = F.f[0][3][fx1] - F.f[0][3][fx0];
+        const double dymy = F.f[1][1][fy1] - F.f[1][1][fy0];
+        const double dymz = F.f[1][2][fy1] - F.f[1][2][fy0];
+        const double dymx = F.f[1][3][fy1] - F.f[1][3][fy0];
+        const double dzmz = F.f[2][1][fz1] - F.f[2][1][fz0];
+        const double dzmx = F.f[2][2][fz1] - F.f[2][2][fz0];
+        const double dzmy = F.f[2][3][fz1] - F.f[2][3][fz0];
+        const double u0 = base.u[0][c] - cx * dxr - cy * dyr - cz * dzr;
+        const double u1 = base.u[1][c] - cx * dxmx - cy * dymx - cz * dzmx;
+        const double u2 = base.u[2][c] - cx * dxmy - cy * dymy - cz * dzmy;
+        const double u3 = base.u[3][c] - cx * dxmz - cy * dymz - cz * dzmz;
+        const double u4 = base.u[4][c] - cx * dxe - cy * dye - cz * dze;
+        out.u[0][c] = u0;
+        out.u[1][c] = u1;
+        out.u[2][c] = u2;
+        out.u[3][c] = u3;
+        out.u[4][c] = u4;
+        if (FULL) bad |= !isfinite(u0) || !isfinite(u1) || !isfinite(u2) || !isfinite(u3) ||
+                         !isfinite(u4);
+    }
+    // face x (i-1/2, j, k): B_x -= dt/dy dE_z/dj - dt/dz dE_y/dk
+    if (j < ny && k < nz && !(g.bc[0] == VLCT_BC_PERIODIC && i == nx)) {
+        const double b0 = base.b[0][face_store(g, 0, i, j, k)];
+        const double v = b0 - cy * (E.e[2][eidx(g, 2, i, j + 1, k)] - E.e[2][eidx(g, 2, i, j, k)])
+                         + cz * (E.e[1][eidx(g, 1, i, j, k + 1)] - E.e[1][eidx(g, 1, i, j, k)]);
+        out.b[0][face_store(g, 0, i, j, k)] = v;
+        if (g.bc[0] == VLCT_BC_PERIODIC && i == 0) out.b[0][face_store(g, 0, nx, j, k)] = v;
+        if (FULL) bad |= !isfinite(v);
+    }
+    // face y (i, j-1/2, k): B_y -= dt/dz dE_x/dk - dt/dx dE_z/di
+    if (i < nx && k < nz && !(g.bc[1] == VLCT_BC_PERIODIC && j == ny)) {
+        const double b0 = base.b[1][face_store(g, 1, i, j, k)];
+        const double v = b0 - cz * (E.e[0][eidx(g, 0, i, j, k + 1)] - E.e[0][eidx(g, 0, i, j, k)])
+                         + cx * (E.e[2][eidx(g, 2, i + 1, j, k)] - E.e[2][eidx(g, 2, i, j, k)]);
+        out.b[1][face_store(g, 1, i, j, k)] = v;
+        if (g.bc[1] == VLCT_BC_PERIODIC && j == 0) out.b[1][face_store(g, 1, i, ny, k)] = v;
+        if (FULL) bad |= !isfinite(v);
+    }
+    // face z (i, j, k-1/2): B_z -= dt/dx dE_y/di - dt/dy dE_x/dj
+    if (i < nx && j < ny && !(g.bc[2] == VLCT_BC_PERIODIC && k == nz)) {
+        const double b0 = base.b[2][face_store(g, 2, i, j, k)];
+        const double v = b0 - cx * (E.e[1][eidx(g, 1, i + 1, j, k)] - E.e[1][eidx(g, 1, i, j, k)])
+                         + cy * (E.e[0][eidx(g, 0, i, j + 1, k)] - E.e[0][eidx(g, 0, i, j, k)]);
+        out.b[2][face_store(g, 2, i, j, k)] = v;
+        if (g.bc[2] == VLCT_BC_PERIODIC && k == 0) out.b[2][face_store(g, 2, i, j, nz)] = v;
+        if (FULL) bad |= !isfinite(v);
+    }
+    if (FULL && bad && status) atomicOr(status, kStatusNonfinite);
+}
+
+// ---------------------------------------------------------------------------
+// CFL reduction (Step 1, Eq. dt): per-block maxima of max_l (|v_l| + c_f,l)/d_l,
+// then one block reduces the partials and writes dt = cfl / max.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_dt_partial(Geom g, StateP s, double *partial,
+                                                       uint32_t *status)
+{
+    __shared__ double red[kBlock / 64];
+    const idx_t N = (idx_t)g.n[0] * g.n[1] * g.n[2];
+    const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double m = 0.0;
+    if (t < N) {
+        const int i = (int)(t % g.n[0]);
+        const idx_t r = t / g.n[0];
+        const int j = (int)(r % g.n[1]);
+        const int k = (int)(r / g.n[1]);
+        // high faces through the face map: a periodic duplicate face is not read
+        const int ip = map_face(i + 1, g.n[0], g.bc[0]);
+        const int jp = map_face(j + 1, g.n[1], g.bc[1]);
+        const int kp = map_face(k + 1, g.n[2], g.bc[2]);
+        const double b[3] = {
+            0.5 * (s.b[0][face_store(g, 0, i, j, k)] + s.b[0][face_store(g, 0, ip, j, k)]),
+            0.5 * (s.b[1][face_store(g, 1, i, j, k)] + s.b[1][face_store(g, 1, i, jp, k)]),
+            0.5 * (s.b[2][face_store(g, 2, i, j, k)] + s.b[2][face_store(g, 2, i, j, kp)])};
+        uint32_t st = 0;
+        double d = s.u[0][t];
+        if (!(d >= kFloorRho)) { d = kFloorRho; st |= kStatusDensityFloor; }
+        const double id = 1.0 / d;
+        const double v[3] = {s.u[1][t] * id, s.u[2][t] * id, s.u[3][t] * id};
+        const double ke = 0.5 * d * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        const double me = 0.5 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+        double p = (g.gamma - 1.0) * (s.u[4][t] - ke - me);
+        if (!(p >= kFloorP)) { p = kFloorP; st |= kStatusPressureFloor; }
+        if (st && status) atomicOr(status, st);
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const double cf = fast_speed(d, p, b[l], b[(l + 1) % 3], b[(l + 2) % 3], g.gamma);
+            m = fmax(m, (fabs(v[l]) + cf) / g.dl[l]);
+        }
+    }
+    m = wave_max(m);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) red[wv] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = red[0];
+        for (int q = 1; q < kBlock / 64; ++q) b = fmax(b, red[q]);
+        partial[blockIdx.x] = b;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_dt_final(const double *partial, int n, double cfl,
+                                                   double *dt_out)
+{
+    __shared__ double red[1024 / 64];
+    double m = 0.0;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) m = fmax(m, partial[q]);
+    m = wave_max(m);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) red[wv] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = red[0];
+        for (int q = 1; q < (int)(blockDim.x / 64); ++q) b = fmax(b, red[q]);
+        dt_out[0] = cfl / b;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side: validation, workspace carving, launches
+// ---------------------------------------------------------------------------
+static bool grid_ok(const vlct_grid *g)
+{
+    if (!g) return false;
+    const int n[3] = {g->nx, g->ny, g->nz};
+    for (int d = 0; d < 3; ++d) {
+        if (n[d] < 1 || n[d] > kMaxN) return false;
+        if (g->bc[d] != VLCT_BC_PERIODIC && g->bc[d] != VLCT_BC_OUTFLOW) return false;
+    }
+    if (!(g->dx > 0.0) || !(g->dy > 0.0) || !(g->dz > 0.0)) return false;
+    if (!(g->gamma > 1.0) || !(g->cfl > 0.0 && g->cfl <= 0.5)) return false;
+    if (g->recon != VLCT_RECON_PCM && g->recon != VLCT_RECON_PLMC && g->recon != VLCT_RECON_PPMC)
+        return false;
+    return true;
+}
+
+static Geom make_geom(const vlct_grid *vg)
+{
+    Geom g;
+    g.n[0] = vg->nx;
+    g.n[1] = vg->ny;
+    g.n[2] = vg->nz;
+    for (int d = 0; d < 3; ++d) {
+        g.bc[d] = vg->bc[d];
+        g.p[d] = g.n[d] + 2 * kGhost;
+    }
+    g.dl[0] = vg->dx;
+    g.dl[1] = vg->dy;
+    g.dl[2] = vg->dz;
+    g.gamma = vg->gamma;
+    g.gm1i = 1.0 / (vg->gamma - 1.0);
+    g.cfl = vg->cfl;
+    return g;
+}
+
+static size_t field_len(const int n[3], int f)
+{
+    size_t nx = n[0], ny = n[1], nz = n[2];
+    if (f < 5) return nx * ny * nz;
+    if (f == 5) return (nx + 1) * ny * nz;
+    if (f == 6) return nx * (ny + 1) * nz;
+    return nx * ny * (nz + 1);
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t half[8], prims, flux[3], edges[3], partial, total;
+    size_t prims_len, flux_len[3], edge_len[3], npartial;
+};
+
+static Layout layout(const Geom &g)
+{
+    Layout L;
+    size_t off = 0;
+    for (int f = 0; f < 8; ++f) {
+        L.half[f] = off;
+        off += align_up(field_len(g.n, f) * sizeof(double));
+    }
+    L.prims_len = (size_t)g.p[0] * g.p[1] * g.p[2];
+    L.prims = off;
+    off += 8 * align_up(L.prims_len * sizeof(double));
+    for (int d = 0; d < 3; ++d) {
+        L.flux_len[d] = (size_t)flux_dim(g.n, d, 0) * flux_dim(g.n, d, 1) * flux_dim(g.n, d, 2);
+        L.flux[d] = off;
+        off += 8 * align_up(L.flux_len[d] * sizeof(double));
+    }
+    for (int a = 0; a < 3; ++a) {
+        L.edge_len[a] = (size_t)edge_dim(g.n, a, 0) * edge_dim(g.n, a, 1) * edge_dim(g.n, a, 2);
+        L.edges[a] = off;
+        off += align_up(L.edge_len[a] * sizeof(double));
+    }
+    const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+    L.npartial = (N + kBlock - 1) / kBlock;
+    L.partial = off;
+    off += align_up(L.npartial * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+static unsigned nblocks(size_t work) { return (unsigned)((work + kBlock - 1) / kBlock); }
+
+// launch observer (diagnostics, see vlct_set_launch_observer)
+static vlct_launch_observer g_observer = nullptr;
+static void *g_observer_user = nullptr;
+
+struct Observe {
+    int kernel;
+    hipStream_t s;
+    Observe(int k, hipStream_t st) : kernel(k), s(st)
+    {
+        if (g_observer) g_observer(g_observer_user, kernel, 0, static_cast<void *>(s));
+    }
+    ~Observe()
+    {
+        if (g_observer) g_observer(g_observer_user, kernel, 1, static_cast<void *>(s));
+    }
+};
+
+struct Bound {
+    Prims P;
+    Flux F;
+    Edges E;
+    StateW half;
+    double *partial;
+};
+
+static Bound bind(const Layout &L, void *ws)
+{
+    char *b = static_cast<char *>(ws);
+    Bound B;
+    for (int f = 0; f < 8; ++f) {
+        double *p = reinterpret_cast<double *>(b + L.half[f]);
+        if (f < 5) B.half.u[f] = p; else B.half.b[f - 5] = p;
+    }
+    for (int f = 0; f < 8; ++f)
+        B.P.w[f] = reinterpret_cast<double *>(b + L.prims + f * align_up(L.prims_len * sizeof(double)));
+    for (int d = 0; d < 3; ++d)
+        for (int c = 0; c < 8; ++c)
+            B.F.f[d][c] = reinterpret_cast<double *>(
+                b + L.flux[d] + c * align_up(L.flux_len[d] * sizeof(double)));
+    for (int a = 0; a < 3; ++a) B.E.e[a] = reinterpret_cast<double *>(b + L.edges[a]);
+    B.partial = reinterpret_cast<double *>(b + L.partial);
+    return B;
+}
+
+static bool state_ok(const vlct_state *s)
+{
+    if (!s) return false;
+    const double *p[8] = {s->rho, s->mx, s->my, s->mz, s->E, s->bx, s->by, s->bz};
+    for (int f = 0; f < 8; ++f)
+        if (!p[f]) return false;
+    return true;
+}
+
+static StateP as_const(const vlct_state *s)
+{
+    StateP p;
+    p.u[0] = s->rho; p.u[1] = s->mx; p.u[2] = s->my; p.u[3] = s->mz; p.u[4] = s->E;
+    p.b[0] = s->bx; p.b[1] = s->by; p.b[2] = s->bz;
+    return p;
+}
+static StateP as_const(const StateW &s)
+{
+    StateP p;
+    for (int f = 0; f < 5; ++f) p.u[f] = s.u[f];
+    for (int d = 0; d < 3; ++d) p.b[d] = s.b[d];
+    return p;
+}
+static StateW as_mut(const vlct_state *s)
+{
+    StateW p;
+    p.u[0] = s->rho; p.u[1] = s->mx; p.u[2] = s->my; p.u[3] = s->mz; p.u[4] = s->E;
+    p.b[0] = s->bx; p.b[1] = s->by; p.b[2] = s->bz;
+    return p;
+}
+
+static int launch_stage_fluxes(const Geom &g, const StateP &st, const Bound &B, int recon,
+                               uint32_t *status, hipStream_t s)
+{
+    const size_t np = (size_t)g.p[0] * g.p[1] * g.p[2];
+    {
+        Observe o(VLCT_KERNEL_PRIMS, s);
+        k_prims<<<nblocks(np), kBlock, 0, s>>>(g, st, B.P, status);
+    }
+    size_t nf[3];
+    for (int d = 0; d < 3; ++d)
+        nf[d] = (size_t)flux_dim(g.n, d, 0) * flux_dim(g.n, d, 1) * flux_dim(g.n, d, 2);
+    const int kid = recon == VLCT_RECON_PCM ? VLCT_KERNEL_FLUX_PCM : VLCT_KERNEL_FLUX_RECON;
+#define VLCT_FLUX(D, R)                                                            \
+    {                                                                              \
+        Observe o(kid, s);                                                         \
+        k_flux<D, R><<<nblocks(nf[D]), kBlock, 0, s>>>(g, st, B.P, B.F, status);   \
+    }
+    if (recon == VLCT_RECON_PCM) {
+        VLCT_FLUX(0, VLCT_RECON_PCM) VLCT_FLUX(1, VLCT_RECON_PCM) VLCT_FLUX(2, VLCT_RECON_PCM)
+    } else {
+        // one reconstruction per cell and axis
+        const size_t nseg_x = (g.n[0] + 1 + kRowFaces - 1) / kRowFaces;
+        const size_t rows_x = (size_t)(g.n[1] + 2) * (g.n[2] + 2);
+        auto march_blocks = [&](int D) {
+            const int T = D == 1 ? 2 : 1;
+            return (size_t)((g.n[0] + 2 + kMarchX - 1) / kMarchX) *
+                   ((g.n[T] + 2 + kMarchT - 1) / kMarchT) * ((g.n[D] + 1 + kMarch - 1) / kMarch);
+        };
+        if (recon == VLCT_RECON_PLMC) {
+            { Observe o(kid, s); k_flux_recon_x<VLCT_RECON_PLMC><<<(unsigned)(nseg_x * rows_x), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
+            { Observe o(kid, s); k_flux_recon_march<1, VLCT_RECON_PLMC><<<(unsigned)march_blocks(1), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
+            { Observe o(kid, s); k_flux_recon_march<2, VLCT_RECON_PLMC><<<(unsigned)march_blocks(2), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
+        } else {
+            { Observe o(kid, s); k_flux_recon_x<VLCT_RECON_PPMC><<<(unsigned)(nseg_x * rows_x), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
+            { Observe o(kid, s); k_flux_recon_march<1, VLCT_RECON_PPMC><<<(unsigned)march_blocks(1), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
+            { Observe o(kid, s); k_flux_recon_march<2, VLCT_RECON_PPMC><<<(unsigned)march_blocks(2), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
+        }
+    }
+#undef VLCT_FLUX
+    const size_t ne = (size_t)(g.n[0] + 1) * (g.n[1] + 1) * (g.n[2] + 1);
+    {
+        Observe o(VLCT_KERNEL_EDGES, s);
+        k_edges<<<nblocks(ne), kBlock, 0, s>>>(g, B.P, B.F, B.E);
+    }
+    return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
+}
+
+static int launch_dt(const Geom &g, const StateP &st, const Bound &B, const Layout &L,
+                     double *dt_out, uint32_t *status, hipStream_t s)
+{
+    const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+    Observe o(VLCT_KERNEL_DT, s);
+    k_dt_partial<<<nblocks(N), kBlock, 0, s>>>(g, st, B.partial, status);
+    k_dt_final<<<1, 1024, 0, s>>>(B.partial, (int)L.npartial, g.cfl, dt_out);
+    return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
+}
+
+}  // namespace vlct
+
+using namespace vlct;
+
+extern "C" {
+
+size_t vlct_workspace_bytes(const vlct_grid *g)
+{
+    if (!grid_ok(g)) return 0;
+    return layout(make_geom(g)).total;
+}
+
+int vlct_cfl_dt(const vlct_grid *vg, const vlct_state *s, double *dt_dev, void *ws,
+                size_t ws_bytes, void *stream)
+{
+    if (!grid_ok(vg) || !state_ok(s) || !dt_dev) return VLCT_EINVAL;
+    const Geom g = make_geom(vg);
+    const Layout L = layout(g);
+    if (!ws || ws_bytes < L.total) return VLCT_EWORKSPACE;
+    const Bound B = bind(L, ws);
+    return launch_dt(g, as_const(s), B, L, dt_dev, nullptr, static_cast<hipStream_t>(stream));
+}
+
+int vlct_step(const vlct_grid *vg, const vlct_state *in, const vlct_state *out,
+              const double *dt_dev, double *next_dt_dev, uint32_t *status_dev, void *ws,
+              size_t ws_bytes, void *stream)
+{
+    if (!grid_ok(vg) || !state_ok(in) || !state_ok(out) || !dt_dev) return VLCT_EINVAL;
+    {
+        // out must equal in or be disjoint from it field by field
+        const double *pi[8] = {in->rho, in->mx, in->my, in->mz, in->E, in->bx, in->by, in->bz};
+        const double *po[8] = {out->rho, out->mx, out->my, out->mz, out->E, out->bx, out->by, out->bz};
+        bool all_same = true;
+        for (int f = 0; f < 8; ++f) all_same &= (pi[f] == po[f]);
+        if (!all_same)
+            for (int f = 0; f < 8; ++f)
+                for (int h = 0; h < 8; ++h)
+                    if (po[f] == pi[h]) return VLCT_EINVAL;
+    }
+    const Geom g = make_geom(vg);
+    const Layout L = layout(g);
+    if (!ws || ws_bytes < L.total) return VLCT_EWORKSPACE;
+    const Bound B = bind(L, ws);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const StateP sin = as_const(in);
+    const size_t nu = (size_t)(g.n[0] + 1) * (g.n[1] + 1) * (g.n[2] + 1);
+
+    // predictor (Steps 2-5)
+    int rc = launch_stage_fluxes(g, sin, B, VLCT_RECON_PCM, status_dev, s);
+    if (rc) return rc;
+    {
+        Observe o(VLCT_KERNEL_UPDATE_HALF, s);
+        k_update<false><<<nblocks(nu), kBlock, 0, s>>>(g, sin, B.half, B.F, B.E, dt_dev,
+                                                       status_dev);
+    }
+    // corrector (Steps 6-9)
+    rc = launch_stage_fluxes(g, as_const(B.half), B, vg->recon, status_dev, s);
+    if (rc) return rc;
+    {
+        Observe o(VLCT_KERNEL_UPDATE_FULL, s);
+        k_update<true><<<nblocks(nu), kBlock, 0, s>>>(g, sin, as_mut(out), B.F, B.E, dt_dev,
+                                                      status_dev);
+    }
+    if (hipGetLastError() != hipSuccess) return VLCT_EHIP;
+    if (next_dt_dev) return launch_dt(g, as_const(out), B, L, next_dt_dev, status_dev, s);
+    return VLCT_OK;
+}
+
+const char *vlct_strerror(int code)
+{
+    switch (code) {
+    case VLCT_OK: return "ok";
+    case VLCT_EINVAL: return "invalid argument (grid descriptor, state pointers or dt)";
+    case VLCT_EWORKSPACE: return "workspace missing or smaller than vlct_workspace_bytes()";
+    case VLCT_EHIP: return "HIP launch or runtime error";
+    case VLCT_EUNSUPPORTED: return "unsupported option";
+    default: return "unknown error code";
+    }
+}
+
+int vlct_abi_version(void) { return VLCT_ABI_VERSION; }
+
+int vlct_set_launch_observer(vlct_launch_observer cb, void *user)
+{
+    g_observer = cb;
+    g_observer_user = user;
+    return VLCT_OK;
+}
+
+const char *vlct_kernel_name(int kernel)
+{
+    static const char *names[VLCT_KERNEL_COUNT] = {"prims", "flux_pcm_hlld", "flux_recon_hlld",
+                                                   "edges", "update_half", "update_full", "dt"};
+    return kernel >= 0 && kernel < VLCT_KERNEL_COUNT ? names[kernel] : "?";
+}
+
+}  // extern "C"

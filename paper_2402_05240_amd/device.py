@@ -1,0 +1,92 @@
+"""Device-resident state for the VL+CT library: torch tensors provide HBM and
+the stream, every computation runs in libvlct.so through the C ABI."""
+from __future__ import annotations
+
+from typing import Dict
+
+import numpy as np
+
+from . import vlct
+from .inputs import FIELDS, Grid
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class DeviceState:
+    """Eight FP64 device arrays in the layout of include/vlct.h."""
+
+    def __init__(self, grid: Grid, device: str = "cuda:0"):
+        torch = _torch()
+        self.grid = grid
+        self.t = {f: torch.empty(grid.field_shape(f), dtype=torch.float64, device=device)
+                  for f in FIELDS}
+
+    def ptrs(self):
+        return [self.t[f].data_ptr() for f in FIELDS]
+
+    def c_state(self) -> vlct.vlct_state:
+        return vlct.make_state(self.ptrs())
+
+    def upload(self, s: Dict[str, np.ndarray]) -> "DeviceState":
+        torch = _torch()
+        for f in FIELDS:
+            self.t[f].copy_(torch.from_numpy(np.ascontiguousarray(s[f], dtype=np.float64)))
+        return self
+
+    def download(self) -> Dict[str, np.ndarray]:
+        return {f: self.t[f].cpu().numpy() for f in FIELDS}
+
+
+class Stepper:
+    """Owns the workspace and the device dt words; steps ping-pong between two
+    states (or in place) on torch's current stream."""
+
+    def __init__(self, grid: Grid, device: str = "cuda:0", inplace: bool = False):
+        torch = _torch()
+        self.grid = grid
+        self.device = device
+        self.cg = vlct.make_grid(grid)
+        self.ws_bytes = vlct.vlct_workspace_bytes(self.cg)
+        if self.ws_bytes == 0:
+            raise ValueError("invalid grid descriptor")
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.cur = DeviceState(grid, device)
+        self.nxt = self.cur if inplace else DeviceState(grid, device)
+        self.dt = torch.zeros(1, dtype=torch.float64, device=device)
+        self.next_dt = torch.zeros(1, dtype=torch.float64, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def stream(self) -> int:
+        return _torch().cuda.current_stream().cuda_stream
+
+    def upload(self, s):
+        self.cur.upload(s)
+        return self
+
+    def download(self):
+        return self.cur.download()
+
+    def compute_dt(self) -> None:
+        rc = vlct.vlct_cfl_dt(self.cg, self.cur.c_state(), self.dt.data_ptr(), self.ws.data_ptr(),
+                              self.ws_bytes, self.stream())
+        if rc:
+            raise vlct.VlctError(rc, "vlct_cfl_dt")
+
+    def set_dt(self, dt: float) -> None:
+        self.dt.fill_(float(dt))
+
+    def step(self) -> None:
+        """One step of size self.dt; afterwards self.dt holds the next CFL step."""
+        rc = vlct.vlct_step(self.cg, self.cur.c_state(), self.nxt.c_state(), self.dt.data_ptr(),
+                            self.next_dt.data_ptr(), self.status.data_ptr(), self.ws.data_ptr(),
+                            self.ws_bytes, self.stream())
+        if rc:
+            raise vlct.VlctError(rc, "vlct_step")
+        self.cur, self.nxt = self.nxt, self.cur
+        self.dt, self.next_dt = self.next_dt, self.dt
+
+    def status_bits(self) -> int:
+        return int(self.status.item())

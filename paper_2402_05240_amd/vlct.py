@@ -1,0 +1,155 @@
+"""Python binding of the C ABI in include/vlct.h (argument marshalling only).
+
+Every step of the VL+CT integrator runs in the gfx950 library libvlct.so;
+PyTorch supplies device memory and the stream.  The binding refuses to run if
+the library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvlct.so")
+
+VLCT_OK = 0
+VLCT_EINVAL = 1
+VLCT_EWORKSPACE = 2
+VLCT_EHIP = 3
+VLCT_EUNSUPPORTED = 4
+VLCT_RECON_PCM = 1
+VLCT_RECON_PLMC = 2
+VLCT_RECON_PPMC = 3
+VLCT_BC_PERIODIC = 0
+VLCT_BC_OUTFLOW = 1
+VLCT_STATUS_PRESSURE_FLOOR = 1
+VLCT_STATUS_DENSITY_FLOOR = 2
+VLCT_STATUS_NONFINITE = 4
+
+EXPORTED = ("vlct_workspace_bytes", "vlct_cfl_dt", "vlct_step", "vlct_strerror",
+            "vlct_abi_version", "vlct_set_launch_observer", "vlct_kernel_name")
+
+VLCT_KERNEL_PRIMS = 0
+VLCT_KERNEL_FLUX_PCM = 1
+VLCT_KERNEL_FLUX_RECON = 2
+VLCT_KERNEL_EDGES = 3
+VLCT_KERNEL_UPDATE_HALF = 4
+VLCT_KERNEL_UPDATE_FULL = 5
+VLCT_KERNEL_DT = 6
+VLCT_KERNEL_COUNT = 7
+
+vlct_launch_observer = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_void_p)
+
+
+class vlct_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("recon", ctypes.c_int32), ("bc", ctypes.c_int32 * 3)]
+
+
+class vlct_state(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in ("rho", "mx", "my", "mz", "E", "bx", "by", "bz")]
+
+
+class VlctError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__("%s failed: %s (code %d)" % (where, vlct_strerror(code), code))
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libvlct.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError("libvlct.so not found at %s: build it with "
+                               "`python -m paper_2402_05240_amd.build`" % path)
+        lib = ctypes.CDLL(path)
+        lib.vlct_workspace_bytes.argtypes = [ctypes.POINTER(vlct_grid)]
+        lib.vlct_workspace_bytes.restype = ctypes.c_size_t
+        lib.vlct_cfl_dt.argtypes = [ctypes.POINTER(vlct_grid), ctypes.POINTER(vlct_state),
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                    ctypes.c_void_p]
+        lib.vlct_cfl_dt.restype = ctypes.c_int
+        lib.vlct_step.argtypes = [ctypes.POINTER(vlct_grid), ctypes.POINTER(vlct_state),
+                                  ctypes.POINTER(vlct_state), ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                  ctypes.c_void_p]
+        lib.vlct_step.restype = ctypes.c_int
+        lib.vlct_strerror.argtypes = [ctypes.c_int]
+        lib.vlct_strerror.restype = ctypes.c_char_p
+        lib.vlct_abi_version.argtypes = []
+        lib.vlct_abi_version.restype = ctypes.c_int
+        lib.vlct_set_launch_observer.argtypes = [vlct_launch_observer, ctypes.c_void_p]
+        lib.vlct_set_launch_observer.restype = ctypes.c_int
+        lib.vlct_kernel_name.argtypes = [ctypes.c_int]
+        lib.vlct_kernel_name.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+def make_grid(g) -> vlct_grid:
+    """vlct_grid from any object with nx, ny, nz, dx, dy, dz, gamma, cfl, recon, bc."""
+    cg = vlct_grid()
+    cg.nx, cg.ny, cg.nz = int(g.nx), int(g.ny), int(g.nz)
+    cg.dx, cg.dy, cg.dz = float(g.dx), float(g.dy), float(g.dz)
+    cg.gamma, cg.cfl, cg.recon = float(g.gamma), float(g.cfl), int(g.recon)
+    for d in range(3):
+        cg.bc[d] = int(g.bc[d])
+    return cg
+
+
+def make_state(ptrs) -> vlct_state:
+    """vlct_state from 8 device addresses (rho, mx, my, mz, E, bx, by, bz)."""
+    st = vlct_state()
+    for name, p in zip(("rho", "mx", "my", "mz", "E", "bx", "by", "bz"), ptrs):
+        setattr(st, name, int(p) if p else None)
+    return st
+
+
+def vlct_workspace_bytes(grid: vlct_grid) -> int:
+    return int(load().vlct_workspace_bytes(ctypes.byref(grid)))
+
+
+def vlct_cfl_dt(grid: vlct_grid, state: vlct_state, dt_dev: int, ws: int, ws_bytes: int,
+                stream: int) -> int:
+    return int(load().vlct_cfl_dt(ctypes.byref(grid), ctypes.byref(state), dt_dev, ws,
+                                  ws_bytes, stream))
+
+
+def vlct_step(grid: vlct_grid, state_in: vlct_state, state_out: vlct_state, dt_dev: int,
+              next_dt_dev: int, status_dev: int, ws: int, ws_bytes: int, stream: int) -> int:
+    return int(load().vlct_step(ctypes.byref(grid), ctypes.byref(state_in),
+                                ctypes.byref(state_out), dt_dev, next_dt_dev, status_dev, ws,
+                                ws_bytes, stream))
+
+
+def vlct_strerror(code: int) -> str:
+    return load().vlct_strerror(int(code)).decode()
+
+
+def vlct_abi_version() -> int:
+    return int(load().vlct_abi_version())
+
+
+_observer_keepalive = None
+
+
+def vlct_set_launch_observer(cb) -> int:
+    """Install a Python callable cb(kernel, phase, stream) (or None)."""
+    global _observer_keepalive
+    if cb is None:
+        _observer_keepalive = None
+        return int(load().vlct_set_launch_observer(vlct_launch_observer(), None))
+    wrapped = vlct_launch_observer(lambda user, k, ph, st: cb(k, ph, st or 0))
+    _observer_keepalive = wrapped
+    return int(load().vlct_set_launch_observer(wrapped, None))
+
+
+def vlct_kernel_name(kernel: int) -> str:
+    return load().vlct_kernel_name(int(kernel)).decode()

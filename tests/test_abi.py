@@ -1,0 +1,115 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and
+exports every function include/vlct.h declares, argument validation returns
+the documented codes before anything is launched, and the full-size sampling
+used by the GPU parity tests reproduces the oracle exactly."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2402_05240_amd import inputs as I
+from paper_2402_05240_amd import vlct
+from parity_util import ROOT, WINDOW_HALF, cell_values, window
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "vlct.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vlct_\w+)\s*\(", src)))
+
+
+def _lib():
+    if not os.path.exists(vlct.LIB_PATH):
+        pytest.skip("libvlct.so not built")
+    return vlct.load()
+
+
+def test_library_exports_every_declared_function():
+    lib = _lib()
+    decl = _declared_functions()
+    assert set(decl) == set(vlct.EXPORTED)
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert vlct.vlct_abi_version() == 100
+
+
+def _grid(**kw):
+    base = dict(nx=8, ny=8, nz=8, dx=0.1, dy=0.1, dz=0.1, gamma=5 / 3, cfl=0.4, recon=2, bc=(0, 0, 0))
+    base.update(kw)
+    return vlct.make_grid(I.Grid(**base))
+
+
+@pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-3), dict(nz=5000), dict(dx=0.0), dict(dy=-1.0),
+                                 dict(dz=float("nan")), dict(gamma=1.0), dict(cfl=0.0), dict(cfl=0.6),
+                                 dict(recon=0), dict(recon=4), dict(bc=(0, 2, 0))])
+def test_invalid_grid_rejected(bad):
+    _lib()
+    g = _grid(**bad)
+    assert vlct.vlct_workspace_bytes(g) == 0
+    fake = vlct.make_state([16] * 8)
+    rc = vlct.vlct_step(g, fake, fake, 16, 16, 0, 16, 1 << 40, 0)
+    assert rc == vlct.VLCT_EINVAL
+    assert vlct.vlct_cfl_dt(g, fake, 16, 16, 1 << 40, 0) == vlct.VLCT_EINVAL
+
+
+def test_workspace_and_pointer_validation():
+    _lib()
+    g = _grid()
+    need = vlct.vlct_workspace_bytes(g)
+    assert need > 8 * 8 ** 3 * 8
+    fake = vlct.make_state([4096 * (f + 1) for f in range(8)])
+    # missing / short workspace
+    assert vlct.vlct_step(g, fake, fake, 64, 0, 0, 0, need, 0) == vlct.VLCT_EWORKSPACE
+    assert vlct.vlct_step(g, fake, fake, 64, 0, 0, 128, need - 1, 0) == vlct.VLCT_EWORKSPACE
+    assert vlct.vlct_cfl_dt(g, fake, 64, 128, need - 1, 0) == vlct.VLCT_EWORKSPACE
+    # NULL field, NULL dt
+    holey = vlct.make_state([4096 * (f + 1) for f in range(7)] + [0])
+    assert vlct.vlct_step(g, holey, fake, 64, 0, 0, 128, need, 0) == vlct.VLCT_EINVAL
+    assert vlct.vlct_step(g, fake, fake, 0, 0, 0, 128, need, 0) == vlct.VLCT_EINVAL
+    # partial aliasing of out and in
+    other = vlct.make_state([4096 * (f + 1) for f in range(7)] + [10 ** 9])
+    part = vlct.make_state([10 ** 9 + 4096 * f for f in range(7)] + [4096])
+    assert vlct.vlct_step(g, fake, part, 64, 0, 0, 128, need, 0) == vlct.VLCT_EINVAL
+    assert vlct.vlct_step(g, fake, other, 64, 0, 0, 128, need, 0) == vlct.VLCT_EINVAL
+
+
+def test_strerror_covers_codes():
+    _lib()
+    for c in range(5):
+        assert vlct.vlct_strerror(c)
+    assert "unknown" in vlct.vlct_strerror(99)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    saved = vlct._lib
+    try:
+        vlct._lib = None
+        with pytest.raises(RuntimeError):
+            vlct.load(str(tmp_path / "nope.so"))
+    finally:
+        vlct._lib = saved
+
+
+@pytest.mark.parametrize("maker", ["turb_plmc", "turb_ppmc", "blast"])
+def test_window_sampling_reproduces_full_oracle(maker):
+    """A cell of a one-step result depends only on cells within 4 of it, so
+    the oracle run on a window around a sampled cell equals the full run
+    there; the full-size GPU parity tests rely on this."""
+    if maker == "turb_plmc":
+        g, s = I.turbulence((16, 16, 16))
+    elif maker == "turb_ppmc":
+        g, s = I.turbulence((16, 16, 16), recon=3)
+    else:
+        g, s = I.blast((16, 16, 16), b0=1.0)
+    dt = ref.cfl_dt(g, s)
+    full, _, _ = ref.step(g, s, dt, nthreads=2)
+    rng = np.random.default_rng(3)
+    cells = [(0, 15, 7), (15, 0, 0)] + [tuple(int(x) for x in rng.integers(0, 16, 3)) for _ in range(3)]
+    for c in cells:
+        wg, ws, cw = window(g, s, c, 4)
+        wout, _, _ = ref.step(wg, ws, dt, nthreads=1)
+        assert np.array_equal(cell_values(wg, wout, cw), cell_values(g, full, c))
+    assert WINDOW_HALF >= 4

@@ -1,0 +1,245 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle on
+the same seeded inputs and the same dt sequence.
+
+Bar: per-variable relative L1 difference <= 1e-12 (with the scale floors of
+parity_util.scales) after the stated number of steps, plus an element-wise
+bound; uniform states, in-place/out-of-place and repeated runs bit-exact.
+The GPU contracts multiply-adds into FMAs while the oracle rounds every
+operation, so the two differ at rounding level (~1e-16 relative per
+operation); the bounds leave room for that accumulated over 100 steps."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2402_05240_amd import inputs as I
+from parity_util import (FIELDS, WINDOW_HALF, cell_values, gpu_available, max_abs_over_scale,
+                         rel_l1, scales, window)
+
+pytestmark = pytest.mark.gpu
+
+REL_L1 = 1e-12
+
+
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _gpu_run(g, s0, dts, inplace=False):
+    """Run len(dts) GPU steps with the given dt sequence; returns the final
+    state and the device-computed next dt after each step."""
+    from paper_2402_05240_amd.device import Stepper
+    import torch
+    st = Stepper(g, inplace=inplace).upload(s0)
+    nexts = []
+    for dt in dts:
+        st.set_dt(dt)
+        st.step()
+        nexts.append(st.dt)   # after the step self.dt holds the next dt (device)
+    torch.cuda.synchronize()
+    out = st.download()
+    return out, [float(x.item()) for x in nexts], st.status_bits()
+
+
+def _oracle_run(g, s0, nsteps=None, t_end=None, nthreads=0):
+    s = s0
+    dt = ref.cfl_dt(g, s0, nthreads)
+    dts, nexts = [], []
+    t = 0.0
+    status = 0
+    while True:
+        if t_end is not None:
+            if t >= t_end * (1 - 1e-14):
+                break
+            if t + dt > t_end:
+                dt = t_end - t
+        elif len(dts) >= nsteps:
+            break
+        s, nd, stt = ref.step(g, s, dt, nthreads)
+        status |= stt
+        dts.append(dt)
+        nexts.append(nd)
+        t += dt
+        dt = nd
+    return s, dts, nexts, status
+
+
+def _check(g, s0, gpu, orc, rel=REL_L1, elem=1e-10):
+    sc = scales(g, s0)
+    r = rel_l1(gpu, orc, sc)
+    m = max_abs_over_scale(gpu, orc, sc)
+    _say("rel L1 %s" % {f: "%.1e" % r[f] for f in FIELDS})
+    _say("max/scale %s" % {f: "%.1e" % m[f] for f in FIELDS})
+    for f in FIELDS:
+        assert np.all(np.isfinite(gpu[f])), f
+        assert r[f] <= rel, (f, r[f])
+        assert m[f] <= elem, (f, m[f])
+
+
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("recon", [1, 2, 3])
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 0, 1)])
+def test_uniform_state_bit_exact_gpu(recon, bc):
+    _need_gpu()
+    rng = np.random.default_rng(7 + recon)
+    g, s0 = I.uniform((37, 29, 23), rho=1.3, v=tuple(rng.normal(0, 1, 3)), p=0.7,
+                      b=tuple(rng.normal(0, 1, 3)), gamma=1.4, recon=recon, bc=bc,
+                      length=(1.0, 0.9, 0.8))
+    dt = ref.cfl_dt(g, s0)
+    gpu, nexts, status = _gpu_run(g, s0, [dt] * 3)
+    assert status == 0
+    for f in FIELDS:
+        assert np.array_equal(gpu[f], s0[f]), f
+    assert abs(nexts[-1] - dt) <= 1e-15 * dt
+
+
+def test_cfl_dt_matches_oracle():
+    _need_gpu()
+    from paper_2402_05240_amd.device import Stepper
+    import torch
+    for g, s in (I.turbulence((33, 20, 17)), I.blast((21, 19, 26), b0=1.0)):
+        st = Stepper(g).upload(s)
+        st.compute_dt()
+        torch.cuda.synchronize()
+        d_gpu = float(st.dt.item())
+        d_ref = ref.cfl_dt(g, s)
+        assert abs(d_gpu - d_ref) <= 1e-14 * d_ref
+
+
+def test_linear_fast_wave_32_one_period():
+    """32^3 fast magnetosonic wave, PLMC + HLLD, CFL 0.4, one period."""
+    _need_gpu()
+    g, s0, T = I.linear_wave((32, 32, 32), "fast")
+    _say("oracle: 32^3 fast wave, one period")
+    orc, dts, nexts_ref, st_ref = _oracle_run(g, s0, t_end=T)
+    _say("gpu: %d steps" % len(dts))
+    gpu, nexts, status = _gpu_run(g, s0, dts)
+    assert status == 0 and st_ref == 0
+    _check(g, s0, gpu, orc)
+    # the device dt reduction reproduces the oracle's next-dt sequence
+    assert np.allclose(nexts[:-1], nexts_ref[:-1], rtol=1e-13, atol=0)
+    # and the wave-error of the run is the oracle's
+    e_gpu = np.sqrt(sum(np.mean(np.abs(gpu[f] - s0[f])) ** 2 for f in FIELDS))
+    e_ref = np.sqrt(sum(np.mean(np.abs(orc[f] - s0[f])) ** 2 for f in FIELDS))
+    assert abs(e_gpu - e_ref) <= 1e-6 * e_ref
+
+
+@pytest.mark.parametrize("recon,nsteps", [(2, 100), (3, 40), (1, 20)])
+def test_turbulence_multi_step(recon, nsteps):
+    """Decaying turbulence on a ragged grid (not a multiple of the block size)."""
+    _need_gpu()
+    g, s0 = I.turbulence((22, 19, 17), recon=recon)
+    _say("oracle: turbulence recon %d, %d steps" % (recon, nsteps))
+    orc, dts, nexts_ref, st_ref = _oracle_run(g, s0, nsteps=nsteps)
+    _say("gpu")
+    gpu, nexts, status = _gpu_run(g, s0, dts)
+    assert status == st_ref == 0
+    _check(g, s0, gpu, orc, elem=1e-9)
+    assert abs(nexts[-1] - nexts_ref[-1]) <= 1e-12 * nexts_ref[-1]
+
+
+@pytest.mark.parametrize("recon", [2, 3])
+def test_blast_outflow_multi_step(recon):
+    """Magnetised blast wave (beta = 0.2) with outflow boundaries on all faces."""
+    _need_gpu()
+    g, s0 = I.blast((26, 23, 20), b0=1.0, recon=recon)
+    _say("oracle: blast recon %d" % recon)
+    orc, dts, _, st_ref = _oracle_run(g, s0, nsteps=10)
+    gpu, _, status = _gpu_run(g, s0, dts)
+    assert status == st_ref == 0
+    _check(g, s0, gpu, orc, elem=1e-9)
+
+
+def test_single_step_tight():
+    """One step: only rounding separates the two."""
+    _need_gpu()
+    g, s0 = I.turbulence((31, 27, 24))
+    orc, dts, _, _ = _oracle_run(g, s0, nsteps=1)
+    gpu, _, _ = _gpu_run(g, s0, dts)
+    _check(g, s0, gpu, orc, rel=1e-14, elem=1e-13)
+
+
+def test_inplace_equals_out_of_place_and_is_deterministic():
+    _need_gpu()
+    g, s0 = I.turbulence((24, 24, 24))
+    dts = [ref.cfl_dt(g, s0)] * 3
+    a, _, _ = _gpu_run(g, s0, dts)
+    b, _, _ = _gpu_run(g, s0, dts, inplace=True)
+    c, _, _ = _gpu_run(g, s0, dts)
+    for f in FIELDS:
+        assert np.array_equal(a[f], b[f]), f
+        assert np.array_equal(a[f], c[f]), f
+
+
+def test_status_reports_floors():
+    """A cell whose internal energy is negative gets the pressure floor in both
+    implementations, and the GPU reports it."""
+    _need_gpu()
+    g, s0 = I.uniform((12, 10, 9), p=0.5, b=(0.4, 0.2, 0.1), v=(0.2, 0.0, 0.0))
+    s0["E"][4, 5, 6] = 0.0
+    dt = 1e-4
+    gpu, _, status = _gpu_run(g, s0, [dt])
+    orc, _, st_ref = ref.step(g, s0, dt)
+    assert status & 1 and st_ref & 1
+    _check(g, s0, gpu, orc, rel=1e-13, elem=1e-11)
+
+
+def _sampled_full_size(g, s0, ncells, seed):
+    from paper_2402_05240_amd.device import Stepper
+    import torch
+    dt = ref.cfl_dt(g, s0, 0)
+    _say("gpu: one full-size step")
+    st = Stepper(g).upload(s0)
+    st.set_dt(dt)
+    st.step()
+    torch.cuda.synchronize()
+    assert st.status_bits() == 0
+    out = st.download()
+    sc = scales(g, s0)
+    scv = np.array([sc[f] for f in FIELDS])
+    rng = np.random.default_rng(seed)
+    n = (g.nx, g.ny, g.nz)
+    cells = [(0, 0, 0), (n[0] - 1, n[1] - 1, n[2] - 1), (0, n[1] - 1, n[2] // 2)]
+    cells += [tuple(int(rng.integers(0, n[d])) for d in range(3)) for _ in range(ncells)]
+    _say("oracle: %d sampled windows" % len(cells))
+    worst = 0.0
+    for c in cells:
+        wg, ws, cw = window(g, s0, c, WINDOW_HALF)
+        wout, _, _ = ref.step(wg, ws, dt, nthreads=1)
+        diff = np.abs(cell_values(wg, wout, cw) - cell_values(g, out, c)) / scv
+        worst = max(worst, float(diff.max()))
+    _say("worst sampled |gpu - oracle| / scale = %.2e" % worst)
+    assert worst <= 1e-13
+    return out
+
+
+def test_turbulence_256_full_size_sampled():
+    """The benchmark's workload (256^3 turbulence, PLMC) in the launch
+    configuration bench.py times: sampled cells against the oracle, plus the
+    invariants the method holds at any size."""
+    _need_gpu()
+    g, s0 = I.turbulence((256, 256, 256))
+    out = _sampled_full_size(g, s0, 24, 11)
+    # conservation (periodic) and div B at full size
+    vol = g.dx * g.dy * g.dz
+    for f in ("rho", "E"):
+        a, b = out[f].sum() * vol, s0[f].sum() * vol
+        assert abs(a - b) <= 1e-13 * abs(b), f
+    for f in ("mx", "my", "mz"):
+        assert abs(out[f].sum() - s0[f].sum()) <= 1e-13 * np.abs(s0[f]).sum(), f
+    assert ref.divb_norm(g, out) <= 1e-13
+
+
+def test_blast_full_size_sampled():
+    """Outflow + PPMC at a large size (256^3 blast wave, beta = 0.2)."""
+    _need_gpu()
+    g, s0 = I.blast((256, 256, 256), b0=1.0)
+    _sampled_full_size(g, s0, 16, 12)
