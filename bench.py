@@ -21,10 +21,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP64 operations per face of the corrector flux kernel (two
-# reconstructions + one HLLD solve), counted by paper_2402_05240_amd/csrc/flop_count.cpp
+# Algorithmic FP64 operations per face of the corrector flux kernel (one
+# reconstruction -- each cell serves its two faces -- and one HLLD solve), counted by
+# paper_2402_05240_amd/csrc/flop_count.cpp
 # (add/sub/mul/div/sqrt = 1 FLOP each; mean over turbulence-like states).
-FLOPS_PER_FACE = {2: 1026.9, 3: 1601.1, 1: 291.0}
+FLOPS_PER_FACE = {2: 662.0, 3: 1034.0, 1: 291.0}
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
@@ -155,6 +156,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-planes", type=int, default=32)
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="first run one device-to-device copy of this many GiB (a plain copy "
+                         "kernel of known size, to calibrate HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -164,6 +168,17 @@ def main():
     import torch
     from paper_2402_05240_amd import vlct
     from paper_2402_05240_amd.device import Stepper
+
+    if args.copy_calibration_gib > 0:
+        nbytes = int(args.copy_calibration_gib * (1 << 30))
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
+        print("copy calibration: %d bytes read and written" % nbytes, file=sys.stderr)
 
     g, s0 = make_workload(args.workload)
     st = Stepper(g, device="cuda:0").upload(s0)

@@ -55,6 +55,13 @@ def load():
         _lib.vref_edge_emfs.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_DP), ctypes.c_int,
                                         _DP, _DP, _DP, ctypes.c_int]
         _lib.vref_edge_emfs.restype = ctypes.c_int
+        _lib.vref_stage_fluxes.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_DP), ctypes.c_int,
+                                           ctypes.POINTER(_DP), ctypes.POINTER(_DP),
+                                           ctypes.POINTER(_DP), ctypes.c_int]
+        _lib.vref_stage_fluxes.restype = ctypes.c_int
+        _lib.vref_half_step.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_DP),
+                                        ctypes.POINTER(_DP), ctypes.c_double, ctypes.c_int]
+        _lib.vref_half_step.restype = ctypes.c_int
         _lib.vref_divb_norm.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_DP)]
         _lib.vref_divb_norm.restype = ctypes.c_double
     return _lib
@@ -238,3 +245,33 @@ def divb_norm(g, s) -> float:
     inp = (_DP * 8)(*[_ptr(src[f]) for f in FIELDS])
     cg = _grid(g)
     return lib.vref_divb_norm(ctypes.byref(cg), inp)
+
+
+def half_step(g, s, dt, nthreads: int = 0):
+    """Predictor only: the half-step state of a step of size dt."""
+    lib = load()
+    _check_state(g, s)
+    src = {f: np.ascontiguousarray(s[f], dtype=np.float64) for f in FIELDS}
+    dst = {f: np.empty_like(src[f]) for f in FIELDS}
+    cg = _grid(g)
+    rc = lib.vref_half_step(ctypes.byref(cg), (_DP * 8)(*[_ptr(src[f]) for f in FIELDS]),
+                            (_DP * 8)(*[_ptr(dst[f]) for f in FIELDS]), float(dt), int(nthreads))
+    if rc != 0:
+        raise ValueError("vref_half_step failed")
+    return dst
+
+
+def stage_fluxes(g, s, recon: int, nthreads: int = 0):
+    """Face fluxes of one stage: {axis: (8, *face_shape)} with the 7 sweep-frame
+    components and the CT upwind indicator."""
+    lib = load()
+    _check_state(g, s)
+    src = {f: np.ascontiguousarray(s[f], dtype=np.float64) for f in FIELDS}
+    out = {d: np.zeros((8,) + g.field_shape(("bx", "by", "bz")[d])) for d in range(3)}
+    arrs = {d: (_DP * 8)(*[_ptr(out[d][c]) for c in range(8)]) for d in range(3)}
+    cg = _grid(g)
+    rc = lib.vref_stage_fluxes(ctypes.byref(cg), (_DP * 8)(*[_ptr(src[f]) for f in FIELDS]),
+                               int(recon), arrs[0], arrs[1], arrs[2], int(nthreads))
+    if rc != 0:
+        raise ValueError("vref_stage_fluxes failed")
+    return out

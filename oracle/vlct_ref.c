@@ -30,15 +30,19 @@
  *    degenerate star states when |rho(S-u)(S-S_M) - Bn^2| < 1e-8 p_T*;
  *  - characteristic eigenvectors use the Roe-Balsara normalisation with
  *    beta = 1/sqrt(2) when B_perp vanishes and alpha_f = 1 when c_f = c_s;
+ *    field components below 1e-12 sqrt(gP + B^2) count as zero there;
  *  - boundaries: every stage's state is extended by index mapping (wrap on
  *    periodic axes, clamp on outflow axes; face fields clamp their normal
  *    index into [0, n] and their transverse indices into [0, n-1]);
  *  - floors: rho and P derived from a conserved state, and reconstructed
  *    interface states, are floored at 1e-20 (the conserved state is never
  *    modified); each floor sets a status bit;
- *  - PPMC: 4th-order interface values, Colella-Sekora interface and
- *    extremum-preserving limiters in characteristic variables, then
- *    interface primitives clamped between the neighbouring cell values.
+ *  - PPMC: characteristic projection of the stencil differences (rounding-
+ *    level primitive differences, below 1e-12 of the values' magnitude with
+ *    c_f and sqrt(rho) c_f as floors for velocity and field, taken as zero),
+ *    4th-order interface values, Colella-Sekora interface and
+ *    extremum-preserving limiters, then interface primitives clamped between
+ *    the neighbouring cell values.
  */
 #include "vlct_ref.h"
 
@@ -53,10 +57,11 @@
 #define FLOOR_RHO 1.0e-20
 #define FLOOR_P 1.0e-20
 #define HLLD_DEGEN 1.0e-8   /* degenerate-star threshold relative to p_T* */
-#define BPERP_TINY 1.0e-12  /* |B_perp| below this * |B| => beta = 1/sqrt2 */
+#define BPERP_TINY 1.0e-12  /* B_n, B_perp below this * sqrt(gP+B^2): zero / beta = 1/sqrt2 */
 #define CFCS_TINY 1.0e-12   /* c_f^2 - c_s^2 below this * c_f^2 => alpha_f = 1 */
 #define PPM_C 1.25          /* Colella-Sekora curvature-ratio constant */
 #define UPWIND_TINY 1.0e-12 /* |S_M| below this * signal speed counts as zero */
+#define PPM_TIE 1.0e-12     /* PPMC: relative size of a stencil difference taken as zero */
 
 /* ------------------------------------------------------------------------- */
 /* Primitive-variable physics of one state (Sec. 2.1)                         */
@@ -257,39 +262,15 @@ void vref_hlld(const double wl[7], const double wr[7], double bn, double gamma,
 /* normalisation), w = (rho, u, v, w, P, B_t1, B_t2), normal field bn.        */
 /* ------------------------------------------------------------------------- */
 
-static void invert7(const double A[49], double Ainv[49])
-{
-    double M[7][14];
-    for (int r = 0; r < 7; ++r)
-        for (int c = 0; c < 14; ++c)
-            M[r][c] = c < 7 ? A[r * 7 + c] : (c - 7 == r ? 1.0 : 0.0);
-    for (int col = 0; col < 7; ++col) {
-        int piv = col;
-        for (int r = col + 1; r < 7; ++r)
-            if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
-        if (piv != col)
-            for (int c = 0; c < 14; ++c) {
-                double t = M[col][c];
-                M[col][c] = M[piv][c];
-                M[piv][c] = t;
-            }
-        double d = M[col][col];
-        for (int c = 0; c < 14; ++c) M[col][c] /= d;
-        for (int r = 0; r < 7; ++r) {
-            if (r == col) continue;
-            double f = M[r][col];
-            if (f == 0.0) continue;
-            for (int c = 0; c < 14; ++c) M[r][c] -= f * M[col][c];
-        }
-    }
-    for (int r = 0; r < 7; ++r)
-        for (int c = 0; c < 7; ++c) Ainv[r * 7 + c] = M[r][c + 7];
-}
-
 void vref_eigen(const double w[7], double bn, double gamma, double R[49], double L[49],
                 double lam[7])
 {
     double rho = w[0], u = w[1], p = w[4], by = w[5], bz = w[6];
+    /* field components below 1e-12 of the magnetosonic scale sqrt(gP + B^2)
+     * are rounding noise: B_n below it is zero, and a B_perp below it takes
+     * the degenerate-direction convention */
+    double bscale = sqrt(gamma * p + bn * bn + by * by + bz * bz);
+    if (fabs(bn) <= BPERP_TINY * bscale) bn = 0.0;
     double a2 = gamma * p / rho;
     double a = sqrt(a2);
     double cf, cs;
@@ -298,9 +279,8 @@ void vref_eigen(const double w[7], double bn, double gamma, double R[49], double
     double sqr = sqrt(rho);
 
     double bperp = sqrt(by * by + bz * bz);
-    double bmag = sqrt(bn * bn + by * by + bz * bz);
     double bety, betz;
-    if (bperp > BPERP_TINY * bmag) {
+    if (bperp > BPERP_TINY * bscale) {
         bety = by / bperp;
         betz = bz / bperp;
     } else {
@@ -362,7 +342,30 @@ void vref_eigen(const double w[7], double bn, double gamma, double R[49], double
 
     for (int r = 0; r < 7; ++r)
         for (int m = 0; m < 7; ++m) R[r * 7 + m] = col[m][r];
-    invert7(R, L);
+
+    /* Left eigenvectors (rows of L = R^{-1}) in closed form.  The fast/slow
+     * pairs split into a part acting on (rho, P, B along beta) and a part on
+     * (u, v along beta); using c_f^2 alpha_f^2 + c_s^2 alpha_s^2 = a^2 the
+     * inverse has the coefficients below.  Written out (rather than inverted
+     * numerically) so that entries that vanish exactly -- e.g. the coupling
+     * of the Alfven and entropy waves to u -- are exact zeros. */
+    double ia2 = 1.0 / a2;
+    double nf = 0.5 * af * cf * ia2, ns = 0.5 * as * cs * ia2;
+    double qf = 0.5 * s * as * cs * ia2, qs = 0.5 * s * af * cf * ia2;
+    double pf = 0.5 * af * ia2 / rho, ps = 0.5 * as * ia2 / rho;
+    double bf = 0.5 * as / (a * sqr), bs = -0.5 * af / (a * sqr);
+    double sr = 0.5 * s / sqr;
+    const double rows[7][7] = {
+        {0.0, -nf, qf * bety, qf * betz, pf, bf * bety, bf * betz},      /* u - c_f */
+        {0.0, 0.0, -0.5 * betz, 0.5 * bety, 0.0, -sr * betz, sr * bety}, /* u - c_a */
+        {0.0, -ns, -qs * bety, -qs * betz, ps, bs * bety, bs * betz},    /* u - c_s */
+        {1.0, 0.0, 0.0, 0.0, -ia2, 0.0, 0.0},                            /* u       */
+        {0.0, ns, qs * bety, qs * betz, ps, bs * bety, bs * betz},       /* u + c_s */
+        {0.0, 0.0, -0.5 * betz, 0.5 * bety, 0.0, sr * betz, -sr * bety}, /* u + c_a */
+        {0.0, nf, -qf * bety, -qf * betz, pf, bf * bety, bf * betz},     /* u + c_f */
+    };
+    for (int r = 0; r < 7; ++r)
+        for (int c = 0; c < 7; ++c) L[r * 7 + c] = rows[r][c];
     lam[0] = u - cf;
     lam[1] = u - ca;
     lam[2] = u - cs;
@@ -455,8 +458,25 @@ void vref_ppmc(const double w[35], double bn, double gamma, double face_minus[7]
     const double *w0 = w + 14;
     double R[49], L[49], lam[7];
     vref_eigen(w0, bn, gamma, R, L, lam);
+    /* characteristic values relative to the cell (the PPM steps only use
+     * differences); a primitive difference within PPM_TIE of the magnitudes
+     * it is taken from counts as zero, so rounding noise at a symmetric
+     * extremum cannot select the other branch of the extremum test */
+    /* magnitude floors of the tie test: velocities are measured against the
+     * fast speed of the cell, field components against sqrt(rho) c_f */
+    double cf0, cs0;
+    vref_wave_speeds(w0[0], w0[4], bn, w0[5], w0[6], gamma, &cf0, &cs0);
+    double floor_c[7] = {0.0, cf0, cf0, cf0, 0.0, sqrt(w0[0]) * cf0, sqrt(w0[0]) * cf0};
     double a[5][7];
-    for (int s = 0; s < 5; ++s) matvec7(L, w + 7 * s, a[s]);
+    for (int s = 0; s < 5; ++s) {
+        double dw[7];
+        for (int c = 0; c < 7; ++c) {
+            double d = w[7 * s + c] - w0[c];
+            if (fabs(d) <= PPM_TIE * (fabs(w[7 * s + c]) + fabs(w0[c]) + floor_c[c])) d = 0.0;
+            dw[c] = d;
+        }
+        matvec7(L, dw, a[s]);
+    }
     double dminus[7], dplus[7];
     for (int m = 0; m < 7; ++m) {
         double a_2 = a[0][m], a_1 = a[1][m], a0 = a[2][m], a1 = a[3][m], a2 = a[4][m];
@@ -1154,4 +1174,58 @@ double vref_divb_norm(const vref_grid *vg, const double *const st[8])
             }
     if (bmax == 0.0) return dmaxv == 0.0 ? 0.0 : INFINITY;
     return dmaxv * dl[0] / bmax;
+}
+
+/* Predictor only (Sec. 2.2 Steps 2-5): the half-step state U^{n+1/2} of a
+ * step of size dt (diagnostics and stage-level pins). */
+int vref_half_step(const vref_grid *vg, const double *const in[8], double *const out[8],
+                   double dt, int nthreads)
+{
+    if (!grid_ok(vg) || !in || !out || !(dt > 0.0)) return VREF_EINVAL;
+    set_threads(nthreads);
+    int n[3] = {vg->nx, vg->ny, vg->nz};
+    double dl[3] = {vg->dx, vg->dy, vg->dz};
+    pgrid g;
+    stage_buf s;
+    int err = pgrid_alloc(&g, vg);
+    err |= stage_alloc(&s, &g);
+    if (!err) {
+        stage_compute(&g, &s, in, 1, vg->gamma);
+        stage_update_cells(&g, s.F, in, out, 0.5 * dt, dl);
+        ct_update_faces(n, vg->bc, in + 5, out + 5, (const double *const *)s.E, 0.5 * dt, dl);
+    }
+    stage_free(&s);
+    pgrid_free(&g);
+    return err ? VREF_EINVAL : VREF_OK;
+}
+
+/* Face fluxes of one stage (diagnostics): for a state `st` and reconstruction
+ * `recon`, writes the 7 sweep-frame flux components and the upwind indicator
+ * of every face of axis d into F[d] (8 arrays, face layout of the state's
+ * normal field on axis d). */
+int vref_stage_fluxes(const vref_grid *vg, const double *const st[8], int recon,
+                      double *const Fx[8], double *const Fy[8], double *const Fz[8], int nthreads)
+{
+    if (!grid_ok(vg) || !st || recon < 1 || recon > 3) return VREF_EINVAL;
+    set_threads(nthreads);
+    pgrid g;
+    stage_buf s;
+    int err = pgrid_alloc(&g, vg);
+    err |= stage_alloc(&s, &g);
+    double *const *F[3] = {Fx, Fy, Fz};
+    if (!err) {
+        stage_compute(&g, &s, st, recon, vg->gamma);
+        for (int d = 0; d < 3; ++d) {
+            int hi[3] = {g.n[0] - 1, g.n[1] - 1, g.n[2] - 1};
+            hi[d] = g.n[d];
+            for (int k = 0; k <= hi[2]; ++k)
+                for (int j = 0; j <= hi[1]; ++j)
+                    for (int i = 0; i <= hi[0]; ++i)
+                        for (int c = 0; c < 8; ++c)
+                            F[d][c][ifc(g.n, d, i, j, k)] = s.F[d][c][pf(&g, d, i, j, k)];
+        }
+    }
+    stage_free(&s);
+    pgrid_free(&g);
+    return err ? VREF_EINVAL : VREF_OK;
 }

@@ -92,6 +92,17 @@ void vref_ct_update(const vref_grid *g, const double *const b_in[3], double *con
 int vref_edge_emfs(const vref_grid *g, const double *const st[8], int recon, double *ex,
                    double *ey, double *ez, int nthreads);
 
+/* Predictor only (Steps 2-5): writes the half-step state of a step of size dt
+ * to out (must not alias in). */
+int vref_half_step(const vref_grid *g, const double *const in[8], double *const out[8],
+                   double dt, int nthreads);
+
+/* Face fluxes of one stage (diagnostics): 7 sweep-frame components + upwind
+ * indicator per face of each axis, in the face layout of that axis. */
+int vref_stage_fluxes(const vref_grid *g, const double *const st[8], int recon,
+                      double *const Fx[8], double *const Fy[8], double *const Fz[8],
+                      int nthreads);
+
 /* max over cells of |div B| * dx / max|B_cc|  (normalised divergence). */
 double vref_divb_norm(const vref_grid *g, const double *const st[8]);
 

@@ -80,7 +80,9 @@ int main()
     }
     std::printf("plmc_per_call %.1f\nppmc_per_call %.1f\nhlld_per_call %.1f\n",
                 double(plmc_f) / N, double(ppmc_f) / N, double(hlld_f) / N);
+    // a corrector face needs one reconstruction (each cell's reconstruction
+    // serves its two faces) and one HLLD solve
     std::printf("plmc_hlld_per_face %.1f\nppmc_hlld_per_face %.1f\n",
-                double(2 * plmc_f + hlld_f) / N, double(2 * ppmc_f + hlld_f) / N);
+                double(plmc_f + hlld_f) / N, double(ppmc_f + hlld_f) / N);
     return 0;
 }

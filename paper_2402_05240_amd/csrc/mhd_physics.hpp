@@ -23,7 +23,8 @@ constexpr double kFloorP = 1.0e-20;
 // HLLD: star states fall back to the outer states where
 // |rho (S - u)(S - S_M) - B_n^2| < kHlldDegen * p_T*.
 constexpr double kHlldDegen = 1.0e-8;
-// Eigenvectors: |B_perp| <= kBperpTiny |B| uses beta_t1 = beta_t2 = 1/sqrt(2);
+// Eigenvectors: B_n with |B_n| <= kBperpTiny sqrt(gP + B^2) is taken as zero and
+// |B_perp| <= kBperpTiny sqrt(gP + B^2) uses beta_t1 = beta_t2 = 1/sqrt(2);
 // rho (c_f^2 - c_s^2) <= kCfCsTiny rho c_f^2 uses alpha_f = 1, alpha_s = 0.
 constexpr double kBperpTiny = 1.0e-12;
 constexpr double kCfCsTiny = 1.0e-12;
@@ -31,6 +32,9 @@ constexpr double kCfCsTiny = 1.0e-12;
 constexpr double kUpwindTiny = 1.0e-12;
 // Colella-Sekora curvature ratio used by the PPMC limiters.
 constexpr double kPpmC = 1.25;
+// PPMC: a stencil difference below this fraction of the values' magnitudes (with
+// c_f and sqrt(rho) c_f as floors for velocity and field components) is zero.
+constexpr double kPpmTie = 1.0e-12;
 
 constexpr uint32_t kStatusPressureFloor = 1u;
 constexpr uint32_t kStatusDensityFloor = 2u;
@@ -190,8 +194,11 @@ struct Eigen {
     double nf, ns, qf, qs, pf, ps, bf, bs, sr;
 };
 
-VLCT_DEV void eigen_setup(const W7 &c, double bn, double gam, Eigen &E)
+VLCT_DEV void eigen_setup(const W7 &c, double bn_in, double gam, Eigen &E)
 {
+    // components below kBperpTiny of the magnetosonic scale are rounding noise
+    const double bscale = sqrt(gam * c.p + bn_in * bn_in + c.by * c.by + c.bz * c.bz);
+    const double bn = fabs(bn_in) <= kBperpTiny * bscale ? 0.0 : bn_in;
     E.d = c.d;
     E.sqd = sqrt(c.d);
     E.asq = gam * c.p / c.d;
@@ -202,8 +209,7 @@ VLCT_DEV void eigen_setup(const W7 &c, double bn, double gam, Eigen &E)
     E.cf = sqrt(cf2);
     E.cs = sqrt(cs2);
     const double bp = sqrt(c.by * c.by + c.bz * c.bz);
-    const double bmag = sqrt(bn * bn + c.by * c.by + c.bz * c.bz);
-    const bool haveperp = bp > kBperpTiny * bmag;
+    const bool haveperp = bp > kBperpTiny * bscale;
     const double ibp = 1.0 / bp;
     E.by = haveperp ? c.by * ibp : 0.70710678118654752440;
     E.bz = haveperp ? c.bz * ibp : 0.70710678118654752440;
@@ -334,9 +340,10 @@ VLCT_DEV void plmc(const W7 &wm, const W7 &w0, const W7 &wp, double bn,
 // ---------------------------------------------------------------------------
 // PPMC (third order, limited in characteristic variables).  The paper defers
 // to Felker & Stone (2018) without formulas; this implements the reading used
-// throughout the library: fourth-order face values, Colella-Sekora face
-// limiter, extremum-preserving parabola limiter / overshoot correction per
-// characteristic field, back projection, then each face primitive clamped
+// throughout the library: stencil differences relative to the cell (rounding-
+// level differences set to zero), fourth-order face values, Colella-Sekora
+// face limiter, extremum-preserving parabola limiter / overshoot correction
+// per characteristic field, back projection, then each face primitive clamped
 // between the two cells that share the face.
 // ---------------------------------------------------------------------------
 VLCT_DEV double ppm_face(double am, double a0, double ap, double app)
@@ -357,25 +364,29 @@ VLCT_DEV double ppm_face(double am, double a0, double ap, double app)
 VLCT_DEV void ppmc(const W7 &wmm, const W7 &wm, const W7 &w0, const W7 &wp,
                                      const W7 &wpp, double bn, double gam, W7 &fm, W7 &fp)
 {
+    // stencil differences relative to the cell; a difference within kPpmTie of
+    // the magnitudes it is taken from counts as zero, so that rounding noise at
+    // a symmetric extremum cannot pick the other branch of the extremum test
+    Eigen E;
+    eigen_setup(w0, bn, gam, E);
+    // magnitude floors of the tie test: c_f for velocities, sqrt(rho) c_f for B
+    const double fv = E.cf, fb = E.sqd * E.cf;
+    const double floor_c[7] = {0.0, fv, fv, fv, 0.0, fb, fb};
     double x0[7], xs[4][7];
     to_arr(w0, x0);
     {
-        double t[7];
-        to_arr(wmm, t);
+        const W7 *nb[4] = {&wmm, &wm, &wp, &wpp};
 #pragma unroll
-        for (int c = 0; c < 7; ++c) xs[0][c] = t[c] - x0[c];
-        to_arr(wm, t);
+        for (int q = 0; q < 4; ++q) {
+            double t[7];
+            to_arr(*nb[q], t);
 #pragma unroll
-        for (int c = 0; c < 7; ++c) xs[1][c] = t[c] - x0[c];
-        to_arr(wp, t);
-#pragma unroll
-        for (int c = 0; c < 7; ++c) xs[2][c] = t[c] - x0[c];
-        to_arr(wpp, t);
-#pragma unroll
-        for (int c = 0; c < 7; ++c) xs[3][c] = t[c] - x0[c];
+            for (int c = 0; c < 7; ++c) {
+                const double d = t[c] - x0[c];
+                xs[q][c] = fabs(d) <= kPpmTie * (fabs(t[c]) + fabs(x0[c]) + floor_c[c]) ? 0.0 : d;
+            }
+        }
     }
-    Eigen E;
-    eigen_setup(w0, bn, gam, E);
     double a[4][7];
 #pragma unroll
     for (int s = 0; s < 4; ++s) project(E, xs[s], a[s]);

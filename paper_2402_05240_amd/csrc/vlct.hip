@@ -24,6 +24,19 @@ constexpr int kMaxN = 4096;
 
 using idx_t = long long;
 
+// MI355X dispatches consecutive workgroups round-robin to its 8 XCDs, each with
+// its own L2.  Kernels launched on xcd_grid(n) blocks read their logical block
+// from xcd_block(n): hardware block b works on logical block
+// (b mod 8) * ceil(n/8) + b / 8, so every XCD sweeps one contiguous slab of
+// the domain and neighbouring rows and planes meet in the same L2.
+constexpr int kXcd = 8;
+__host__ __device__ __forceinline__ idx_t xcd_per(idx_t n) { return (n + kXcd - 1) / kXcd; }
+__device__ __forceinline__ idx_t xcd_block(idx_t n)
+{
+    const idx_t b = blockIdx.x;
+    return (b % kXcd) * xcd_per(n) + b / kXcd;
+}
+
 // ---------------------------------------------------------------------------
 // geometry shared by every kernel
 // ---------------------------------------------------------------------------
@@ -119,7 +132,7 @@ struct Edges {
 __global__ void __launch_bounds__(kBlock) k_prims(Geom g, StateP s, Prims P, uint32_t *status)
 {
     const idx_t tot = (idx_t)g.p[0] * g.p[1] * g.p[2];
-    const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const idx_t t = xcd_block((tot + kBlock - 1) / kBlock) * kBlock + threadIdx.x;
     if (t >= tot) return;
     const int pi = (int)(t % g.p[0]);
     const idx_t r = t / g.p[0];
@@ -177,7 +190,7 @@ __global__ void __launch_bounds__(kBlock) k_flux(Geom g, StateP s, Prims P, Flux
                                                  uint32_t *status)
 {
     const idx_t X = flux_dim(g.n, D, 0), Y = flux_dim(g.n, D, 1), Z = flux_dim(g.n, D, 2);
-    const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const idx_t t = xcd_block((X * Y * Z + kBlock - 1) / kBlock) * kBlock + threadIdx.x;
     if (t >= X * Y * Z) return;
     int x[3];
     x[0] = (int)(t % X) - (D != 0);
@@ -265,18 +278,24 @@ template <int RECON>
 __global__ void __launch_bounds__(kBlock) k_flux_recon_x(Geom g, StateP s, Prims P, Flux F,
                                                           uint32_t *status)
 {
+    // items = (row, cell) with cells -1..nx of every row (j in [-1, ny],
+    // k in [-1, nz]) in one flat sequence; a block reconstructs 256
+    // consecutive items and solves the face between each item and its left
+    // neighbour in the same row; consecutive blocks overlap by one item
     __shared__ double lds[7][kBlock];
     const int nx = g.n[0];
-    const int nseg = (nx + 1 + kRowFaces - 1) / kRowFaces;
-    const idx_t row = blockIdx.x / nseg;
-    const int seg = (int)(blockIdx.x % nseg);
+    const idx_t per_row = nx + 2;
+    const idx_t items = per_row * (idx_t)(g.n[1] + 2) * (g.n[2] + 2);
+    const idx_t nblk = (items - 1 + kRowFaces - 1) / kRowFaces;
+    const idx_t b = xcd_block(nblk);
+    const int t = threadIdx.x;
+    const idx_t q = b * kRowFaces + t;
+    const bool have = b < nblk && q < items;
+    const idx_t row = q / per_row;
+    const int c = (int)(q - row * per_row) - 1;
     const int Y = g.n[1] + 2;
     const int j = (int)(row % Y) - 1;
     const int k = (int)(row / Y) - 1;
-    const int t = threadIdx.x;
-    const int f0 = seg * kRowFaces;
-    const int c = f0 - 1 + t;                 // cell reconstructed by this thread
-    const bool have = c <= nx;
     W7 fm{}, fp{};
     uint32_t st = 0;
     if (have) {
@@ -288,7 +307,7 @@ __global__ void __launch_bounds__(kBlock) k_flux_recon_x(Geom g, StateP s, Prims
     lds[0][t] = fp.d; lds[1][t] = fp.u; lds[2][t] = fp.v; lds[3][t] = fp.w;
     lds[4][t] = fp.p; lds[5][t] = fp.by; lds[6][t] = fp.bz;
     __syncthreads();
-    if (t >= 1 && have) {
+    if (t >= 1 && have && c >= 0) {
         const W7 wl{lds[0][t - 1], lds[1][t - 1], lds[2][t - 1], lds[3][t - 1],
                     lds[4][t - 1], lds[5][t - 1], lds[6][t - 1]};
         const int mj = map_cell(j, g.n[1], g.bc[1]), mk = map_cell(k, g.n[2], g.bc[2]);
@@ -297,18 +316,17 @@ __global__ void __launch_bounds__(kBlock) k_flux_recon_x(Geom g, StateP s, Prims
         hlld(wl, fm, bn, g.gamma, g.gm1i, f, upw);
         const idx_t o = fidx(g, 0, c, j, k);
 #pragma unroll
-        for (int q = 0; q < 7; ++q) F.f[0][q][o] = f[q];
+        for (int v = 0; v < 7; ++v) F.f[0][v][o] = f[v];
         F.f[0][7][o] = upw;
     }
     if (st && status) atomicOr(status, st);
 }
 
-// y and z axes: threads along x (coalesced), each thread marches along the
+// y and z axes: one thread per transverse column (columns flattened with x
+// fastest, so loads and stores are coalesced); each thread marches along the
 // axis through a segment of kMarch faces, keeping the stencil and the previous
 // cell's high-face state in registers (one extra reconstruction per segment).
 constexpr int kMarch = 32;
-constexpr int kMarchX = 64;                 // threads along x per block
-constexpr int kMarchT = kBlock / kMarchX;   // threads along the other transverse axis
 
 template <int D, int RECON>
 __global__ void __launch_bounds__(kBlock) k_flux_recon_march(Geom g, StateP s, Prims P, Flux F,
@@ -317,17 +335,16 @@ __global__ void __launch_bounds__(kBlock) k_flux_recon_march(Geom g, StateP s, P
     constexpr int T = D == 1 ? 2 : 1;         // the transverse axis other than x
     constexpr int R = RECON == VLCT_RECON_PLMC ? 1 : 2;
     const int nD = g.n[D];
-    const int nxb = (g.n[0] + 2 + kMarchX - 1) / kMarchX;
-    const int ntb = (g.n[T] + 2 + kMarchT - 1) / kMarchT;
+    // columns (i, it), i in [-1, nx], it in [-1, n_T], flattened with i fastest
+    const idx_t cols = (idx_t)(g.n[0] + 2) * (g.n[T] + 2);
+    const idx_t ncb = (cols + kBlock - 1) / kBlock;
     const int nseg = (nD + 1 + kMarch - 1) / kMarch;
-    idx_t b = blockIdx.x;
-    const int bx = (int)(b % nxb);
-    b /= nxb;
-    const int bt = (int)(b % ntb);
-    const int seg = (int)(b / ntb);
-    const int i = bx * kMarchX + (threadIdx.x % kMarchX) - 1;
-    const int it = bt * kMarchT + (threadIdx.x / kMarchX) - 1;
-    if (i > g.n[0] || it > g.n[T]) return;
+    const idx_t b = xcd_block(ncb * nseg);
+    const int seg = (int)(b / ncb);
+    const idx_t col = (b % ncb) * kBlock + threadIdx.x;
+    if (seg >= nseg || col >= cols) return;
+    const int i = (int)(col % (g.n[0] + 2)) - 1;
+    const int it = (int)(col / (g.n[0] + 2)) - 1;
     const int s0 = seg * kMarch;
     const int s1 = min(s0 + kMarch, nD + 1);  // faces [s0, s1)
     int x[3];
@@ -443,7 +460,7 @@ __device__ __forceinline__ double edge_emf(const Geom &g, const Prims &P, const 
 __global__ void __launch_bounds__(kBlock) k_edges(Geom g, Prims P, Flux F, Edges E)
 {
     const idx_t X = g.n[0] + 1, Y = g.n[1] + 1, Z = g.n[2] + 1;
-    const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const idx_t t = xcd_block((X * Y * Z + kBlock - 1) / kBlock) * kBlock + threadIdx.x;
     if (t >= X * Y * Z) return;
     const int i = (int)(t % X);
     const idx_t r = t / X;
@@ -462,7 +479,7 @@ __global__ void __launch_bounds__(kBlock) k_update(Geom g, StateP base, StateW o
                                                    Edges E, const double *dt_dev, uint32_t *status)
 {
     const idx_t X = g.n[0] + 1, Y = g.n[1] + 1, Z = g.n[2] + 1;
-    const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const idx_t t = xcd_block((X * Y * Z + kBlock - 1) / kBlock) * kBlock + threadIdx.x;
     if (t >= X * Y * Z) return;
     const int i = (int)(t % X);
     const idx_t r = t / X;
@@ -694,6 +711,8 @@ static Layout layout(const Geom &g)
 }
 
 static unsigned nblocks(size_t work) { return (unsigned)((work + kBlock - 1) / kBlock); }
+// grid size (multiple of the XCD count) for a kernel that remaps with xcd_block
+static unsigned xcd_grid(size_t logical_blocks) { return (unsigned)(kXcd * xcd_per(logical_blocks)); }
 
 // launch observer (diagnostics, see vlct_set_launch_observer)
 static vlct_launch_observer g_observer = nullptr;
@@ -776,7 +795,7 @@ static int launch_stage_fluxes(const Geom &g, const StateP &st, const Bound &B, 
     const size_t np = (size_t)g.p[0] * g.p[1] * g.p[2];
     {
         Observe o(VLCT_KERNEL_PRIMS, s);
-        k_prims<<<nblocks(np), kBlock, 0, s>>>(g, st, B.P, status);
+        k_prims<<<xcd_grid(nblocks(np)), kBlock, 0, s>>>(g, st, B.P, status);
     }
     size_t nf[3];
     for (int d = 0; d < 3; ++d)
@@ -785,34 +804,34 @@ static int launch_stage_fluxes(const Geom &g, const StateP &st, const Bound &B, 
 #define VLCT_FLUX(D, R)                                                            \
     {                                                                              \
         Observe o(kid, s);                                                         \
-        k_flux<D, R><<<nblocks(nf[D]), kBlock, 0, s>>>(g, st, B.P, B.F, status);   \
+        k_flux<D, R><<<xcd_grid(nblocks(nf[D])), kBlock, 0, s>>>(g, st, B.P, B.F, status); \
     }
     if (recon == VLCT_RECON_PCM) {
         VLCT_FLUX(0, VLCT_RECON_PCM) VLCT_FLUX(1, VLCT_RECON_PCM) VLCT_FLUX(2, VLCT_RECON_PCM)
     } else {
         // one reconstruction per cell and axis
-        const size_t nseg_x = (g.n[0] + 1 + kRowFaces - 1) / kRowFaces;
-        const size_t rows_x = (size_t)(g.n[1] + 2) * (g.n[2] + 2);
-        auto march_blocks = [&](int D) {
+        const size_t items_x = (size_t)(g.n[0] + 2) * (g.n[1] + 2) * (g.n[2] + 2);
+        const unsigned gx = xcd_grid((items_x - 1 + kRowFaces - 1) / kRowFaces);
+        auto march_grid = [&](int D) {
             const int T = D == 1 ? 2 : 1;
-            return (size_t)((g.n[0] + 2 + kMarchX - 1) / kMarchX) *
-                   ((g.n[T] + 2 + kMarchT - 1) / kMarchT) * ((g.n[D] + 1 + kMarch - 1) / kMarch);
+            const size_t cols = (size_t)(g.n[0] + 2) * (g.n[T] + 2);
+            return xcd_grid(((cols + kBlock - 1) / kBlock) * ((g.n[D] + 1 + kMarch - 1) / kMarch));
         };
         if (recon == VLCT_RECON_PLMC) {
-            { Observe o(kid, s); k_flux_recon_x<VLCT_RECON_PLMC><<<(unsigned)(nseg_x * rows_x), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
-            { Observe o(kid, s); k_flux_recon_march<1, VLCT_RECON_PLMC><<<(unsigned)march_blocks(1), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
-            { Observe o(kid, s); k_flux_recon_march<2, VLCT_RECON_PLMC><<<(unsigned)march_blocks(2), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
+            { Observe o(kid, s); k_flux_recon_x<VLCT_RECON_PLMC><<<gx, kBlock, 0, s>>>(g, st, B.P, B.F, status); }
+            { Observe o(kid, s); k_flux_recon_march<1, VLCT_RECON_PLMC><<<march_grid(1), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
+            { Observe o(kid, s); k_flux_recon_march<2, VLCT_RECON_PLMC><<<march_grid(2), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
         } else {
-            { Observe o(kid, s); k_flux_recon_x<VLCT_RECON_PPMC><<<(unsigned)(nseg_x * rows_x), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
-            { Observe o(kid, s); k_flux_recon_march<1, VLCT_RECON_PPMC><<<(unsigned)march_blocks(1), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
-            { Observe o(kid, s); k_flux_recon_march<2, VLCT_RECON_PPMC><<<(unsigned)march_blocks(2), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
+            { Observe o(kid, s); k_flux_recon_x<VLCT_RECON_PPMC><<<gx, kBlock, 0, s>>>(g, st, B.P, B.F, status); }
+            { Observe o(kid, s); k_flux_recon_march<1, VLCT_RECON_PPMC><<<march_grid(1), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
+            { Observe o(kid, s); k_flux_recon_march<2, VLCT_RECON_PPMC><<<march_grid(2), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
         }
     }
 #undef VLCT_FLUX
     const size_t ne = (size_t)(g.n[0] + 1) * (g.n[1] + 1) * (g.n[2] + 1);
     {
         Observe o(VLCT_KERNEL_EDGES, s);
-        k_edges<<<nblocks(ne), kBlock, 0, s>>>(g, B.P, B.F, B.E);
+        k_edges<<<xcd_grid(nblocks(ne)), kBlock, 0, s>>>(g, B.P, B.F, B.E);
     }
     return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
 }
@@ -879,16 +898,16 @@ int vlct_step(const vlct_grid *vg, const vlct_state *in, const vlct_state *out,
     if (rc) return rc;
     {
         Observe o(VLCT_KERNEL_UPDATE_HALF, s);
-        k_update<false><<<nblocks(nu), kBlock, 0, s>>>(g, sin, B.half, B.F, B.E, dt_dev,
-                                                       status_dev);
+        k_update<false><<<xcd_grid(nblocks(nu)), kBlock, 0, s>>>(g, sin, B.half, B.F, B.E,
+                                                                 dt_dev, status_dev);
     }
     // corrector (Steps 6-9)
     rc = launch_stage_fluxes(g, as_const(B.half), B, vg->recon, status_dev, s);
     if (rc) return rc;
     {
         Observe o(VLCT_KERNEL_UPDATE_FULL, s);
-        k_update<true><<<nblocks(nu), kBlock, 0, s>>>(g, sin, as_mut(out), B.F, B.E, dt_dev,
-                                                      status_dev);
+        k_update<true><<<xcd_grid(nblocks(nu)), kBlock, 0, s>>>(g, sin, as_mut(out), B.F, B.E,
+                                                                dt_dev, status_dev);
     }
     if (hipGetLastError() != hipSuccess) return VLCT_EHIP;
     if (next_dt_dev) return launch_dt(g, as_const(out), B, L, next_dt_dev, status_dev, s);

@@ -42,7 +42,7 @@ def _gpu_run(g, s0, dts, inplace=False):
     for dt in dts:
         st.set_dt(dt)
         st.step()
-        nexts.append(st.dt)   # after the step self.dt holds the next dt (device)
+        nexts.append(st.dt.clone())   # after the step st.dt holds the next dt (device)
     torch.cuda.synchronize()
     out = st.download()
     return out, [float(x.item()) for x in nexts], st.status_bits()
@@ -141,7 +141,9 @@ def test_turbulence_multi_step(recon, nsteps):
     orc, dts, nexts_ref, st_ref = _oracle_run(g, s0, nsteps=nsteps)
     _say("gpu")
     gpu, nexts, status = _gpu_run(g, s0, dts)
-    assert status == st_ref == 0
+    # both implementations report the same floors (PPMC on this coarse Mach-1
+    # grid reconstructs a few negative interface pressures)
+    assert status == st_ref
     _check(g, s0, gpu, orc, elem=1e-9)
     assert abs(nexts[-1] - nexts_ref[-1]) <= 1e-12 * nexts_ref[-1]
 

@@ -259,10 +259,13 @@ def test_field_loop_advection():
 # symmetry and the hydrodynamic limit
 # ---------------------------------------------------------------------------
 
-def test_blast_mirror_symmetry_plmc():
-    """z -> -z mirror symmetry of the magnetised blast (B_z = 0)."""
-    g, s = I.blast((16, 16, 16), b0=1.0, recon=2)
-    s, _, st = ref.run(g, s, 3, nthreads=2)
+@pytest.mark.parametrize("recon", [2, 3])
+def test_blast_mirror_symmetry(recon):
+    """z -> -z mirror symmetry of the magnetised blast (B_z = 0).  With PPMC this
+    also pins the rounding-robust tie handling: without it the discontinuous
+    extremum test turns rounding asymmetry into O(1e-2) differences."""
+    g, s = I.blast((24, 24, 24), b0=1.0, recon=recon)
+    s, _, st = ref.run(g, s, 4, nthreads=4)
     assert st == 0
     m = {f: s[f][::-1].copy() for f in FIELDS}
     m["mz"] = -m["mz"]
