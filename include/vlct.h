@@ -88,8 +88,8 @@ typedef struct vlct_state {
 
 /* Bytes of device workspace vlct_step / vlct_cfl_dt need for this grid
  * (0 if the descriptor is invalid).  The workspace holds the half-step state,
- * ghost-padded primitives, face fluxes and edge fields; its contents are
- * scratch between calls. */
+ * ghost-padded primitives and face fluxes; its contents are scratch between
+ * calls. */
 size_t vlct_workspace_bytes(const vlct_grid *g);
 
 /* CFL time step of state `s` (Sec. 2.2 Step 1, Eq. dt):
@@ -121,9 +121,9 @@ int vlct_step(const vlct_grid *g, const vlct_state *in, const vlct_state *out,
 #define VLCT_KERNEL_PRIMS 0        /* primitive variables (both stages) */
 #define VLCT_KERNEL_FLUX_PCM 1     /* predictor: PCM states + HLLD, one launch per axis */
 #define VLCT_KERNEL_FLUX_RECON 2   /* corrector: PLMC/PPMC states + HLLD, one launch per axis */
-#define VLCT_KERNEL_EDGES 3        /* CT edge electric fields (both stages) */
-#define VLCT_KERNEL_UPDATE_HALF 4  /* half-step cell and face update */
-#define VLCT_KERNEL_UPDATE_FULL 5  /* full-step cell and face update */
+#define VLCT_KERNEL_EDGES 3        /* reserved (edge fields are computed inside the updates) */
+#define VLCT_KERNEL_UPDATE_HALF 4  /* CT edge fields + half-step cell and face update */
+#define VLCT_KERNEL_UPDATE_FULL 5  /* CT edge fields + full-step cell and face update */
 #define VLCT_KERNEL_DT 6           /* CFL reduction (two launches) */
 #define VLCT_KERNEL_COUNT 7
 typedef void (*vlct_launch_observer)(void *user, int kernel, int phase, void *stream);

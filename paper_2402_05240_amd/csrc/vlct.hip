@@ -2,9 +2,9 @@
 // "Cholla-MHD", Sec. 2.2) behind the C ABI of include/vlct.h.
 //
 // Step structure (all kernels on the caller's stream, state resident in HBM):
-//   stage(U^n, PCM)        : prims -> 3 x (HLLD fluxes) -> edge EMFs -> half update
-//   stage(U^{n+1/2}, PLMC) : prims -> 3 x (reconstruction + HLLD) -> edge EMFs
-//                            -> full update from U^n -> next-dt reduction
+//   stage(U^n, PCM)        : prims -> 3 x (HLLD fluxes) -> CT edge EMFs + half update
+//   stage(U^{n+1/2}, PLMC) : prims -> 3 x (reconstruction + HLLD)
+//                            -> CT edge EMFs + full update from U^n -> next-dt reduction
 // Boundary conditions enter only through the primitive kernel, which fills a
 // ghost-padded primitive array by index mapping (wrap / clamp), and through
 // face-index mapping when the stored normal field is read.
@@ -96,17 +96,6 @@ __device__ __forceinline__ idx_t fidx(const Geom &g, int d, int i, int j, int k)
     return ((idx_t)(k + (d != 2)) * Y + (j + (d != 1))) * X + (i + (d != 0));
 }
 
-// edge arrays of axis a: index in [0, n_e] across a, [0, n_a - 1] along a
-__host__ __device__ __forceinline__ idx_t edge_dim(const int n[3], int a, int e)
-{
-    return n[e] + (e != a ? 1 : 0);
-}
-__device__ __forceinline__ idx_t eidx(const Geom &g, int a, int i, int j, int k)
-{
-    const idx_t X = edge_dim(g.n, a, 0), Y = edge_dim(g.n, a, 1);
-    return ((idx_t)k * Y + j) * X + i;
-}
-
 struct StateP {
     const double *u[5];
     const double *b[3];
@@ -120,9 +109,6 @@ struct Prims {
 };
 struct Flux {
     double *f[3][8];  // per axis: 7 sweep-frame components + upwind indicator
-};
-struct Edges {
-    double *e[3];
 };
 
 // ---------------------------------------------------------------------------
@@ -457,97 +443,128 @@ __device__ __forceinline__ double edge_emf(const Geom &g, const Prims &P, const 
     return avg + 0.25 * (t1 + t2 + t3 + t4);
 }
 
-__global__ void __launch_bounds__(kBlock) k_edges(Geom g, Prims P, Flux F, Edges E)
-{
-    const idx_t X = g.n[0] + 1, Y = g.n[1] + 1, Z = g.n[2] + 1;
-    const idx_t t = xcd_block((X * Y * Z + kBlock - 1) / kBlock) * kBlock + threadIdx.x;
-    if (t >= X * Y * Z) return;
-    const int i = (int)(t % X);
-    const idx_t r = t / X;
-    const int j = (int)(r % Y);
-    const int k = (int)(r / Y);
-    if (i < g.n[0]) E.e[0][eidx(g, 0, i, j, k)] = edge_emf<0>(g, P, F, i, j, k);
-    if (j < g.n[1]) E.e[1][eidx(g, 1, i, j, k)] = edge_emf<1>(g, P, F, i, j, k);
-    if (k < g.n[2]) E.e[2][eidx(g, 2, i, j, k)] = edge_emf<2>(g, P, F, i, j, k);
-}
+// ---------------------------------------------------------------------------
+// fused CT + update (Steps 4-5 and 8-9): a block owns a 32 x 8 column tile and
+// marches along z.  For each plane k it computes the edge fields it needs once
+// into LDS -- E_z of plane k, E_x / E_y of the plane above (k+1/2); those of
+// the plane below are kept from the previous iteration -- and then updates the
+// plane's cells and the faces owned by them.  Same arithmetic as k_edges and
+// k_update, without the round trip of the edge arrays through HBM.
+// ---------------------------------------------------------------------------
+constexpr int kTx = 32, kTy = 8, kTz = 16;
 
-// ---------------------------------------------------------------------------
-// conservative cell update and CT face update (Steps 5 and 9)
-// ---------------------------------------------------------------------------
 template <bool FULL>
-__global__ void __launch_bounds__(kBlock) k_update(Geom g, StateP base, StateW out, Flux F,
-                                                   Edges E, const double *dt_dev, uint32_t *status)
+__global__ void __launch_bounds__(kBlock) k_ct_update(Geom g, Prims P, Flux F, StateP base,
+                                                       StateW out, const double *dt_dev,
+                                                       uint32_t *status)
 {
-    const idx_t X = g.n[0] + 1, Y = g.n[1] + 1, Z = g.n[2] + 1;
-    const idx_t t = xcd_block((X * Y * Z + kBlock - 1) / kBlock) * kBlock + threadIdx.x;
-    if (t >= X * Y * Z) return;
-    const int i = (int)(t % X);
-    const idx_t r = t / X;
-    const int j = (int)(r % Y);
-    const int k = (int)(r / Y);
+    __shared__ double sez[kTy + 1][kTx + 1];
+    __shared__ double sex[2][kTy + 1][kTx];
+    __shared__ double sey[2][kTy][kTx + 1];
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    // positions owned by threads: cells/faces i in [0, ex), j in [0, ey)
+    const int ex = nx + (g.bc[0] == VLCT_BC_OUTFLOW), ey = ny + (g.bc[1] == VLCT_BC_OUTFLOW);
+    const int ntx = (ex + kTx - 1) / kTx, nty = (ey + kTy - 1) / kTy, ntz = (nz + kTz - 1) / kTz;
+    const idx_t b = xcd_block((idx_t)ntx * nty * ntz);
+    if (b >= (idx_t)ntx * nty * ntz) return;
+    const int bx = (int)(b % ntx), by = (int)((b / ntx) % nty), bz = (int)(b / ((idx_t)ntx * nty));
+    const int i0 = bx * kTx, j0 = by * kTy, k0 = bz * kTz, k1 = min(k0 + kTz, nz);
+    const int tx = threadIdx.x % kTx, ty = threadIdx.x / kTx;
+    const int i = i0 + tx, j = j0 + ty;
     const double dt = FULL ? dt_dev[0] : 0.5 * dt_dev[0];
     const double cx = dt / g.dl[0], cy = dt / g.dl[1], cz = dt / g.dl[2];
-    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    constexpr int NEZ = (kTy + 1) * (kTx + 1), NEX = (kTy + 1) * kTx, NEY = kTy * (kTx + 1);
+
+    // edges of the plane k+1/2 (E_x, E_y at edge index k) into slot h
+    auto horizontal_edges = [&](int kk, int h) {
+        for (int q = threadIdx.x; q < NEX; q += kBlock) {
+            const int a = q % kTx, c = q / kTx, ii = i0 + a, jj = j0 + c;
+            if (ii < nx && jj <= ny) sex[h][c][a] = edge_emf<0>(g, P, F, ii, jj, kk);
+        }
+        for (int q = threadIdx.x; q < NEY; q += kBlock) {
+            const int a = q % (kTx + 1), c = q / (kTx + 1), ii = i0 + a, jj = j0 + c;
+            if (ii <= nx && jj < ny) sey[h][c][a] = edge_emf<1>(g, P, F, ii, jj, kk);
+        }
+    };
+    int lo = 0;
+    horizontal_edges(k0, lo);
     bool bad = false;
-    if (i < nx && j < ny && k < nz) {
-        const idx_t c = cell_store(g, i, j, k);
-        const idx_t fx0 = fidx(g, 0, i, j, k), fx1 = fidx(g, 0, i + 1, j, k);
-        const idx_t fy0 = fidx(g, 1, i, j, k), fy1 = fidx(g, 1, i, j + 1, k);
-        const idx_t fz0 = fidx(g, 2, i, j, k), fz1 = fidx(g, 2, i, j, k + 1);
-        // lab components of the sweep-frame fluxes: x (x,y,z), y (y,z,x), z (z,x,y)
-        const double dxr = F.f[0][0][fx1] - F.f[0][0][fx0];
-        const double dyr = F.f[1][0][fy1] - F.f[1][0][fy0];
-        const double dzr = F.f[2][0][fz1] - F.f[2][0][fz0];
-        const double dxe = F.f[0][4][fx1] - F.f[0][4][fx0];
-        const double dye = F.f[1][4][fy1] - F.f[1][4][fy0];
-        const double dze = F.f[2][4][fz1] - F.f[2][4][fz0];
-        const double dxmx = F.f[0][1][fx1] - F.f[0][1][fx0];
-        const double dxmy = F.f[0][2][fx1] - F.f[0][2][fx0];
-        const double dxmz = F.f[0][3][fx1] - F.f[0][3][fx0];
-        const double dymy = F.f[1][1][fy1] - F.f[1][1][fy0];
-        const double dymz = F.f[1][2][fy1] - F.f[1][2][fy0];
-        const double dymx = F.f[1][3][fy1] - F.f[1][3][fy0];
-        const double dzmz = F.f[2][1][fz1] - F.f[2][1][fz0];
-        const double dzmx = F.f[2][2][fz1] - F.f[2][2][fz0];
-        const double dzmy = F.f[2][3][fz1] - F.f[2][3][fz0];
-        const double u0 = base.u[0][c] - cx * dxr - cy * dyr - cz * dzr;
-        const double u1 = base.u[1][c] - cx * dxmx - cy * dymx - cz * dzmx;
-        const double u2 = base.u[2][c] - cx * dxmy - cy * dymy - cz * dzmy;
-        const double u3 = base.u[3][c] - cx * dxmz - cy * dymz - cz * dzmz;
-        const double u4 = base.u[4][c] - cx * dxe - cy * dye - cz * dze;
-        out.u[0][c] = u0;
-        out.u[1][c] = u1;
-        out.u[2][c] = u2;
-        out.u[3][c] = u3;
-        out.u[4][c] = u4;
-        if (FULL) bad |= !isfinite(u0) || !isfinite(u1) || !isfinite(u2) || !isfinite(u3) ||
-                         !isfinite(u4);
+    for (int k = k0; k < k1; ++k) {
+        for (int q = threadIdx.x; q < NEZ; q += kBlock) {
+            const int a = q % (kTx + 1), c = q / (kTx + 1), ii = i0 + a, jj = j0 + c;
+            if (ii <= nx && jj <= ny) sez[c][a] = edge_emf<2>(g, P, F, ii, jj, k);
+        }
+        horizontal_edges(k + 1, 1 - lo);
+        __syncthreads();
+        const int hi = 1 - lo;
+        if (i < ex && j < ey) {
+            if (i < nx && j < ny) {
+                const idx_t c = cell_store(g, i, j, k);
+                const idx_t fx0 = fidx(g, 0, i, j, k), fx1 = fidx(g, 0, i + 1, j, k);
+                const idx_t fy0 = fidx(g, 1, i, j, k), fy1 = fidx(g, 1, i, j + 1, k);
+                const idx_t fz0 = fidx(g, 2, i, j, k), fz1 = fidx(g, 2, i, j, k + 1);
+                const double dxr = F.f[0][0][fx1] - F.f[0][0][fx0];
+                const double dyr = F.f[1][0][fy1] - F.f[1][0][fy0];
+                const double dzr = F.f[2][0][fz1] - F.f[2][0][fz0];
+                const double dxe = F.f[0][4][fx1] - F.f[0][4][fx0];
+                const double dye = F.f[1][4][fy1] - F.f[1][4][fy0];
+                const double dze = F.f[2][4][fz1] - F.f[2][4][fz0];
+                const double dxmx = F.f[0][1][fx1] - F.f[0][1][fx0];
+                const double dxmy = F.f[0][2][fx1] - F.f[0][2][fx0];
+                const double dxmz = F.f[0][3][fx1] - F.f[0][3][fx0];
+                const double dymy = F.f[1][1][fy1] - F.f[1][1][fy0];
+                const double dymz = F.f[1][2][fy1] - F.f[1][2][fy0];
+                const double dymx = F.f[1][3][fy1] - F.f[1][3][fy0];
+                const double dzmz = F.f[2][1][fz1] - F.f[2][1][fz0];
+                const double dzmx = F.f[2][2][fz1] - F.f[2][2][fz0];
+                const double dzmy = F.f[2][3][fz1] - F.f[2][3][fz0];
+                const double u0 = base.u[0][c] - cx * dxr - cy * dyr - cz * dzr;
+                const double u1 = base.u[1][c] - cx * dxmx - cy * dymx - cz * dzmx;
+                const double u2 = base.u[2][c] - cx * dxmy - cy * dymy - cz * dzmy;
+                const double u3 = base.u[3][c] - cx * dxmz - cy * dymz - cz * dzmz;
+                const double u4 = base.u[4][c] - cx * dxe - cy * dye - cz * dze;
+                out.u[0][c] = u0;
+                out.u[1][c] = u1;
+                out.u[2][c] = u2;
+                out.u[3][c] = u3;
+                out.u[4][c] = u4;
+                if (FULL) bad |= !isfinite(u0) || !isfinite(u1) || !isfinite(u2) || !isfinite(u3) ||
+                                 !isfinite(u4);
+            }
+            if (j < ny) {  // face x (i-1/2, j, k)
+                const double b0 = base.b[0][face_store(g, 0, i, j, k)];
+                const double v = b0 - cy * (sez[ty + 1][tx] - sez[ty][tx])
+                                 + cz * (sey[hi][ty][tx] - sey[lo][ty][tx]);
+                out.b[0][face_store(g, 0, i, j, k)] = v;
+                if (g.bc[0] == VLCT_BC_PERIODIC && i == 0) out.b[0][face_store(g, 0, nx, j, k)] = v;
+                if (FULL) bad |= !isfinite(v);
+            }
+            if (i < nx) {  // face y (i, j-1/2, k)
+                const double b0 = base.b[1][face_store(g, 1, i, j, k)];
+                const double v = b0 - cz * (sex[hi][ty][tx] - sex[lo][ty][tx])
+                                 + cx * (sez[ty][tx + 1] - sez[ty][tx]);
+                out.b[1][face_store(g, 1, i, j, k)] = v;
+                if (g.bc[1] == VLCT_BC_PERIODIC && j == 0) out.b[1][face_store(g, 1, i, ny, k)] = v;
+                if (FULL) bad |= !isfinite(v);
+            }
+            if (i < nx && j < ny) {  // face z (i, j, k-1/2)
+                const double b0 = base.b[2][face_store(g, 2, i, j, k)];
+                const double v = b0 - cx * (sey[lo][ty][tx + 1] - sey[lo][ty][tx])
+                                 + cy * (sex[lo][ty + 1][tx] - sex[lo][ty][tx]);
+                out.b[2][face_store(g, 2, i, j, k)] = v;
+                if (g.bc[2] == VLCT_BC_PERIODIC && k == 0) out.b[2][face_store(g, 2, i, j, nz)] = v;
+                if (FULL) bad |= !isfinite(v);
+            }
+        }
+        __syncthreads();
+        lo = hi;
     }
-    // face x (i-1/2, j, k): B_x -= dt/dy dE_z/dj - dt/dz dE_y/dk
-    if (j < ny && k < nz && !(g.bc[0] == VLCT_BC_PERIODIC && i == nx)) {
-        const double b0 = base.b[0][face_store(g, 0, i, j, k)];
-        const double v = b0 - cy * (E.e[2][eidx(g, 2, i, j + 1, k)] - E.e[2][eidx(g, 2, i, j, k)])
-                         + cz * (E.e[1][eidx(g, 1, i, j, k + 1)] - E.e[1][eidx(g, 1, i, j, k)]);
-        out.b[0][face_store(g, 0, i, j, k)] = v;
-        if (g.bc[0] == VLCT_BC_PERIODIC && i == 0) out.b[0][face_store(g, 0, nx, j, k)] = v;
-        if (FULL) bad |= !isfinite(v);
-    }
-    // face y (i, j-1/2, k): B_y -= dt/dz dE_x/dk - dt/dx dE_z/di
-    if (i < nx && k < nz && !(g.bc[1] == VLCT_BC_PERIODIC && j == ny)) {
-        const double b0 = base.b[1][face_store(g, 1, i, j, k)];
-        const double v = b0 - cz * (E.e[0][eidx(g, 0, i, j, k + 1)] - E.e[0][eidx(g, 0, i, j, k)])
-                         + cx * (E.e[2][eidx(g, 2, i + 1, j, k)] - E.e[2][eidx(g, 2, i, j, k)]);
-        out.b[1][face_store(g, 1, i, j, k)] = v;
-        if (g.bc[1] == VLCT_BC_PERIODIC && j == 0) out.b[1][face_store(g, 1, i, ny, k)] = v;
-        if (FULL) bad |= !isfinite(v);
-    }
-    // face z (i, j, k-1/2): B_z -= dt/dx dE_y/di - dt/dy dE_x/dj
-    if (i < nx && j < ny && !(g.bc[2] == VLCT_BC_PERIODIC && k == nz)) {
-        const double b0 = base.b[2][face_store(g, 2, i, j, k)];
-        const double v = b0 - cx * (E.e[1][eidx(g, 1, i + 1, j, k)] - E.e[1][eidx(g, 1, i, j, k)])
-                         + cy * (E.e[0][eidx(g, 0, i, j + 1, k)] - E.e[0][eidx(g, 0, i, j, k)]);
-        out.b[2][face_store(g, 2, i, j, k)] = v;
-        if (g.bc[2] == VLCT_BC_PERIODIC && k == 0) out.b[2][face_store(g, 2, i, j, nz)] = v;
+    // the top z faces of an outflow axis, from the last plane of edges
+    if (k1 == nz && g.bc[2] == VLCT_BC_OUTFLOW && i < nx && j < ny && i < ex && j < ey) {
+        const double b0 = base.b[2][face_store(g, 2, i, j, nz)];
+        const double v = b0 - cx * (sey[lo][ty][tx + 1] - sey[lo][ty][tx])
+                         + cy * (sex[lo][ty + 1][tx] - sex[lo][ty][tx]);
+        out.b[2][face_store(g, 2, i, j, nz)] = v;
         if (FULL) bad |= !isfinite(v);
     }
     if (FULL && bad && status) atomicOr(status, kStatusNonfinite);
@@ -677,8 +694,8 @@ static size_t field_len(const int n[3], int f)
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t half[8], prims, flux[3], edges[3], partial, total;
-    size_t prims_len, flux_len[3], edge_len[3], npartial;
+    size_t half[8], prims, flux[3], partial, total;
+    size_t prims_len, flux_len[3], npartial;
 };
 
 static Layout layout(const Geom &g)
@@ -696,11 +713,6 @@ static Layout layout(const Geom &g)
         L.flux_len[d] = (size_t)flux_dim(g.n, d, 0) * flux_dim(g.n, d, 1) * flux_dim(g.n, d, 2);
         L.flux[d] = off;
         off += 8 * align_up(L.flux_len[d] * sizeof(double));
-    }
-    for (int a = 0; a < 3; ++a) {
-        L.edge_len[a] = (size_t)edge_dim(g.n, a, 0) * edge_dim(g.n, a, 1) * edge_dim(g.n, a, 2);
-        L.edges[a] = off;
-        off += align_up(L.edge_len[a] * sizeof(double));
     }
     const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
     L.npartial = (N + kBlock - 1) / kBlock;
@@ -734,7 +746,6 @@ struct Observe {
 struct Bound {
     Prims P;
     Flux F;
-    Edges E;
     StateW half;
     double *partial;
 };
@@ -753,7 +764,6 @@ static Bound bind(const Layout &L, void *ws)
         for (int c = 0; c < 8; ++c)
             B.F.f[d][c] = reinterpret_cast<double *>(
                 b + L.flux[d] + c * align_up(L.flux_len[d] * sizeof(double)));
-    for (int a = 0; a < 3; ++a) B.E.e[a] = reinterpret_cast<double *>(b + L.edges[a]);
     B.partial = reinterpret_cast<double *>(b + L.partial);
     return B;
 }
@@ -828,11 +838,6 @@ static int launch_stage_fluxes(const Geom &g, const StateP &st, const Bound &B, 
         }
     }
 #undef VLCT_FLUX
-    const size_t ne = (size_t)(g.n[0] + 1) * (g.n[1] + 1) * (g.n[2] + 1);
-    {
-        Observe o(VLCT_KERNEL_EDGES, s);
-        k_edges<<<xcd_grid(nblocks(ne)), kBlock, 0, s>>>(g, B.P, B.F, B.E);
-    }
     return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
 }
 
@@ -891,23 +896,25 @@ int vlct_step(const vlct_grid *vg, const vlct_state *in, const vlct_state *out,
     const Bound B = bind(L, ws);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const StateP sin = as_const(in);
-    const size_t nu = (size_t)(g.n[0] + 1) * (g.n[1] + 1) * (g.n[2] + 1);
+    const int ntx = (g.n[0] + (g.bc[0] == VLCT_BC_OUTFLOW) + kTx - 1) / kTx;
+    const int nty = (g.n[1] + (g.bc[1] == VLCT_BC_OUTFLOW) + kTy - 1) / kTy;
+    const int ntz = (g.n[2] + kTz - 1) / kTz;
+    const unsigned gct = xcd_grid((size_t)ntx * nty * ntz);
 
     // predictor (Steps 2-5)
     int rc = launch_stage_fluxes(g, sin, B, VLCT_RECON_PCM, status_dev, s);
     if (rc) return rc;
     {
         Observe o(VLCT_KERNEL_UPDATE_HALF, s);
-        k_update<false><<<xcd_grid(nblocks(nu)), kBlock, 0, s>>>(g, sin, B.half, B.F, B.E,
-                                                                 dt_dev, status_dev);
+        k_ct_update<false><<<gct, kBlock, 0, s>>>(g, B.P, B.F, sin, B.half, dt_dev, status_dev);
     }
     // corrector (Steps 6-9)
     rc = launch_stage_fluxes(g, as_const(B.half), B, vg->recon, status_dev, s);
     if (rc) return rc;
     {
         Observe o(VLCT_KERNEL_UPDATE_FULL, s);
-        k_update<true><<<xcd_grid(nblocks(nu)), kBlock, 0, s>>>(g, sin, as_mut(out), B.F, B.E,
-                                                                dt_dev, status_dev);
+        k_ct_update<true><<<gct, kBlock, 0, s>>>(g, B.P, B.F, sin, as_mut(out), dt_dev,
+                                                 status_dev);
     }
     if (hipGetLastError() != hipSuccess) return VLCT_EHIP;
     if (next_dt_dev) return launch_dt(g, as_const(out), B, L, next_dt_dev, status_dev, s);
