@@ -187,7 +187,7 @@ VLCT_DEV void hlld(const W7 &L, const W7 &R, double bn, double gam, double gm1i,
 // Waves m = 0..6: u-cf, u-ca, u-cs, u, u+cs, u+ca, u+cf.
 // ---------------------------------------------------------------------------
 struct Eigen {
-    double d, sqd, asq, a;        // rho, sqrt(rho), a^2 = gP/rho, a
+    double d, sqd, asq, a, ia2;   // rho, sqrt(rho), a^2 = gP/rho, a, 1/a^2
     double cf, cs, af, as;        // fast/slow speeds and alpha_f, alpha_s
     double by, bz, s;             // beta_t1, beta_t2, sign(B_n)
     // left-eigenvector coefficients
@@ -199,13 +199,16 @@ VLCT_DEV void eigen_setup(const W7 &c, double bn_in, double gam, Eigen &E)
     // components below kBperpTiny of the magnetosonic scale are rounding noise
     const double bscale = sqrt(gam * c.p + bn_in * bn_in + c.by * c.by + c.bz * c.bz);
     const double bn = fabs(bn_in) <= kBperpTiny * bscale ? 0.0 : bn_in;
+    const double id = 1.0 / c.d;
+    const double gp = gam * c.p;
     E.d = c.d;
     E.sqd = sqrt(c.d);
-    E.asq = gam * c.p / c.d;
+    E.asq = gp * id;
     E.a = sqrt(E.asq);
+    E.ia2 = c.d / gp;
     double disc;
     const double cf2 = fast_sq(c.d, c.p, bn, c.by, c.bz, gam, disc);
-    const double cs2 = (gam * c.p * bn * bn) / (c.d * c.d * cf2);
+    const double cs2 = E.asq * bn * bn * id / cf2;
     E.cf = sqrt(cf2);
     E.cs = sqrt(cs2);
     const double bp = sqrt(c.by * c.by + c.bz * c.bz);
@@ -221,17 +224,18 @@ VLCT_DEV void eigen_setup(const W7 &c, double bn_in, double gam, Eigen &E)
     E.af = split ? sqrt(af2) : 1.0;
     E.as = split ? sqrt(as2) : 0.0;
     E.s = bn >= 0.0 ? 1.0 : -1.0;
-    const double ia2 = 1.0 / E.asq;
+    const double ia2 = E.ia2;
     E.nf = 0.5 * E.af * E.cf * ia2;
     E.ns = 0.5 * E.as * E.cs * ia2;
     E.qf = 0.5 * E.s * E.as * E.cs * ia2;
     E.qs = 0.5 * E.s * E.af * E.cf * ia2;
-    E.pf = 0.5 * E.af * ia2 / c.d;
-    E.ps = 0.5 * E.as * ia2 / c.d;
-    const double iasq = 1.0 / (E.a * E.sqd);
+    E.pf = 0.5 * E.af * ia2 * id;
+    E.ps = 0.5 * E.as * ia2 * id;
+    const double isqd = 1.0 / E.sqd;
+    const double iasq = isqd / E.a;      // 1 / (a sqrt(rho))
     E.bf = 0.5 * E.as * iasq;
     E.bs = -0.5 * E.af * iasq;
-    E.sr = 0.5 * E.s / E.sqd;
+    E.sr = 0.5 * E.s * isqd;
 }
 
 // characteristic amplitudes a = L dW of a primitive increment dW
@@ -251,7 +255,7 @@ VLCT_DEV void project(const Eigen &E, const double dw[7], double a[7])
     a[4] = hs + gs;
     a[1] = 0.5 * vperp + E.sr * bperp;
     a[5] = 0.5 * vperp - E.sr * bperp;
-    a[3] = dw[0] - dw[4] / E.asq;
+    a[3] = dw[0] - dw[4] * E.ia2;
 }
 
 // primitive increment dW = R a of characteristic amplitudes a
