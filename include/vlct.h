@@ -62,6 +62,8 @@ extern "C" {
 #define VLCT_RECON_PCM 1     /* first order (debugging mode of Step 2) */
 #define VLCT_RECON_PLMC 2    /* piecewise linear, limited in characteristic variables */
 #define VLCT_RECON_PPMC 3    /* piecewise parabolic, limited in characteristic variables */
+#define VLCT_RECON_PLMP 4    /* piecewise linear, limited in primitive variables */
+#define VLCT_RECON_PPMP 5    /* piecewise parabolic, limited in primitive variables */
 
 /* boundary condition per axis */
 #define VLCT_BC_PERIODIC 0

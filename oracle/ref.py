@@ -50,6 +50,8 @@ def load():
         _lib.vref_eigen.argtypes = [_DP, ctypes.c_double, ctypes.c_double, _DP, _DP, _DP]
         _lib.vref_plmc.argtypes = [_DP, ctypes.c_double, ctypes.c_double, _DP, _DP]
         _lib.vref_ppmc.argtypes = [_DP, ctypes.c_double, ctypes.c_double, _DP, _DP]
+        _lib.vref_plmp.argtypes = [_DP, _DP, _DP]
+        _lib.vref_ppmp.argtypes = [_DP, ctypes.c_double, ctypes.c_double, _DP, _DP]
         _lib.vref_ct_update.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_DP),
                                         ctypes.POINTER(_DP), _DP, _DP, _DP, ctypes.c_double]
         _lib.vref_edge_emfs.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_DP), ctypes.c_int,
@@ -204,6 +206,28 @@ def ppmc(stencil, bn, gamma):
     fm = np.zeros(7)
     fp = np.zeros(7)
     lib.vref_ppmc(_ptr(st), float(bn), float(gamma), _ptr(fm), _ptr(fp))
+    return fm, fp
+
+
+def plmp(stencil):
+    """Primitive-limited PLM: stencil (3, 7) -> (face_minus, face_plus)."""
+    lib = load()
+    st = _vec(stencil).reshape(-1)
+    assert st.size == 21
+    fm = np.zeros(7)
+    fp = np.zeros(7)
+    lib.vref_plmp(_ptr(st), _ptr(fm), _ptr(fp))
+    return fm, fp
+
+
+def ppmp(stencil, bn, gamma):
+    """Primitive-limited PPM: stencil (5, 7) -> (face_minus, face_plus)."""
+    lib = load()
+    st = _vec(stencil).reshape(-1)
+    assert st.size == 35
+    fm = np.zeros(7)
+    fp = np.zeros(7)
+    lib.vref_ppmp(_ptr(st), float(bn), float(gamma), _ptr(fm), _ptr(fp))
     return fm, fp
 
 

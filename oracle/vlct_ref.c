@@ -37,6 +37,8 @@
  *  - floors: rho and P derived from a conserved state, and reconstructed
  *    interface states, are floored at 1e-20 (the conserved state is never
  *    modified); each floor sets a status bit;
+ *  - PLMP / PPMP: the same reconstructions with the projections skipped
+ *    (limiting in the primitive variables, Step 6's closing remark);
  *  - PPMC: characteristic projection of the stencil differences (rounding-
  *    level primitive differences, below 1e-12 of the values' magnitude with
  *    c_f and sqrt(rho) c_f as floors for velocity and field, taken as zero),
@@ -428,6 +430,22 @@ void vref_plmc(const double w[21], double bn, double gamma, double face_minus[7]
     }
 }
 
+/* PLMP: the same steps with the limiter applied to the primitive slopes, i.e.
+ * skipping the projections of items 3 and 5 (Sec. 2.2 Step 6, closing remark). */
+void vref_plmp(const double w[21], double face_minus[7], double face_plus[7])
+{
+    const double *wm = w, *w0 = w + 7, *wp = w + 14;
+    for (int c = 0; c < 7; ++c) {
+        double dL = w0[c] - wm[c], dR = wp[c] - w0[c], dC = 0.5 * (wp[c] - wm[c]);
+        double dV = (dL * dR > 0.0) ? 2.0 * dL * dR / (dL + dR) : 0.0;
+        double dm = 0.0;
+        if (dL * dR > 0.0)
+            dm = sgn_pos(dC) * dmin(dmin(2.0 * fabs(dL), 2.0 * fabs(dR)), dmin(fabs(dC), fabs(dV)));
+        face_plus[c] = w0[c] + 0.5 * dm;
+        face_minus[c] = w0[c] - 0.5 * dm;
+    }
+}
+
 /* ------------------------------------------------------------------------- */
 /* PPMC: piecewise-parabolic reconstruction in characteristic variables.     */
 /* The paper gives no formulas (Sec. 2.2 Step 6 defers to Felker & Stone     */
@@ -452,12 +470,32 @@ static double ppm_face(double am, double a0, double ap, double app)
     return f;
 }
 
+static void ppm_basis(const double w[35], double bn, double gamma, int characteristic,
+                      double face_minus[7], double face_plus[7]);
+
 void vref_ppmc(const double w[35], double bn, double gamma, double face_minus[7],
                double face_plus[7])
 {
+    ppm_basis(w, bn, gamma, 1, face_minus, face_plus);
+}
+
+/* PPMP: PPM limited in the primitive variables (projections skipped). */
+void vref_ppmp(const double w[35], double bn, double gamma, double face_minus[7],
+               double face_plus[7])
+{
+    ppm_basis(w, bn, gamma, 0, face_minus, face_plus);
+}
+
+static void ppm_basis(const double w[35], double bn, double gamma, int characteristic,
+                      double face_minus[7], double face_plus[7])
+{
     const double *w0 = w + 14;
     double R[49], L[49], lam[7];
-    vref_eigen(w0, bn, gamma, R, L, lam);
+    if (characteristic) {
+        vref_eigen(w0, bn, gamma, R, L, lam);
+    } else {
+        for (int q = 0; q < 49; ++q) R[q] = L[q] = (q % 8 == 0) ? 1.0 : 0.0;
+    }
     /* characteristic values relative to the cell (the PPM steps only use
      * differences); a primitive difference within PPM_TIE of the magnitudes
      * it is taken from counts as zero, so rounding noise at a symmetric
@@ -694,7 +732,7 @@ static void step_cell(int d, int *i, int *j, int *k, int s)
 static uint32_t stage_fluxes(const pgrid *g, int d, int recon, double gamma, double *F[8])
 {
     const int *n = g->n;
-    int r = recon == 1 ? 0 : (recon == 2 ? 1 : 2);
+    int r = recon == 1 ? 0 : ((recon == 2 || recon == 4) ? 1 : 2);
     size_t nc = ncell_padded(g);
     /* per-cell interface states: minus = low face, plus = high face */
     double *wm[7], *wp[7];
@@ -722,10 +760,14 @@ static uint32_t stage_fluxes(const pgrid *g, int d, int recon, double gamma, dou
                 if (r == 0) {
                     memcpy(fm, sten, sizeof(fm));
                     memcpy(fp, sten, sizeof(fp));
-                } else if (r == 1) {
+                } else if (recon == 2) {
                     vref_plmc(sten, bn_cc, gamma, fm, fp);
-                } else {
+                } else if (recon == 4) {
+                    vref_plmp(sten, fm, fp);
+                } else if (recon == 3) {
                     vref_ppmc(sten, bn_cc, gamma, fm, fp);
+                } else {
+                    vref_ppmp(sten, bn_cc, gamma, fm, fp);
                 }
                 /* floors on reconstructed interface states */
                 if (!(fm[0] >= FLOOR_RHO)) { fm[0] = FLOOR_RHO; st |= VREF_STATUS_DENSITY_FLOOR; }
@@ -1004,7 +1046,7 @@ static int grid_ok(const vref_grid *g)
     if (!(g->dx > 0.0) || !(g->dy > 0.0) || !(g->dz > 0.0)) return 0;
     if (!(g->gamma > 1.0)) return 0;
     if (!(g->cfl > 0.0 && g->cfl <= 0.5)) return 0;
-    if (g->recon < 1 || g->recon > 3) return 0;
+    if (g->recon < 1 || g->recon > 5) return 0;
     for (int d = 0; d < 3; ++d)
         if (g->bc[d] != 0 && g->bc[d] != 1) return 0;
     return 1;
@@ -1137,7 +1179,7 @@ int vref_step(const vref_grid *vg, const double *const in[8], double *const out[
 int vref_edge_emfs(const vref_grid *vg, const double *const st[8], int recon, double *ex,
                    double *ey, double *ez, int nthreads)
 {
-    if (!grid_ok(vg) || !st || recon < 1 || recon > 3) return VREF_EINVAL;
+    if (!grid_ok(vg) || !st || recon < 1 || recon > 5) return VREF_EINVAL;
     set_threads(nthreads);
     pgrid g;
     stage_buf s;
@@ -1206,7 +1248,7 @@ int vref_half_step(const vref_grid *vg, const double *const in[8], double *const
 int vref_stage_fluxes(const vref_grid *vg, const double *const st[8], int recon,
                       double *const Fx[8], double *const Fy[8], double *const Fz[8], int nthreads)
 {
-    if (!grid_ok(vg) || !st || recon < 1 || recon > 3) return VREF_EINVAL;
+    if (!grid_ok(vg) || !st || recon < 1 || recon > 5) return VREF_EINVAL;
     set_threads(nthreads);
     pgrid g;
     stage_buf s;

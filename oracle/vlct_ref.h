@@ -28,7 +28,7 @@ typedef struct {
     double dx, dy, dz;    /* cell widths, > 0 */
     double gamma;         /* adiabatic index, > 1 */
     double cfl;           /* Courant number in (0, 0.5] */
-    int32_t recon;        /* 1 = PCM, 2 = PLMC, 3 = PPMC (corrector reconstruction) */
+    int32_t recon;        /* corrector reconstruction: 1 PCM, 2 PLMC, 3 PPMC, 4 PLMP, 5 PPMP */
     int32_t bc[3];        /* per axis: 0 = periodic, 1 = outflow (zero gradient) */
 } vref_grid;
 
@@ -77,6 +77,10 @@ void vref_eigen(const double w[7], double bn, double gamma, double R[49], double
 void vref_plmc(const double w[21], double bn, double gamma, double face_minus[7],
                double face_plus[7]);
 void vref_ppmc(const double w[35], double bn, double gamma, double face_minus[7],
+               double face_plus[7]);
+/* primitive-variable limiting: the same steps without the characteristic projections */
+void vref_plmp(const double w[21], double face_minus[7], double face_plus[7]);
+void vref_ppmp(const double w[35], double bn, double gamma, double face_minus[7],
                double face_plus[7]);
 
 /* Conservative face update of B from edge EMFs (Sec. 2.2 Step 5/9 CT update):

@@ -68,10 +68,10 @@ int main()
         const double bn = 1.1 + 0.2 * nrm(rng);
         vlct::W7 fm, fp;
         long long f0 = g_flops;
-        vlct::plmc(m1, c, p1, Counted(bn), Counted(gam), fm, fp);
+        vlct::plmc<true>(m1, c, p1, Counted(bn), Counted(gam), fm, fp);
         plmc_f += g_flops - f0;
         f0 = g_flops;
-        vlct::ppmc(m2, m1, c, p1, p2, Counted(bn), Counted(gam), fm, fp);
+        vlct::ppmc<true>(m2, m1, c, p1, p2, Counted(bn), Counted(gam), fm, fp);
         ppmc_f += g_flops - f0;
         Counted f[7], upw;
         f0 = g_flops;

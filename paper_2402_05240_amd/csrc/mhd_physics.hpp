@@ -300,9 +300,11 @@ VLCT_DEV uint32_t floor_state(W7 &w)
 // primitive differences projected with the eigenvectors of the cell,
 // limited, projected back; fm = state at the low face, fp = at the high face.
 // ---------------------------------------------------------------------------
+template <bool CHAR>
 VLCT_DEV void plmc(const W7 &wm, const W7 &w0, const W7 &wp, double bn,
                                      double gam, W7 &fm, W7 &fp)
 {
+    // CHAR = false is PLMP: the same steps with the projections skipped
     double xm[7], x0[7], xp[7];
     to_arr(wm, xm);
     to_arr(w0, x0);
@@ -317,12 +319,22 @@ VLCT_DEV void plmc(const W7 &wm, const W7 &w0, const W7 &wp, double bn,
         dv[c] = pr > 0.0 ? 2.0 * pr / (dl[c] + dr[c]) : 0.0;
     }
     Eigen E;
-    eigen_setup(w0, bn, gam, E);
     double al[7], ar[7], ac[7], av[7], am[7];
-    project(E, dl, al);
-    project(E, dr, ar);
-    project(E, dc, ac);
-    project(E, dv, av);
+    if (CHAR) {
+        eigen_setup(w0, bn, gam, E);
+        project(E, dl, al);
+        project(E, dr, ar);
+        project(E, dc, ac);
+        project(E, dv, av);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            al[c] = dl[c];
+            ar[c] = dr[c];
+            ac[c] = dc[c];
+            av[c] = dv[c];
+        }
+    }
 #pragma unroll
     for (int m = 0; m < 7; ++m) {
         const double lim = fmin(fmin(2.0 * fabs(al[m]), 2.0 * fabs(ar[m])),
@@ -330,7 +342,12 @@ VLCT_DEV void plmc(const W7 &wm, const W7 &w0, const W7 &wp, double bn,
         am[m] = al[m] * ar[m] > 0.0 ? copysign(lim, ac[m]) : 0.0;
     }
     double dw[7];
-    unproject(E, am, dw);
+    if (CHAR) {
+        unproject(E, am, dw);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) dw[c] = am[c];
+    }
     double p[7], q[7];
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
@@ -365,16 +382,25 @@ VLCT_DEV double ppm_face(double am, double a0, double ap, double app)
     return f;
 }
 
+template <bool CHAR>
 VLCT_DEV void ppmc(const W7 &wmm, const W7 &wm, const W7 &w0, const W7 &wp,
                                      const W7 &wpp, double bn, double gam, W7 &fm, W7 &fp)
 {
+    // CHAR = false is PPMP: the same steps with the projections skipped
     // stencil differences relative to the cell; a difference within kPpmTie of
     // the magnitudes it is taken from counts as zero, so that rounding noise at
     // a symmetric extremum cannot pick the other branch of the extremum test
     Eigen E;
-    eigen_setup(w0, bn, gam, E);
+    double fv, fb;
+    if (CHAR) {
+        eigen_setup(w0, bn, gam, E);
+        fv = E.cf;
+        fb = E.sqd * E.cf;
+    } else {
+        fv = fast_speed(w0.d, w0.p, bn, w0.by, w0.bz, gam);
+        fb = sqrt(w0.d) * fv;
+    }
     // magnitude floors of the tie test: c_f for velocities, sqrt(rho) c_f for B
-    const double fv = E.cf, fb = E.sqd * E.cf;
     const double floor_c[7] = {0.0, fv, fv, fv, 0.0, fb, fb};
     double x0[7], xs[4][7];
     to_arr(w0, x0);
@@ -393,7 +419,14 @@ VLCT_DEV void ppmc(const W7 &wmm, const W7 &wm, const W7 &w0, const W7 &wp,
     }
     double a[4][7];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) project(E, xs[s], a[s]);
+    for (int s = 0; s < 4; ++s) {
+        if (CHAR) {
+            project(E, xs[s], a[s]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 7; ++c) a[s][c] = xs[s][c];
+        }
+    }
     double dplus[7], dminus[7];
 #pragma unroll
     for (int m = 0; m < 7; ++m) {
@@ -423,8 +456,16 @@ VLCT_DEV void ppmc(const W7 &wmm, const W7 &wm, const W7 &w0, const W7 &wp,
         dminus[m] = -dm;
     }
     double wpl[7], wmi[7];
-    unproject(E, dplus, wpl);
-    unproject(E, dminus, wmi);
+    if (CHAR) {
+        unproject(E, dplus, wpl);
+        unproject(E, dminus, wmi);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            wpl[c] = dplus[c];
+            wmi[c] = dminus[c];
+        }
+    }
     double xl[7], xr[7], p[7], q[7];
     to_arr(wm, xl);
     to_arr(wp, xr);

@@ -169,7 +169,7 @@ __device__ __forceinline__ W7 load_w7(const Prims &P, idx_t o)
 }
 
 // ---------------------------------------------------------------------------
-// interface states + HLLD on every face of axis D (Steps 2-3 and 6-7)
+// PCM interface states + HLLD on every face of axis D (Steps 2-3)
 // ---------------------------------------------------------------------------
 template <int D, int RECON>
 __global__ void __launch_bounds__(kBlock) k_flux(Geom g, StateP s, Prims P, Flux F,
@@ -189,31 +189,10 @@ __global__ void __launch_bounds__(kBlock) k_flux(Geom g, StateP s, Prims P, Flux
         c[D] += off;
         return pidx(g, c[0], c[1], c[2]);
     };
-    W7 wl, wr;
-    uint32_t st = 0;
-    if (RECON == VLCT_RECON_PCM) {
-        wl = load_w7<D>(P, cell_at(-1));
-        wr = load_w7<D>(P, cell_at(0));
-    } else if (RECON == VLCT_RECON_PLMC) {
-        const idx_t cm2 = cell_at(-2), cm1 = cell_at(-1), c0 = cell_at(0), cp1 = cell_at(1);
-        const W7 a = load_w7<D>(P, cm2), b = load_w7<D>(P, cm1), c = load_w7<D>(P, c0),
-                 e = load_w7<D>(P, cp1);
-        W7 dummy;
-        plmc(a, b, c, P.w[5 + D][cm1], g.gamma, dummy, wl);
-        plmc(b, c, e, P.w[5 + D][c0], g.gamma, wr, dummy);
-        st |= floor_state(wl);
-        st |= floor_state(wr);
-    } else {
-        const idx_t cm3 = cell_at(-3), cm2 = cell_at(-2), cm1 = cell_at(-1), c0 = cell_at(0),
-                    cp1 = cell_at(1), cp2 = cell_at(2);
-        const W7 a = load_w7<D>(P, cm3), b = load_w7<D>(P, cm2), c = load_w7<D>(P, cm1),
-                 e = load_w7<D>(P, c0), h = load_w7<D>(P, cp1), q = load_w7<D>(P, cp2);
-        W7 dummy;
-        ppmc(a, b, c, e, h, P.w[5 + D][cm1], g.gamma, dummy, wl);
-        ppmc(b, c, e, h, q, P.w[5 + D][c0], g.gamma, wr, dummy);
-        st |= floor_state(wl);
-        st |= floor_state(wr);
-    }
+    static_assert(RECON == VLCT_RECON_PCM, "k_flux serves the PCM predictor");
+    const W7 wl = load_w7<D>(P, cell_at(-1));
+    const W7 wr = load_w7<D>(P, cell_at(0));
+    const uint32_t st = 0;
     // stored normal field of this face (transverse indices mapped like cells)
     int m[3];
 #pragma unroll
@@ -251,12 +230,15 @@ __device__ __forceinline__ void recon_cell(const Prims &P, const Geom &g, int D,
     };
     const idx_t c0 = at(0);
     const double bn = P.w[5 + D][c0];
+    constexpr bool kChar = RECON == VLCT_RECON_PLMC || RECON == VLCT_RECON_PPMC;
+    constexpr bool kLinear = RECON == VLCT_RECON_PLMC || RECON == VLCT_RECON_PLMP;
     if (D == 0) {
-        if (RECON == VLCT_RECON_PLMC)
-            plmc(load_w7<0>(P, at(-1)), load_w7<0>(P, c0), load_w7<0>(P, at(1)), bn, g.gamma, fm, fp);
+        if (kLinear)
+            plmc<kChar>(load_w7<0>(P, at(-1)), load_w7<0>(P, c0), load_w7<0>(P, at(1)), bn,
+                        g.gamma, fm, fp);
         else
-            ppmc(load_w7<0>(P, at(-2)), load_w7<0>(P, at(-1)), load_w7<0>(P, c0),
-                 load_w7<0>(P, at(1)), load_w7<0>(P, at(2)), bn, g.gamma, fm, fp);
+            ppmc<kChar>(load_w7<0>(P, at(-2)), load_w7<0>(P, at(-1)), load_w7<0>(P, c0),
+                        load_w7<0>(P, at(1)), load_w7<0>(P, at(2)), bn, g.gamma, fm, fp);
     }
 }
 
@@ -319,7 +301,8 @@ __global__ void __launch_bounds__(kBlock) k_flux_recon_march(Geom g, StateP s, P
                                                               uint32_t *status)
 {
     constexpr int T = D == 1 ? 2 : 1;         // the transverse axis other than x
-    constexpr int R = RECON == VLCT_RECON_PLMC ? 1 : 2;
+    constexpr bool kChar = RECON == VLCT_RECON_PLMC || RECON == VLCT_RECON_PPMC;
+    constexpr int R = (RECON == VLCT_RECON_PLMC || RECON == VLCT_RECON_PLMP) ? 1 : 2;
     const int nD = g.n[D];
     // columns (i, it), i in [-1, nx], it in [-1, n_T], flattened with i fastest
     const idx_t cols = (idx_t)(g.n[0] + 2) * (g.n[T] + 2);
@@ -356,10 +339,10 @@ __global__ void __launch_bounds__(kBlock) k_flux_recon_march(Geom g, StateP s, P
     const int mi = map_cell(i, g.n[0], g.bc[0]);
     for (int c = s0 - 1; c < s1; ++c) {
         W7 fm, fp;
-        if (RECON == VLCT_RECON_PLMC)
-            plmc(win[0], win[1], win[2], bnc[1], g.gamma, fm, fp);
+        if (R == 1)
+            plmc<kChar>(win[0], win[1], win[2], bnc[1], g.gamma, fm, fp);
         else
-            ppmc(win[0], win[1], win[2], win[3], win[4], bnc[2], g.gamma, fm, fp);
+            ppmc<kChar>(win[0], win[1], win[2], win[3], win[4], bnc[2], g.gamma, fm, fp);
         st |= floor_state(fm);
         st |= floor_state(fp);
         if (c >= s0) {
@@ -658,8 +641,7 @@ static bool grid_ok(const vlct_grid *g)
     }
     if (!(g->dx > 0.0) || !(g->dy > 0.0) || !(g->dz > 0.0)) return false;
     if (!(g->gamma > 1.0) || !(g->cfl > 0.0 && g->cfl <= 0.5)) return false;
-    if (g->recon != VLCT_RECON_PCM && g->recon != VLCT_RECON_PLMC && g->recon != VLCT_RECON_PPMC)
-        return false;
+    if (g->recon < VLCT_RECON_PCM || g->recon > VLCT_RECON_PPMP) return false;
     return true;
 }
 
@@ -827,15 +809,19 @@ static int launch_stage_fluxes(const Geom &g, const StateP &st, const Bound &B, 
             const size_t cols = (size_t)(g.n[0] + 2) * (g.n[T] + 2);
             return xcd_grid(((cols + kBlock - 1) / kBlock) * ((g.n[D] + 1 + kMarch - 1) / kMarch));
         };
-        if (recon == VLCT_RECON_PLMC) {
-            { Observe o(kid, s); k_flux_recon_x<VLCT_RECON_PLMC><<<gx, kBlock, 0, s>>>(g, st, B.P, B.F, status); }
-            { Observe o(kid, s); k_flux_recon_march<1, VLCT_RECON_PLMC><<<march_grid(1), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
-            { Observe o(kid, s); k_flux_recon_march<2, VLCT_RECON_PLMC><<<march_grid(2), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
-        } else {
-            { Observe o(kid, s); k_flux_recon_x<VLCT_RECON_PPMC><<<gx, kBlock, 0, s>>>(g, st, B.P, B.F, status); }
-            { Observe o(kid, s); k_flux_recon_march<1, VLCT_RECON_PPMC><<<march_grid(1), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
-            { Observe o(kid, s); k_flux_recon_march<2, VLCT_RECON_PPMC><<<march_grid(2), kBlock, 0, s>>>(g, st, B.P, B.F, status); }
+#define VLCT_RECON3(R)                                                                        \
+    {                                                                                         \
+        { Observe o(kid, s); k_flux_recon_x<R><<<gx, kBlock, 0, s>>>(g, st, B.P, B.F, status); } \
+        { Observe o(kid, s); k_flux_recon_march<1, R><<<march_grid(1), kBlock, 0, s>>>(g, st, B.P, B.F, status); } \
+        { Observe o(kid, s); k_flux_recon_march<2, R><<<march_grid(2), kBlock, 0, s>>>(g, st, B.P, B.F, status); } \
+    }
+        switch (recon) {
+        case VLCT_RECON_PLMC: VLCT_RECON3(VLCT_RECON_PLMC) break;
+        case VLCT_RECON_PPMC: VLCT_RECON3(VLCT_RECON_PPMC) break;
+        case VLCT_RECON_PLMP: VLCT_RECON3(VLCT_RECON_PLMP) break;
+        default: VLCT_RECON3(VLCT_RECON_PPMP) break;
         }
+#undef VLCT_RECON3
     }
 #undef VLCT_FLUX
     return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;

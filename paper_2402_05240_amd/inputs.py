@@ -31,6 +31,8 @@ FIELDS = ("rho", "mx", "my", "mz", "E", "bx", "by", "bz")
 RECON_PCM = 1
 RECON_PLMC = 2
 RECON_PPMC = 3
+RECON_PLMP = 4
+RECON_PPMP = 5
 BC_PERIODIC = 0
 BC_OUTFLOW = 1
 

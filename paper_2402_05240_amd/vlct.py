@@ -20,6 +20,8 @@ VLCT_EUNSUPPORTED = 4
 VLCT_RECON_PCM = 1
 VLCT_RECON_PLMC = 2
 VLCT_RECON_PPMC = 3
+VLCT_RECON_PLMP = 4
+VLCT_RECON_PPMP = 5
 VLCT_BC_PERIODIC = 0
 VLCT_BC_OUTFLOW = 1
 VLCT_STATUS_PRESSURE_FLOOR = 1

@@ -44,7 +44,7 @@ def _grid(**kw):
 
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-3), dict(nz=5000), dict(dx=0.0), dict(dy=-1.0),
                                  dict(dz=float("nan")), dict(gamma=1.0), dict(cfl=0.0), dict(cfl=0.6),
-                                 dict(recon=0), dict(recon=4), dict(bc=(0, 2, 0))])
+                                 dict(recon=0), dict(recon=6), dict(bc=(0, 2, 0))])
 def test_invalid_grid_rejected(bad):
     _lib()
     g = _grid(**bad)

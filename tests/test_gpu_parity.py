@@ -85,7 +85,7 @@ def _check(g, s0, gpu, orc, rel=REL_L1, elem=1e-10):
 
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("recon", [1, 2, 3])
+@pytest.mark.parametrize("recon", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("bc", [(0, 0, 0), (1, 0, 1)])
 def test_uniform_state_bit_exact_gpu(recon, bc):
     _need_gpu()
@@ -132,7 +132,7 @@ def test_linear_fast_wave_32_one_period():
     assert abs(e_gpu - e_ref) <= 1e-6 * e_ref
 
 
-@pytest.mark.parametrize("recon,nsteps", [(2, 100), (3, 40), (1, 20)])
+@pytest.mark.parametrize("recon,nsteps", [(2, 100), (3, 40), (1, 20), (4, 30), (5, 30)])
 def test_turbulence_multi_step(recon, nsteps):
     """Decaying turbulence on a ragged grid (not a multiple of the block size)."""
     _need_gpu()
@@ -148,7 +148,7 @@ def test_turbulence_multi_step(recon, nsteps):
     assert abs(nexts[-1] - nexts_ref[-1]) <= 1e-12 * nexts_ref[-1]
 
 
-@pytest.mark.parametrize("recon", [2, 3])
+@pytest.mark.parametrize("recon", [2, 3, 5])
 def test_blast_outflow_multi_step(recon):
     """Magnetised blast wave (beta = 0.2) with outflow boundaries on all faces."""
     _need_gpu()

@@ -24,7 +24,7 @@ def _close_state(a, b, rtol):
 # uniform states, conservation, div B
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("recon", [1, 2, 3])
+@pytest.mark.parametrize("recon", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("bc", [(0, 0, 0), (1, 0, 1), (1, 1, 1)])
 def test_uniform_state_bit_exact(recon, bc):
     rng = np.random.default_rng(100 + recon)
@@ -216,6 +216,9 @@ def test_linear_wave_second_order_convergence():
     assert e64 < 1.5e-8
     p32 = err(32, 3)
     assert p32 < 0.7 * e32
+    # primitive-variable limiting converges at second order as well
+    q32, q64 = err(32, 4), err(64, 4)
+    assert math.log2(q32 / q64) > 1.8
 
 
 def _l2_of_l1(s, s0):

@@ -423,3 +423,44 @@ def test_ppmc_step_data_creates_no_new_extrema():
         lo = sten.min(axis=0) - 1e-13 * np.abs(sten).max(axis=0)
         hi = sten.max(axis=0) + 1e-13 * np.abs(sten).max(axis=0)
         assert np.all(fm >= lo) and np.all(fm <= hi) and np.all(fp >= lo) and np.all(fp <= hi)
+
+
+# ---------------------------------------------------------------------------
+# primitive-variable limiting (Sec. 2.2 Step 6: skip the projections)
+# ---------------------------------------------------------------------------
+
+def test_plmp_componentwise_limiter():
+    """PLMP applies Eq. limiter to each primitive component."""
+    rng = np.random.default_rng(14)
+    for _ in range(200):
+        W, _ = _cell_state(rng)
+        dl = rng.normal(0, 0.05, 7)
+        ratio = rng.choice([-1.0, 0.0, 0.5, 1.0, 3.0, 10.0], 7)
+        Wm, Wp = W - dl, W + dl * ratio
+        fm, fp = ref.plmp(np.stack([Wm, W, Wp]))
+        for c in range(7):
+            a, b = dl[c], dl[c] * ratio[c]
+            if a * b > 0:
+                vl = 2 * a * b / (a + b)
+                m = np.sign(0.5 * (a + b)) * min(2 * abs(a), 2 * abs(b), abs(0.5 * (a + b)), abs(vl))
+            else:
+                m = 0.0
+            assert abs(fp[c] - (W[c] + 0.5 * m)) <= 1e-14 * (abs(W[c]) + 1)
+            assert abs(fm[c] - (W[c] - 0.5 * m)) <= 1e-14 * (abs(W[c]) + 1)
+
+
+def test_ppmp_exact_for_cubic_cell_averages_and_bounded():
+    rng = np.random.default_rng(15)
+    for _ in range(30):
+        W, bn = _cell_state(rng)
+        c = rng.normal(0, 1, 4) * np.array([1e-3, 1e-3, 1e-5, 1e-6])
+        c[1] = abs(c[1]) + 2e-3
+        P = lambda x: c[0] * x + c[1] * x * x / 2 + c[2] * x ** 3 / 3 + c[3] * x ** 4 / 4
+        avg = lambda i: P(i + 0.5) - P(i - 0.5)
+        p = lambda x: c[0] + c[1] * x + c[2] * x * x + c[3] * x ** 3
+        d = rng.normal(0, 1, 7)     # the same profile in every primitive, scaled by d
+        sten = np.stack([W + (avg(i) - avg(0)) * d for i in range(-2, 3)])
+        fm, fp = ref.ppmp(sten, bn, GAM)
+        tol = 1e-12 * np.abs(W).max()
+        assert np.abs(fp - (W + (p(0.5) - avg(0)) * d)).max() <= tol
+        assert np.abs(fm - (W + (p(-0.5) - avg(0)) * d)).max() <= tol
