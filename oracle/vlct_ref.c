@@ -545,19 +545,39 @@ static void ppm_basis(const double w[35], double bn, double gamma, int character
             if (fabs(dp) >= 2.0 * fabs(dm)) dp = 2.0 * dm;
             if (fabs(dm) >= 2.0 * fabs(dp)) dm = 2.0 * dp;
         }
-        dplus[m] = dp;
-        dminus[m] = -dm;
+        /* the limited interface values stay between the cell's and the
+         * neighbour's characteristic values */
+        double ar = dmax(dmin(a0, a1), dmin(a0 + dp, dmax(a0, a1)));
+        double al = dmax(dmin(a0, a_1), dmin(a0 - dm, dmax(a0, a_1)));
+        dplus[m] = ar - a0;
+        dminus[m] = al - a0;
     }
     double wp[7], wm[7];
     matvec7(R, dplus, wp);
     matvec7(R, dminus, wm);
     const double *wl = w + 7, *wr = w + 21;
     for (int c = 0; c < 7; ++c) {
-        double fp = w0[c] + wp[c];
-        double fm = w0[c] + wm[c];
-        /* clamp interface primitives between the neighbouring cell values */
-        fp = dmax(dmin(w0[c], wr[c]), dmin(fp, dmax(w0[c], wr[c])));
-        fm = dmax(dmin(w0[c], wl[c]), dmin(fm, dmax(w0[c], wl[c])));
+        double fp0 = w0[c] + wp[c];
+        double fm0 = w0[c] + wm[c];
+        /* bound the interface primitives between the neighbouring cell values */
+        double fp = dmax(dmin(w0[c], wr[c]), dmin(fp0, dmax(w0[c], wr[c])));
+        double fm = dmax(dmin(w0[c], wl[c]), dmin(fm0, dmax(w0[c], wl[c])));
+        /* a bound that had to act (beyond rounding) marks a profile the
+         * characteristic limiting did not keep monotone in this primitive:
+         * its interface pair gets the Colella-Woodward monotonicity
+         * constraints (flat at an extremum, otherwise the face beyond twice
+         * the other's distance from the cell value is pulled back to it) */
+        double tol = PPM_TIE * (fabs(w0[c]) + fabs(wl[c]) + fabs(wr[c]) + floor_c[c]);
+        if (fabs(fp - fp0) > tol || fabs(fm - fm0) > tol) {
+            double dpp = fp - w0[c], dmm = w0[c] - fm;
+            if (dpp * dmm <= 0.0) {
+                fp = w0[c];
+                fm = w0[c];
+            } else {
+                if (fabs(dpp) >= 2.0 * fabs(dmm)) fp = w0[c] + 2.0 * dmm;
+                if (fabs(dmm) >= 2.0 * fabs(dpp)) fm = w0[c] - 2.0 * dpp;
+            }
+        }
         face_plus[c] = fp;
         face_minus[c] = fm;
     }

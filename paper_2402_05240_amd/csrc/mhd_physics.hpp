@@ -452,8 +452,10 @@ VLCT_DEV void ppmc(const W7 &wmm, const W7 &wm, const W7 &w0, const W7 &wp,
             if (fabs(dp) >= 2.0 * fabs(dm)) dp = 2.0 * dm;
             if (fabs(dm) >= 2.0 * fabs(dp)) dm = 2.0 * dp;
         }
-        dplus[m] = dp;
-        dminus[m] = -dm;
+        // the limited interface values stay between the cell's (0) and the
+        // neighbour's characteristic values
+        dplus[m] = fmax(fmin(0.0, a1), fmin(dp, fmax(0.0, a1)));
+        dminus[m] = fmax(fmin(0.0, a_1), fmin(-dm, fmax(0.0, a_1)));
     }
     double wpl[7], wmi[7];
     if (CHAR) {
@@ -473,8 +475,24 @@ VLCT_DEV void ppmc(const W7 &wmm, const W7 &wm, const W7 &w0, const W7 &wp,
     for (int c = 0; c < 7; ++c) {
         const double up = x0[c] + wpl[c];
         const double um = x0[c] + wmi[c];
-        p[c] = fmax(fmin(x0[c], xr[c]), fmin(up, fmax(x0[c], xr[c])));
-        q[c] = fmax(fmin(x0[c], xl[c]), fmin(um, fmax(x0[c], xl[c])));
+        // bound between the neighbouring cell values
+        double vp = fmax(fmin(x0[c], xr[c]), fmin(up, fmax(x0[c], xr[c])));
+        double vm = fmax(fmin(x0[c], xl[c]), fmin(um, fmax(x0[c], xl[c])));
+        // a bound that acted beyond rounding: Colella-Woodward monotonicity
+        // constraints on this primitive's interface pair
+        const double tol = kPpmTie * (fabs(x0[c]) + fabs(xl[c]) + fabs(xr[c]) + floor_c[c]);
+        if (fabs(vp - up) > tol || fabs(vm - um) > tol) {
+            const double dpp = vp - x0[c], dmm = x0[c] - vm;
+            if (dpp * dmm <= 0.0) {
+                vp = x0[c];
+                vm = x0[c];
+            } else {
+                if (fabs(dpp) >= 2.0 * fabs(dmm)) vp = x0[c] + 2.0 * dmm;
+                if (fabs(dmm) >= 2.0 * fabs(dpp)) vm = x0[c] - 2.0 * dpp;
+            }
+        }
+        p[c] = vp;
+        q[c] = vm;
     }
     fp = from_arr(p);
     fm = from_arr(q);

@@ -466,6 +466,55 @@ def blast(n=(512, 512, 512), gamma=5.0 / 3.0, p_in=10.0, p_out=0.1, r0=0.1,
 
 
 # --------------------------------------------------------------------------
+# MHD Riemann problems (Sec. 3.1.4, Table "Riemann Problem Initial Conditions")
+# --------------------------------------------------------------------------
+
+def riemann(left, right, bn, gamma, n=128, axis=0, flip=False, transverse=4,
+            recon=RECON_PPMC, cfl=0.4) -> Tuple[Grid, State]:
+    """A 1D Riemann problem on the unit box along `axis` with the interface at
+    the middle and outflow boundaries along it (periodic across).  `left` and
+    `right` are sweep-frame primitives (rho, P, v_n, v_t1, v_t2, B_t1, B_t2); B_n
+    is the same on both sides.  flip=True mirrors the problem (states swapped,
+    normal vector components negated)."""
+    L = np.array(left, dtype=float)
+    R = np.array(right, dtype=float)
+    if flip:
+        L, R = R.copy(), L.copy()
+        L[2] = -L[2]
+        R[2] = -R[2]
+        bn = -bn
+    shape = [transverse, transverse, transverse]
+    shape[axis] = n
+    nx, ny, nz = shape
+    bc = [BC_PERIODIC] * 3
+    bc[axis] = BC_OUTFLOW
+    g = Grid(nx, ny, nz, 1.0 / nx, 1.0 / ny, 1.0 / nz, gamma, cfl, recon, tuple(bc))
+    xc = (np.arange(n) + 0.5) / n
+    left_side = xc < 0.5
+    prof = np.where(left_side[:, None], L[None, :], R[None, :])   # (n, 7)
+    t1, t2 = (axis + 1) % 3, (axis + 2) % 3
+    s = empty_state(g)
+
+    def along(vals, shp):
+        sh = [1, 1, 1]
+        sh[2 - axis] = len(vals)
+        return np.broadcast_to(vals.reshape(sh), shp).copy()
+    rho, p = prof[:, 0], prof[:, 1]
+    vel = {axis: prof[:, 2], t1: prof[:, 3], t2: prof[:, 4]}
+    bt = {t1: prof[:, 5], t2: prof[:, 6]}
+    s["rho"] = along(rho, g.shape)
+    for d, name in enumerate(("mx", "my", "mz")):
+        s[name] = along(rho * vel[d], g.shape)
+    for d, name in enumerate(("bx", "by", "bz")):
+        fs = g.field_shape(name)
+        s[name] = np.full(fs, bn) if d == axis else along(bt[d], fs)
+    ke = 0.5 * rho * (prof[:, 2] ** 2 + prof[:, 3] ** 2 + prof[:, 4] ** 2)
+    me = 0.5 * (bn * bn + prof[:, 5] ** 2 + prof[:, 6] ** 2)
+    s["E"] = along(p / (gamma - 1.0) + ke + me, g.shape)
+    return g, s
+
+
+# --------------------------------------------------------------------------
 # named workloads
 # --------------------------------------------------------------------------
 

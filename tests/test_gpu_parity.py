@@ -14,6 +14,7 @@ import pytest
 
 from oracle import ref
 from paper_2402_05240_amd import inputs as I
+from riemann_table import riemann_row
 from parity_util import (FIELDS, WINDOW_HALF, cell_values, gpu_available, max_abs_over_scale,
                          rel_l1, scales, window)
 
@@ -155,6 +156,25 @@ def test_blast_outflow_multi_step(recon):
     g, s0 = I.blast((26, 23, 20), b0=1.0, recon=recon)
     _say("oracle: blast recon %d" % recon)
     orc, dts, _, st_ref = _oracle_run(g, s0, nsteps=10)
+    gpu, _, status = _gpu_run(g, s0, dts)
+    assert status == st_ref == 0
+    _check(g, s0, gpu, orc, elem=1e-9)
+
+
+@pytest.mark.parametrize("name,axis,flip,recon", [
+    ("brio_wu", 1, True, 3), ("einfeldt", 2, False, 3), ("dai_woodward", 0, False, 3),
+    ("ryu_jones_4d", 0, True, 5), ("ryu_jones_1a", 2, True, 2)])
+def test_riemann_problem_to_tmax(name, axis, flip, recon):
+    """The MHD Riemann problems of Sec. 3.1.4 run to t_max: shocks, a
+    near-vacuum rarefaction and outflow boundaries along one axis (periodic
+    across), with the oracle's dt sequence."""
+    _need_gpu()
+    row = riemann_row(name)
+    g, s0 = I.riemann(row["left"], row["right"], row["bx"], row["gamma"], n=128, axis=axis,
+                      flip=flip, transverse=4, recon=recon)
+    _say("oracle: %s axis %d flip %s recon %d" % (name, axis, flip, recon))
+    orc, dts, _, st_ref = _oracle_run(g, s0, t_end=row["tmax"])
+    _say("gpu: %d steps" % len(dts))
     gpu, _, status = _gpu_run(g, s0, dts)
     assert status == st_ref == 0
     _check(g, s0, gpu, orc, elem=1e-9)

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import ref
+from riemann_table import riemann_table
 from paper_2402_05240_amd.inputs import primitive_jacobian
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -287,26 +288,14 @@ def test_hlld_transverse_rotation_covariance():
         assert np.abs(g - fr).max() <= 1e-12 * (np.abs(f).max() + 1.0)
 
 
-def _riemann_table():
-    s4pi = math.sqrt(4 * math.pi)
-    rows = []
-    with open(os.path.join(HERE, "golden", "riemann_problems.txt")) as f:
-        for line in f:
-            if line.startswith("#") or not line.strip():
-                continue
-            tok = line.split()
-            vals = [eval(t, {"s4pi": s4pi}) for t in tok[1:]]  # noqa: S307 (fixture arithmetic)
-            rows.append((tok[0], vals))
-    return rows
-
-
 def test_hlld_riemann_table_states_are_physical():
     """Every left/right pair of the paper's Riemann table gives a finite flux
     that equals the physical flux of either state when both are equal."""
-    for name, v in _riemann_table():
-        gam, bx = v[0], v[2]
-        Wl = np.array([v[3], v[5], v[6], v[7], v[4], v[8], v[9]])
-        Wr = np.array([v[10], v[12], v[13], v[14], v[11], v[15], v[16]])
+    for name, v in riemann_table():
+        gam, bx = v["gamma"], v["bx"]
+        (dl, pl, ul, vl, wl, byl, bzl), (dr, pr, ur, vr, wr, byr, bzr) = v["left"], v["right"]
+        Wl = np.array([dl, ul, vl, wl, pl, byl, bzl])
+        Wr = np.array([dr, ur, vr, wr, pr, byr, bzr])
         f = ref.hlld(Wl, Wr, bx, gam)
         assert np.all(np.isfinite(f)), name
         assert np.allclose(ref.hlld(Wl, Wl, bx, gam), ref.phys_flux(Wl, bx, gam), rtol=1e-13, atol=1e-13)
