@@ -269,10 +269,14 @@ void vref_eigen(const double w[7], double bn, double gamma, double R[49], double
 {
     double rho = w[0], u = w[1], p = w[4], by = w[5], bz = w[6];
     /* field components below 1e-12 of the magnetosonic scale sqrt(gP + B^2)
-     * are rounding noise: B_n below it is zero, and a B_perp below it takes
-     * the degenerate-direction convention */
+     * are rounding noise: each such component (B_n, B_t1, B_t2) is zero, so
+     * that noise cannot turn the B_perp direction and with it a projection
+     * that is exactly zero into a tiny one of either sign; a B_perp below it
+     * takes the degenerate-direction convention */
     double bscale = sqrt(gamma * p + bn * bn + by * by + bz * bz);
     if (fabs(bn) <= BPERP_TINY * bscale) bn = 0.0;
+    if (fabs(by) <= BPERP_TINY * bscale) by = 0.0;
+    if (fabs(bz) <= BPERP_TINY * bscale) bz = 0.0;
     double a2 = gamma * p / rho;
     double a = sqrt(a2);
     double cf, cs;

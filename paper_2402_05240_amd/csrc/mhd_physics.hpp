@@ -196,9 +196,12 @@ struct Eigen {
 
 VLCT_DEV void eigen_setup(const W7 &c, double bn_in, double gam, Eigen &E)
 {
-    // components below kBperpTiny of the magnetosonic scale are rounding noise
+    // field components below kBperpTiny of the magnetosonic scale are rounding
+    // noise and are zero here, so noise cannot turn the B_perp direction
     const double bscale = sqrt(gam * c.p + bn_in * bn_in + c.by * c.by + c.bz * c.bz);
     const double bn = fabs(bn_in) <= kBperpTiny * bscale ? 0.0 : bn_in;
+    const double bt1 = fabs(c.by) <= kBperpTiny * bscale ? 0.0 : c.by;
+    const double bt2 = fabs(c.bz) <= kBperpTiny * bscale ? 0.0 : c.bz;
     const double id = 1.0 / c.d;
     const double gp = gam * c.p;
     E.d = c.d;
@@ -207,16 +210,16 @@ VLCT_DEV void eigen_setup(const W7 &c, double bn_in, double gam, Eigen &E)
     E.a = sqrt(E.asq);
     E.ia2 = c.d / gp;
     double disc;
-    const double cf2 = fast_sq(c.d, c.p, bn, c.by, c.bz, gam, disc);
+    const double cf2 = fast_sq(c.d, c.p, bn, bt1, bt2, gam, disc);
     const double cs2 = E.asq * bn * bn * id / cf2;
     E.cf = sqrt(cf2);
     E.cs = sqrt(cs2);
-    const double bp = sqrt(c.by * c.by + c.bz * c.bz);
+    const double bp = sqrt(bt1 * bt1 + bt2 * bt2);
     const bool haveperp = bp > kBperpTiny * bscale;
     const double ibp = 1.0 / bp;
-    E.by = haveperp ? c.by * ibp : 0.70710678118654752440;
-    E.bz = haveperp ? c.bz * ibp : 0.70710678118654752440;
-    const double tdiff = gam * c.p - (bn * bn + c.by * c.by + c.bz * c.bz);
+    E.by = haveperp ? bt1 * ibp : 0.70710678118654752440;
+    E.bz = haveperp ? bt2 * ibp : 0.70710678118654752440;
+    const double tdiff = gam * c.p - (bn * bn + bt1 * bt1 + bt2 * bt2);
     const bool split = disc > kCfCsTiny * c.d * cf2;
     const double idisc = 0.5 / disc;
     const double af2 = fmin(fmax((disc + tdiff) * idisc, 0.0), 1.0);

@@ -453,3 +453,34 @@ def test_ppmp_exact_for_cubic_cell_averages_and_bounded():
         tol = 1e-12 * np.abs(W).max()
         assert np.abs(fp - (W + (p(0.5) - avg(0)) * d)).max() <= tol
         assert np.abs(fm - (W + (p(-0.5) - avg(0)) * d)).max() <= tol
+
+
+def test_ppmc_insensitive_to_transverse_field_noise():
+    """A cell with B_t2 = 0 exactly and a right neighbour tied to it in rho,
+    v_t2 and B_t1 (the symmetric data of a blast wave's first step): noise of
+    1e-17 in B_t2, the size rounding leaves in a computed zero, must not move
+    the interface values.  The Alfven eigenvector direction is built from
+    B_perp / |B_perp|; noise there turns the tied (exactly zero) Alfven
+    difference into a tiny one of random sign and with it the extremum branch
+    of the limiter, which moved a face by 2.5e-2 before field components at
+    rounding level were taken as zero in the eigen-system."""
+    sten = np.array([
+        [1.0, 0.0, 0.0, 0.0, 0.0744, 0.7349, -1.13e-3],
+        [1.1184, -0.2579, 0.2273, -0.2002, 1.6604, 0.7238, -6.79e-4],
+        [0.8816, -0.2146, 0.1909, -0.1628, 8.3646, 0.6758, 0.0],
+        [0.8816, 0.2060, 0.1812, -0.1628, 8.3635, 0.6758, 0.0],
+        [1.1184, 0.2647, 0.2350, -0.2002, 1.6686, 0.7116, 1.109e-2]])
+    bn, gam = 0.6705, 5.0 / 3.0
+    fm, fp = ref.ppmc(sten, bn, gam)
+    rng = np.random.default_rng(3)
+    for _ in range(100):
+        s2 = sten.copy()
+        s2[:, 6] += 1e-17 * rng.normal(size=5)
+        a, b = ref.ppmc(s2, bn, gam)
+        assert np.abs(a - fm).max() <= 1e-15 and np.abs(b - fp).max() <= 1e-15
+    # and the eigen-system itself: B_t2 noise leaves R, L and the speeds unchanged
+    R0, L0, l0 = ref.eigen(sten[2], bn, gam)
+    w = sten[2].copy()
+    w[6] = 3e-17
+    R1, L1, l1 = ref.eigen(w, bn, gam)
+    assert np.array_equal(R0, R1) and np.array_equal(L0, L1) and np.array_equal(l0, l1)
