@@ -378,33 +378,23 @@ __global__ void __launch_bounds__(kBlock) k_flux_recon_march(Geom g, StateP s, P
 // ---------------------------------------------------------------------------
 // CT edge EMFs (Step 4 / Step 8; Eqs. emf-edge, emf-upwind-slope, emf-slope)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double ref_emf(const Prims &P, int a, idx_t o)
-{
-    const double vx = P.w[1][o], vy = P.w[2][o], vz = P.w[3][o];
-    const double bx = P.w[5][o], by = P.w[6][o], bz = P.w[7][o];
-    if (a == 0) return -(vy * bz - vz * by);
-    if (a == 1) return -(vz * bx - vx * bz);
-    return -(vx * by - vy * bx);
-}
-
 __device__ __forceinline__ double upwind(double s, double lo, double hi)
 {
     return s > 0.0 ? lo : (s < 0.0 ? hi : 0.5 * (lo + hi));
 }
 
 template <int A>
-__device__ __forceinline__ double edge_emf(const Geom &g, const Prims &P, const Flux &F, int i,
-                                           int j, int k)
+__device__ __forceinline__ double edge_emf(const Geom &g, const Flux &F, int i, int j, int k,
+                                           double r00, double r10, double r01, double r11)
 {
+    // r00, r10, r01, r11: cell-centred -(v x B)_A of the cells at x0, x0 - e_B,
+    // x0 - e_C and x0 - e_B - e_C around the edge
     constexpr int B = (A + 1) % 3, C = (A + 2) % 3;
     int x0[3] = {i, j, k};
     int xb[3] = {i, j, k};
     xb[B] -= 1;
     int xc[3] = {i, j, k};
     xc[C] -= 1;
-    int xbc[3] = {i, j, k};
-    xbc[B] -= 1;
-    xbc[C] -= 1;
     const idx_t fb_c = fidx(g, B, x0[0], x0[1], x0[2]);
     const idx_t fb_cm = fidx(g, B, xc[0], xc[1], xc[2]);
     const idx_t fc_b = fidx(g, C, x0[0], x0[1], x0[2]);
@@ -412,10 +402,6 @@ __device__ __forceinline__ double edge_emf(const Geom &g, const Prims &P, const 
     // B-face EMF component A = -F_B[B_t1]; C-face EMF component A = +F_C[B_t2]
     const double eb_c = -F.f[B][5][fb_c], eb_cm = -F.f[B][5][fb_cm];
     const double ec_b = F.f[C][6][fc_b], ec_bm = F.f[C][6][fc_bm];
-    const double r00 = ref_emf(P, A, pidx(g, x0[0], x0[1], x0[2]));
-    const double r10 = ref_emf(P, A, pidx(g, xb[0], xb[1], xb[2]));
-    const double r01 = ref_emf(P, A, pidx(g, xc[0], xc[1], xc[2]));
-    const double r11 = ref_emf(P, A, pidx(g, xbc[0], xbc[1], xbc[2]));
     const double sb_c = F.f[B][7][fb_c], sb_cm = F.f[B][7][fb_cm];
     const double sc_b = F.f[C][7][fc_b], sc_bm = F.f[C][7][fc_bm];
     const double avg = 0.25 * (eb_c + eb_cm + ec_b + ec_bm);
@@ -444,6 +430,9 @@ __global__ void __launch_bounds__(kBlock) k_ct_update(Geom g, Prims P, Flux F, S
     __shared__ double sez[kTy + 1][kTx + 1];
     __shared__ double sex[2][kTy + 1][kTx];
     __shared__ double sey[2][kTy][kTx + 1];
+    // cell-centred -(v x B) of the tile plus a one-cell halo below in x and y,
+    // two planes in flight: plane kk lives in slot (kk - k0 + 1) & 1
+    __shared__ double sref[2][3][kTy + 2][kTx + 2];
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     // positions owned by threads: cells/faces i in [0, ex), j in [0, ey)
     const int ex = nx + (g.bc[0] == VLCT_BC_OUTFLOW), ey = ny + (g.bc[1] == VLCT_BC_OUTFLOW);
@@ -458,24 +447,62 @@ __global__ void __launch_bounds__(kBlock) k_ct_update(Geom g, Prims P, Flux F, S
     const double cx = dt / g.dl[0], cy = dt / g.dl[1], cz = dt / g.dl[2];
     constexpr int NEZ = (kTy + 1) * (kTx + 1), NEX = (kTy + 1) * kTx, NEY = kTy * (kTx + 1);
 
-    // edges of the plane k+1/2 (E_x, E_y at edge index k) into slot h
+    constexpr int NREF = (kTy + 2) * (kTx + 2);
+    auto slot = [&](int kk) { return (kk - k0 + 1) & 1; };
+    // reference EMFs of plane kk (cells up to n: the highest edges are at n - 1/2)
+    auto stage_ref = [&](int kk) {
+        const int sl = slot(kk);
+        for (int q = threadIdx.x; q < NREF; q += kBlock) {
+            const int a = q % (kTx + 2), c = q / (kTx + 2), ii = i0 - 1 + a, jj = j0 - 1 + c;
+            if (ii <= nx && jj <= ny) {
+                const idx_t o = pidx(g, ii, jj, kk);
+                const double vx = P.w[1][o], vy = P.w[2][o], vz = P.w[3][o];
+                const double bx = P.w[5][o], by = P.w[6][o], bz = P.w[7][o];
+                sref[sl][0][c][a] = -(vy * bz - vz * by);
+                sref[sl][1][c][a] = -(vz * bx - vx * bz);
+                sref[sl][2][c][a] = -(vx * by - vy * bx);
+            }
+        }
+    };
+    // LDS coordinates of cell (ii, jj): [jj - j0 + 1][ii - i0 + 1]
+    // edges of the plane kk - 1/2 (E_x, E_y at edge index kk) into slot h
     auto horizontal_edges = [&](int kk, int h) {
+        const int up = slot(kk), dn = slot(kk - 1);
         for (int q = threadIdx.x; q < NEX; q += kBlock) {
             const int a = q % kTx, c = q / kTx, ii = i0 + a, jj = j0 + c;
-            if (ii < nx && jj <= ny) sex[h][c][a] = edge_emf<0>(g, P, F, ii, jj, kk);
+            // E_x at (ii, jj - 1/2, kk - 1/2): B = y, C = z
+            if (ii < nx && jj <= ny)
+                sex[h][c][a] = edge_emf<0>(g, F, ii, jj, kk, sref[up][0][c + 1][a + 1],
+                                           sref[up][0][c][a + 1], sref[dn][0][c + 1][a + 1],
+                                           sref[dn][0][c][a + 1]);
         }
         for (int q = threadIdx.x; q < NEY; q += kBlock) {
             const int a = q % (kTx + 1), c = q / (kTx + 1), ii = i0 + a, jj = j0 + c;
-            if (ii <= nx && jj < ny) sey[h][c][a] = edge_emf<1>(g, P, F, ii, jj, kk);
+            // E_y at (ii - 1/2, jj, kk - 1/2): B = z, C = x
+            if (ii <= nx && jj < ny)
+                sey[h][c][a] = edge_emf<1>(g, F, ii, jj, kk, sref[up][1][c + 1][a + 1],
+                                           sref[dn][1][c + 1][a + 1], sref[up][1][c + 1][a],
+                                           sref[dn][1][c + 1][a]);
         }
     };
     int lo = 0;
+    stage_ref(k0 - 1);
+    stage_ref(k0);
+    __syncthreads();
     horizontal_edges(k0, lo);
+    __syncthreads();
     bool bad = false;
     for (int k = k0; k < k1; ++k) {
+        stage_ref(k + 1);  // into the slot of plane k - 1, no longer read
+        __syncthreads();
+        const int sk = slot(k);
         for (int q = threadIdx.x; q < NEZ; q += kBlock) {
             const int a = q % (kTx + 1), c = q / (kTx + 1), ii = i0 + a, jj = j0 + c;
-            if (ii <= nx && jj <= ny) sez[c][a] = edge_emf<2>(g, P, F, ii, jj, k);
+            // E_z at (ii - 1/2, jj - 1/2, k): B = x, C = y
+            if (ii <= nx && jj <= ny)
+                sez[c][a] = edge_emf<2>(g, F, ii, jj, k, sref[sk][2][c + 1][a + 1],
+                                        sref[sk][2][c + 1][a], sref[sk][2][c][a + 1],
+                                        sref[sk][2][c][a]);
         }
         horizontal_edges(k + 1, 1 - lo);
         __syncthreads();
