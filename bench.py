@@ -21,14 +21,38 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP64 operations per face of the corrector flux kernel (one
-# reconstruction -- each cell serves its two faces -- and one HLLD solve), counted by
-# paper_2402_05240_amd/csrc/flop_count.cpp
-# (add/sub/mul/div/sqrt = 1 FLOP each; mean over turbulence-like states).
-FLOPS_PER_FACE = {2: 662.0, 3: 1034.0, 1: 291.0}
+# Algorithmic FP64 operations per face of a flux kernel (one reconstruction --
+# each cell's serves its two faces -- and one HLLD solve), counted by
+# paper_2402_05240_amd/csrc/flop_count.cpp (add/sub/mul/div/sqrt = 1 FLOP each,
+# mean over smooth random stencils).
+FLOPS_PER_FACE = {1: 291.0, 2: 663.0, 3: 1089.6, 4: 382.0, 5: 769.1}
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+F64 = 8
+# Algorithmic HBM bytes per unit of each kernel family (units: cells, or padded
+# cells for the primitive kernel):
+#   prims      reads 5 cell + 3 face fields, writes 8 primitives
+#   ct_update  reads 5 cell + 3 face fields, 3 axes x 8 flux components and
+#              6 primitives (v, B_cc for -v x B), writes 5 + 3 fields
+#   dt         reads 5 cell + 3 face fields
+BYTES_PER_UNIT = {"prims": 16 * F64, "ct_update": 46 * F64, "dt": 8 * F64}
+# a fully fused step would move the state in and out once
+STEP_MIN_BYTES_PER_CELL = 16 * F64
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "hbm_counters_turbulence_plmc_256.json")
+SOURCES = ("paper_2402_05240_amd/csrc/vlct.hip", "paper_2402_05240_amd/csrc/mhd_physics.hpp",
+           "include/vlct.h")
+
+
+def source_hash():
+    """sha256 over the kernel sources: counter figures are valid only for them."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
 
 WORKLOADS = {
     # name -> (constructor args, metric label)
@@ -123,8 +147,9 @@ def make_workload(name):
     return g, s
 
 
-def cpu_baseline(g, s, planes: int, threads: int):
-    """One oracle step on a z-slab of the workload's own initial state."""
+def cpu_baseline(g, s, planes: int, steps: int, threads: int):
+    """The oracle, as it stands, on a bounded sample of the workload: `steps`
+    steps of a z-slab of `planes` planes of its initial state."""
     import numpy as np
     from oracle import build as refbuild
     from oracle import ref
@@ -138,13 +163,164 @@ def cpu_baseline(g, s, planes: int, threads: int):
         ss["bz"][-1] = ss["bz"][0]
     dt = ref.cfl_dt(sg, ss, threads)
     t0 = time.perf_counter()
-    ref.step(sg, ss, dt, nthreads=threads)
+    for _ in range(steps):
+        ss, dt, _ = ref.step(sg, ss, dt, nthreads=threads)
     sec = time.perf_counter() - t0
-    cells = sg.ncells
-    return {"value": cells / sec, "unit": "cell updates/s", "cores": threads, "kind": "oracle",
-            "sample": "one oracle step (predictor+corrector+dt) on a %dx%dx%d z-slab of the "
-                      "workload's initial state, %.1f s on %d host threads" % (
-                          g.nx, g.ny, planes, sec, threads)}
+    return {"value": sg.ncells * steps / sec, "unit": "cell updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d oracle steps (predictor+corrector+dt, dt chained) on a %dx%dx%d "
+                      "slab of the workload's initial state: %.1f s on %d host threads" % (
+                          steps, g.nx, g.ny, planes, sec, threads)}
+
+
+def load_traffic(workload):
+    """Per-launch HBM bytes of each kernel family from the committed counter
+    summary, when it was taken on this workload with these kernel sources."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return {}
+    if c.get("source_sha256") != source_hash() or c.get("workload") != workload:
+        return {}
+    return {k: v["traffic_bytes_per_launch"] for k, v in c.get("families", {}).items()}
+
+
+def rooflines(g, kern, steps, workload=None):
+    """Roofline of every kernel family, from the launches timed with HIP events
+    on the library's stream: achieved = algorithmic work per launch / average
+    launch duration."""
+    ncell = g.ncells
+    npad = (g.nx + 6) * (g.ny + 6) * (g.nz + 6)
+    traffic = load_traffic(workload) if workload else {}
+    fam = {}
+    for name, v in kern.items():
+        key = "ct_update" if name in ("update_half", "update_full") else name
+        f = fam.setdefault(key, {"launches": 0, "total_ms": 0.0})
+        f["launches"] += v["launches"]
+        f["total_ms"] += v["total_ms"]
+    out = {}
+    for key, f in fam.items():
+        avg_ms = f["total_ms"] / f["launches"]
+        r = {"kernel": key, "launches_per_step": f["launches"] / steps,
+             "ms_per_step": f["total_ms"] / steps, "avg_launch_ms": avg_ms}
+        if key in ("flux_recon_hlld", "flux_pcm_hlld"):
+            recon = g.recon if key == "flux_recon_hlld" else 1
+            # one axis' faces per launch (n faces per row of a periodic axis)
+            flops = FLOPS_PER_FACE[recon] * ncell
+            ach = flops / (avg_ms * 1e-3) / 1e12
+            r.update({"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS,
+                      "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS,
+                      "flops_per_launch": flops, "per_unit": "%.1f FLOP per face" %
+                      FLOPS_PER_FACE[recon]})
+            # HBM bytes of the flux kernels: 8 primitives + normal field in,
+            # 8 flux components out, per face
+            r["bytes_per_step"] = 17 * F64 * ncell * f["launches"] / steps
+        else:
+            units = npad if key == "prims" else ncell
+            nbytes = BYTES_PER_UNIT[key] * units
+            ach = nbytes / (avg_ms * 1e-3) / 1e9
+            r.update({"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                      "frac": ach / PEAK_HBM_GBS, "bytes_per_launch": nbytes,
+                      "per_unit": "%d B per %s" % (BYTES_PER_UNIT[key],
+                                                   "padded cell" if key == "prims" else "cell")})
+            r["bytes_per_step"] = nbytes * f["launches"] / steps
+        r["traffic"] = traffic.get(key)
+        if r["traffic"] is not None:
+            r["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"
+        out[key] = r
+    return out
+
+
+def kernel_family(name):
+    """Kernel family of a device kernel name as rocprofv3 prints it."""
+    if "k_prims" in name:
+        return "prims"
+    if "k_ct_update" in name:
+        return "ct_update"
+    if "k_dt_" in name:
+        return "dt"
+    if "k_flux" in name:
+        # template arguments <..., RECON>; RECON 1 is the PCM predictor
+        targs = name[name.index("<") + 1:name.index(">")].replace(" ", "").split(",")
+        return "flux_pcm_hlld" if targs[-1] == "1" else "flux_recon_hlld"
+    if "copyBuffer" in name:
+        return "copy"
+    return None
+
+
+def summarize_counters(fetch_csv, write_csv, copy_bytes, workload, commands, out_dir):
+    """rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per dispatch) -> calibrated
+    HBM bytes per launch of each kernel family.  FETCH_SIZE and WRITE_SIZE are
+    scaled by the factor that makes them read copy_bytes for the plain device
+    copy the same runs made (the copy's dispatches are summed)."""
+    import collections
+    import csv
+
+    def per_family(path):
+        fam = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            k = kernel_family(r["Kernel_Name"])
+            if k:
+                fam[k].append(float(r["Counter_Value"]) * 1024.0)
+        return fam
+    fe, wr = per_family(fetch_csv), per_family(write_csv)
+    ffac = copy_bytes / sum(fe["copy"])
+    wfac = copy_bytes / sum(wr["copy"])
+    fams = {}
+    for k in fe:
+        if k == "copy":
+            continue
+        nf = len(fe[k])
+        # dt is one launch of a partial and a final kernel
+        per = 2 if k == "dt" else 1
+        fb = ffac * sum(fe[k]) / (nf / per)
+        wb = wfac * sum(wr[k]) / (len(wr[k]) / per)
+        fams[k] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                   "traffic_bytes_per_launch": fb + wb, "dispatches": nf}
+    res = {"workload": workload, "source_sha256": source_hash(),
+           "calibration": {"copy_bytes": copy_bytes, "fetch_factor": ffac, "write_factor": wfac},
+           "commands": commands, "families": fams}
+    base = os.path.join(out_dir, "hbm_counters_%s" % workload)
+    with open(base + ".json", "w") as f:
+        json.dump(res, f, indent=1)
+    lines = ["# HBM traffic per launch, %s" % workload, "",
+             "rocprofv3 counters FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each from its own run:",
+             ""] + ["    " + c for c in commands] + [
+             "", "Calibration: the same runs copy %d bytes device-to-device first; FETCH_SIZE reads "
+             "%.3f of them (factor %.3f), WRITE_SIZE %.3f (factor %.3f)." % (
+                 copy_bytes, 1 / ffac, ffac, 1 / wfac, wfac),
+             "", "Kernel sources sha256: `%s`" % res["source_sha256"], "",
+             "| kernel family | dispatches | read GiB/launch | write GiB/launch | total GB/launch |",
+             "|---|---|---|---|---|"]
+    for k, v in sorted(fams.items()):
+        lines.append("| %s | %d | %.3f | %.3f | %.3f |" % (
+            k, v["dispatches"], v["fetch_bytes_per_launch"] / 2**30,
+            v["write_bytes_per_launch"] / 2**30, v["traffic_bytes_per_launch"] / 1e9))
+    with open(base + ".md", "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return res
+
+
+def summarize_trace(stats_csv, workload, command, out_dir):
+    """rocprofv3 --kernel-trace --stats kernel table -> markdown summary."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = ["# Kernel durations, %s" % workload, "", "    " + command, "",
+             "Kernel sources sha256: `%s`" % source_hash(), "",
+             "| kernel | family | calls | average ms | total ms | % |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        fam = kernel_family(r["Name"])
+        if fam in (None, "copy"):
+            continue
+        name = r["Name"].split("(")[0].replace("void ", "")
+        lines.append("| `%s` | %s | %s | %.4f | %.3f | %s |" % (
+            name, fam, r["Calls"], float(r["AverageNs"]) / 1e6,
+            float(r["TotalDurationNs"]) / 1e6, r["Percentage"]))
+    path = os.path.join(out_dir, "kernel_trace_%s.md" % workload)
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return path
 
 
 def main():
@@ -154,12 +330,31 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="turbulence_plmc_256", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-planes", type=int, default=32)
+    ap.add_argument("--cpu-planes", type=int, default=256)
+    ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="first run one device-to-device copy of this many GiB (a plain copy "
                          "kernel of known size, to calibrate HBM byte counters)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/hbm_counters_<workload>.{json,md} from the two "
+                         "rocprofv3 --pmc runs (no GPU needed)")
+    ap.add_argument("--summarize-trace", metavar="KERNEL_STATS_CSV",
+                    help="write profiles/kernel_trace_<workload>.md (no GPU needed)")
+    ap.add_argument("--commands", nargs="*", default=[],
+                    help="the rocprofv3 command lines the summarised files came from")
     args = ap.parse_args()
+    if args.summarize_counters or args.summarize_trace:
+        out_dir = os.path.join(ROOT, "profiles")
+        os.makedirs(out_dir, exist_ok=True)
+        if args.summarize_counters:
+            summarize_counters(args.summarize_counters[0], args.summarize_counters[1],
+                               int(args.copy_calibration_gib * (1 << 30)) or (1 << 30),
+                               args.workload, args.commands[:2], out_dir)
+        if args.summarize_trace:
+            summarize_trace(args.summarize_trace, args.workload,
+                            args.commands[-1] if args.commands else "", out_dir)
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
@@ -210,13 +405,12 @@ def main():
     ncell = g.ncells
     ms_step = ms_total / args.steps
     value = ncell * args.steps / (ms_total * 1e-3)
-    dom = kern.get("flux_recon_hlld")
-    faces_per_launch = ncell              # one axis' faces of a periodic grid
-    flops_launch = FLOPS_PER_FACE[g.recon] * faces_per_launch
-    achieved = flops_launch / (dom["avg_ms"] * 1e-3) / 1e12
-    recon_name = {1: "PCM", 2: "PLMC", 3: "PPMC"}[g.recon]
+    rl = rooflines(g, kern, args.steps, args.workload)
+    dom = max(rl, key=lambda k: rl[k]["ms_per_step"])
+    recon_name = {1: "PCM", 2: "PLMC", 3: "PPMC", 4: "PLMP", 5: "PPMP"}[g.recon]
+    design_bytes = sum(r["bytes_per_step"] for r in rl.values() if "bytes_per_step" in r) / ncell
     out = {
-        "metric": "FP64 cell updates/s (PLMC+HLLD, 256^3)",
+        "metric": BASELINE_METRIC,
         "value": value,
         "unit": "cell updates/s",
         "n_gpus": 1,
@@ -232,10 +426,17 @@ def main():
                    "reconstruction": recon_name, "riemann": "HLLD", "integrator": "VL+CT",
                    "bc": ["periodic" if b == 0 else "outflow" for b in g.bc], "cfl": g.cfl,
                    "gamma": g.gamma},
-        "roofline": {"bound": "alu", "kernel": "flux_recon_hlld", "achieved": achieved,
-                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "flops_per_launch": flops_launch, "avg_launch_ms": dom["avg_ms"]},
+        "roofline": rl[dom],
+        "rooflines": rl,
+        # whole step against the HBM roofline: as a fused step would move it
+        # (state in and out once) and as this design's kernels move it
+        "step_hbm": {"bytes_per_cell_min": STEP_MIN_BYTES_PER_CELL,
+                     "frac_min": STEP_MIN_BYTES_PER_CELL * value / (PEAK_HBM_GBS * 1e9),
+                     "bytes_per_cell_design": design_bytes,
+                     "frac_design_lower_bound": design_bytes * value / (PEAK_HBM_GBS * 1e9),
+                     "note": "design bytes count the compute-bound flux kernels' reads and "
+                             "writes as well"},
+        "adjoint_forward_cost": None,
         "kernels_ms_per_step": {k: v["total_ms"] / args.steps for k, v in kern.items()},
         "wall_ms_per_step": (w1 - w0) * 1e3 / args.steps,
         "status": status,
@@ -244,7 +445,7 @@ def main():
         del st
         torch.cuda.empty_cache()
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(g, s0, args.cpu_planes, threads)
+        out["cpu_baseline"] = cpu_baseline(g, s0, args.cpu_planes, args.cpu_steps, threads)
     print(json.dumps(out), flush=True)
 
 

@@ -54,7 +54,7 @@ int main()
                         0.2 * nrm(rng)};
     };
     const int N = 20000;
-    long long plmc_f = 0, ppmc_f = 0, hlld_f = 0;
+    long long plmc_f = 0, ppmc_f = 0, plmp_f = 0, ppmp_f = 0, hlld_f = 0;
     for (int q = 0; q < N; ++q) {
         vlct::W7 a = state(), b = state(), c = state(), d = state(), e = state();
         // smooth-ish stencils: neighbours close to the centre
@@ -73,6 +73,12 @@ int main()
         f0 = g_flops;
         vlct::ppmc<true>(m2, m1, c, p1, p2, Counted(bn), Counted(gam), fm, fp);
         ppmc_f += g_flops - f0;
+        f0 = g_flops;
+        vlct::plmc<false>(m1, c, p1, Counted(bn), Counted(gam), fm, fp);
+        plmp_f += g_flops - f0;
+        f0 = g_flops;
+        vlct::ppmc<false>(m2, m1, c, p1, p2, Counted(bn), Counted(gam), fm, fp);
+        ppmp_f += g_flops - f0;
         Counted f[7], upw;
         f0 = g_flops;
         vlct::hlld(m1, c, Counted(bn), Counted(gam), Counted(gm1i), f, upw);
@@ -82,7 +88,11 @@ int main()
                 double(plmc_f) / N, double(ppmc_f) / N, double(hlld_f) / N);
     // a corrector face needs one reconstruction (each cell's reconstruction
     // serves its two faces) and one HLLD solve
+    std::printf("plmp_per_call %.1f\nppmp_per_call %.1f\n", double(plmp_f) / N,
+                double(ppmp_f) / N);
     std::printf("plmc_hlld_per_face %.1f\nppmc_hlld_per_face %.1f\n",
                 double(plmc_f + hlld_f) / N, double(ppmc_f + hlld_f) / N);
+    std::printf("plmp_hlld_per_face %.1f\nppmp_hlld_per_face %.1f\n",
+                double(plmp_f + hlld_f) / N, double(ppmp_f + hlld_f) / N);
     return 0;
 }
