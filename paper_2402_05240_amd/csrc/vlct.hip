@@ -51,19 +51,19 @@ struct Geom {
 __host__ __device__ __forceinline__ int map_cell(int i, int n, int bc)
 {
     if (bc == VLCT_BC_PERIODIC) {
-        int m = i % n;
+        // one period either side without an integer division
+        if (i >= 0 && i < n) return i;
+        if (i < 0 && i >= -n) return i + n;
+        if (i >= n && i < 2 * n) return i - n;
+        const int m = i % n;
         return m < 0 ? m + n : m;
     }
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
-
 // normal-face index: periodic faces wrap into [0, n-1], outflow clamps into [0, n]
 __host__ __device__ __forceinline__ int map_face(int i, int n, int bc)
 {
-    if (bc == VLCT_BC_PERIODIC) {
-        int m = i % n;
-        return m < 0 ? m + n : m;
-    }
+    if (bc == VLCT_BC_PERIODIC) return map_cell(i, n, bc);
     return i < 0 ? 0 : (i > n ? n : i);
 }
 
@@ -421,9 +421,10 @@ __device__ __forceinline__ double edge_emf(const Geom &g, const Flux &F, int i, 
 // k_update, without the round trip of the edge arrays through HBM.
 // ---------------------------------------------------------------------------
 constexpr int kTx = 32, kTy = 8, kTz = 16;
+constexpr int kCt = kTx * kTy;  // threads of a CT block: one per column of the tile
 
 template <bool FULL>
-__global__ void __launch_bounds__(kBlock) k_ct_update(Geom g, Prims P, Flux F, StateP base,
+__global__ void __launch_bounds__(kCt) k_ct_update(Geom g, Prims P, Flux F, StateP base,
                                                        StateW out, const double *dt_dev,
                                                        uint32_t *status)
 {
@@ -452,7 +453,7 @@ __global__ void __launch_bounds__(kBlock) k_ct_update(Geom g, Prims P, Flux F, S
     // reference EMFs of plane kk (cells up to n: the highest edges are at n - 1/2)
     auto stage_ref = [&](int kk) {
         const int sl = slot(kk);
-        for (int q = threadIdx.x; q < NREF; q += kBlock) {
+        for (int q = threadIdx.x; q < NREF; q += kCt) {
             const int a = q % (kTx + 2), c = q / (kTx + 2), ii = i0 - 1 + a, jj = j0 - 1 + c;
             if (ii <= nx && jj <= ny) {
                 const idx_t o = pidx(g, ii, jj, kk);
@@ -468,7 +469,7 @@ __global__ void __launch_bounds__(kBlock) k_ct_update(Geom g, Prims P, Flux F, S
     // edges of the plane kk - 1/2 (E_x, E_y at edge index kk) into slot h
     auto horizontal_edges = [&](int kk, int h) {
         const int up = slot(kk), dn = slot(kk - 1);
-        for (int q = threadIdx.x; q < NEX; q += kBlock) {
+        for (int q = threadIdx.x; q < NEX; q += kCt) {
             const int a = q % kTx, c = q / kTx, ii = i0 + a, jj = j0 + c;
             // E_x at (ii, jj - 1/2, kk - 1/2): B = y, C = z
             if (ii < nx && jj <= ny)
@@ -476,7 +477,7 @@ __global__ void __launch_bounds__(kBlock) k_ct_update(Geom g, Prims P, Flux F, S
                                            sref[up][0][c][a + 1], sref[dn][0][c + 1][a + 1],
                                            sref[dn][0][c][a + 1]);
         }
-        for (int q = threadIdx.x; q < NEY; q += kBlock) {
+        for (int q = threadIdx.x; q < NEY; q += kCt) {
             const int a = q % (kTx + 1), c = q / (kTx + 1), ii = i0 + a, jj = j0 + c;
             // E_y at (ii - 1/2, jj, kk - 1/2): B = z, C = x
             if (ii <= nx && jj < ny)
@@ -496,7 +497,7 @@ __global__ void __launch_bounds__(kBlock) k_ct_update(Geom g, Prims P, Flux F, S
         stage_ref(k + 1);  // into the slot of plane k - 1, no longer read
         __syncthreads();
         const int sk = slot(k);
-        for (int q = threadIdx.x; q < NEZ; q += kBlock) {
+        for (int q = threadIdx.x; q < NEZ; q += kCt) {
             const int a = q % (kTx + 1), c = q / (kTx + 1), ii = i0 + a, jj = j0 + c;
             // E_z at (ii - 1/2, jj - 1/2, k): B = x, C = y
             if (ii <= nx && jj <= ny)
@@ -919,14 +920,14 @@ int vlct_step(const vlct_grid *vg, const vlct_state *in, const vlct_state *out,
     if (rc) return rc;
     {
         Observe o(VLCT_KERNEL_UPDATE_HALF, s);
-        k_ct_update<false><<<gct, kBlock, 0, s>>>(g, B.P, B.F, sin, B.half, dt_dev, status_dev);
+        k_ct_update<false><<<gct, kCt, 0, s>>>(g, B.P, B.F, sin, B.half, dt_dev, status_dev);
     }
     // corrector (Steps 6-9)
     rc = launch_stage_fluxes(g, as_const(B.half), B, vg->recon, status_dev, s);
     if (rc) return rc;
     {
         Observe o(VLCT_KERNEL_UPDATE_FULL, s);
-        k_ct_update<true><<<gct, kBlock, 0, s>>>(g, B.P, B.F, sin, as_mut(out), dt_dev,
+        k_ct_update<true><<<gct, kCt, 0, s>>>(g, B.P, B.F, sin, as_mut(out), dt_dev,
                                                  status_dev);
     }
     if (hipGetLastError() != hipSuccess) return VLCT_EHIP;
