@@ -413,14 +413,14 @@ __device__ __forceinline__ double edge_emf(const Geom &g, const Flux &F, int i, 
 }
 
 // ---------------------------------------------------------------------------
-// fused CT + update (Steps 4-5 and 8-9): a block owns a 32 x 8 column tile and
+// fused CT + update (Steps 4-5 and 8-9): a block owns a 64 x 8 column tile and
 // marches along z.  For each plane k it computes the edge fields it needs once
 // into LDS -- E_z of plane k, E_x / E_y of the plane above (k+1/2); those of
 // the plane below are kept from the previous iteration -- and then updates the
 // plane's cells and the faces owned by them.  Same arithmetic as k_edges and
 // k_update, without the round trip of the edge arrays through HBM.
 // ---------------------------------------------------------------------------
-constexpr int kTx = 32, kTy = 8, kTz = 16;
+constexpr int kTx = 64, kTy = 8, kTz = 16;
 constexpr int kCt = kTx * kTy;  // threads of a CT block: one per column of the tile
 
 template <bool FULL>
