@@ -112,6 +112,31 @@ int vlct_step(const vlct_grid *g, const vlct_state *in, const vlct_state *out,
               const double *dt_dev, double *next_dt_dev, uint32_t *status_dev, void *ws,
               size_t ws_bytes, void *stream);
 
+/* --- batched ensembles ----------------------------------------------------
+ * Independent instances (own sizes, gamma, cfl, boundaries, dt and state)
+ * advanced by one step together: each kernel of the step is launched once for
+ * all instances, which fills the GPU when the grids are small.  Every instance
+ * computes exactly what vlct_step computes for it (bit-identical results).
+ *
+ * Bytes of device workspace vlct_step_batch needs for these `count` grid
+ * descriptors (host array), 0 if count < 1, count > 65536 or a descriptor is
+ * invalid.  The workspace holds a table of the instances and each instance's
+ * own workspace; its contents are scratch between calls. */
+size_t vlct_batch_workspace_bytes(const vlct_grid *grids, int count);
+
+/* One VL+CT step of every instance i in [0, count): grids[i], in[i], out[i]
+ * are HOST arrays of descriptors (the vlct_state members are device
+ * pointers); dt_dev, next_dt_dev (nullable) and status_dev (nullable) are
+ * DEVICE arrays of `count` elements, instance i using element i.  All
+ * instances must use the same reconstruction (else VLCT_EUNSUPPORTED).  Each
+ * instance is either fully in place (out[i] == in[i] field by field) or uses
+ * output arrays no other array of the call uses (else VLCT_EINVAL).  Returns
+ * VLCT_EWORKSPACE if ws_bytes < vlct_batch_workspace_bytes(grids, count).
+ * Stream-ordered; no allocation and no host synchronisation. */
+int vlct_step_batch(int count, const vlct_grid *grids, const vlct_state *in,
+                    const vlct_state *out, const double *dt_dev, double *next_dt_dev,
+                    uint32_t *status_dev, void *ws, size_t ws_bytes, void *stream);
+
 /* --- diagnostics ----------------------------------------------------------
  * Launch observer: when set, every vlct_step / vlct_cfl_dt call invokes
  * cb(user, kernel, phase, stream) on the calling host thread immediately

@@ -12,6 +12,8 @@
 
 #include <cstdint>
 #include <cstring>
+#include <unordered_map>
+#include <vector>
 
 #include "../../include/vlct.h"
 #include "mhd_physics.hpp"
@@ -112,13 +114,57 @@ struct Flux {
 };
 
 // ---------------------------------------------------------------------------
+// logical block counts of the kernels (host launches and batch offsets)
+// ---------------------------------------------------------------------------
+constexpr int kRowFaces = kBlock - 1;
+constexpr int kMarch = 32;
+constexpr int kTx = 64, kTy = 8, kTz = 16;
+constexpr int kCt = kTx * kTy;  // threads of a CT block: one per column of the tile
+
+__host__ __device__ __forceinline__ idx_t nblk_prims(const Geom &g)
+{
+    return ((idx_t)g.p[0] * g.p[1] * g.p[2] + kBlock - 1) / kBlock;
+}
+__host__ __device__ __forceinline__ idx_t flux_dim3(const Geom &g, int d)
+{
+    return flux_dim(g.n, d, 0) * flux_dim(g.n, d, 1) * flux_dim(g.n, d, 2);
+}
+__host__ __device__ __forceinline__ idx_t nblk_flux(const Geom &g, int d)
+{
+    return (flux_dim3(g, d) + kBlock - 1) / kBlock;
+}
+__host__ __device__ __forceinline__ idx_t nblk_row(const Geom &g)
+{
+    const idx_t items = (idx_t)(g.n[0] + 2) * (g.n[1] + 2) * (g.n[2] + 2);
+    return (items - 1 + kRowFaces - 1) / kRowFaces;
+}
+__host__ __device__ __forceinline__ idx_t nblk_march(const Geom &g, int d)
+{
+    const int t = d == 1 ? 2 : 1;
+    const idx_t cols = (idx_t)(g.n[0] + 2) * (g.n[t] + 2);
+    return ((cols + kBlock - 1) / kBlock) * ((g.n[d] + 1 + kMarch - 1) / kMarch);
+}
+__host__ __device__ __forceinline__ idx_t nblk_ct(const Geom &g)
+{
+    const int ntx = (g.n[0] + (g.bc[0] == VLCT_BC_OUTFLOW) + kTx - 1) / kTx;
+    const int nty = (g.n[1] + (g.bc[1] == VLCT_BC_OUTFLOW) + kTy - 1) / kTy;
+    const int ntz = (g.n[2] + kTz - 1) / kTz;
+    return (idx_t)ntx * nty * ntz;
+}
+__host__ __device__ __forceinline__ idx_t nblk_dt(const Geom &g)
+{
+    return ((idx_t)g.n[0] * g.n[1] * g.n[2] + kBlock - 1) / kBlock;
+}
+
+// ---------------------------------------------------------------------------
 // primitive variables on the ghost-padded grid (Sec. 2.1; B_cc = face average,
 // Step 1); the boundary conditions are applied here by index mapping
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_prims(Geom g, StateP s, Prims P, uint32_t *status)
+__device__ __forceinline__ void prims_body(const Geom &g, const StateP &s, const Prims &P,
+                                           uint32_t *status, idx_t b)
 {
     const idx_t tot = (idx_t)g.p[0] * g.p[1] * g.p[2];
-    const idx_t t = xcd_block((tot + kBlock - 1) / kBlock) * kBlock + threadIdx.x;
+    const idx_t t = b * kBlock + threadIdx.x;
     if (t >= tot) return;
     const int pi = (int)(t % g.p[0]);
     const idx_t r = t / g.p[0];
@@ -172,11 +218,11 @@ __device__ __forceinline__ W7 load_w7(const Prims &P, idx_t o)
 // PCM interface states + HLLD on every face of axis D (Steps 2-3)
 // ---------------------------------------------------------------------------
 template <int D, int RECON>
-__global__ void __launch_bounds__(kBlock) k_flux(Geom g, StateP s, Prims P, Flux F,
-                                                 uint32_t *status)
+__device__ __forceinline__ void flux_pcm_body(const Geom &g, const StateP &s, const Prims &P,
+                                              const Flux &F, uint32_t *status, idx_t b)
 {
     const idx_t X = flux_dim(g.n, D, 0), Y = flux_dim(g.n, D, 1), Z = flux_dim(g.n, D, 2);
-    const idx_t t = xcd_block((X * Y * Z + kBlock - 1) / kBlock) * kBlock + threadIdx.x;
+    const idx_t t = b * kBlock + threadIdx.x;
     if (t >= X * Y * Z) return;
     int x[3];
     x[0] = (int)(t % X) - (D != 0);
@@ -216,8 +262,6 @@ __global__ void __launch_bounds__(kBlock) k_flux(Geom g, StateP s, Prims P, Flux
 // row; the high-face states go through LDS to the right neighbour, which
 // solves the Riemann problem of the face between them (255 faces per block).
 // ---------------------------------------------------------------------------
-constexpr int kRowFaces = kBlock - 1;
-
 template <int RECON>
 __device__ __forceinline__ void recon_cell(const Prims &P, const Geom &g, int D, const int c[3],
                                            W7 &fm, W7 &fp)
@@ -243,8 +287,8 @@ __device__ __forceinline__ void recon_cell(const Prims &P, const Geom &g, int D,
 }
 
 template <int RECON>
-__global__ void __launch_bounds__(kBlock) k_flux_recon_x(Geom g, StateP s, Prims P, Flux F,
-                                                          uint32_t *status)
+__device__ __forceinline__ void recon_x_body(const Geom &g, const StateP &s, const Prims &P,
+                                             const Flux &F, uint32_t *status, idx_t b)
 {
     // items = (row, cell) with cells -1..nx of every row (j in [-1, ny],
     // k in [-1, nz]) in one flat sequence; a block reconstructs 256
@@ -255,7 +299,6 @@ __global__ void __launch_bounds__(kBlock) k_flux_recon_x(Geom g, StateP s, Prims
     const idx_t per_row = nx + 2;
     const idx_t items = per_row * (idx_t)(g.n[1] + 2) * (g.n[2] + 2);
     const idx_t nblk = (items - 1 + kRowFaces - 1) / kRowFaces;
-    const idx_t b = xcd_block(nblk);
     const int t = threadIdx.x;
     const idx_t q = b * kRowFaces + t;
     const bool have = b < nblk && q < items;
@@ -294,11 +337,9 @@ __global__ void __launch_bounds__(kBlock) k_flux_recon_x(Geom g, StateP s, Prims
 // fastest, so loads and stores are coalesced); each thread marches along the
 // axis through a segment of kMarch faces, keeping the stencil and the previous
 // cell's high-face state in registers (one extra reconstruction per segment).
-constexpr int kMarch = 32;
-
 template <int D, int RECON>
-__global__ void __launch_bounds__(kBlock) k_flux_recon_march(Geom g, StateP s, Prims P, Flux F,
-                                                              uint32_t *status)
+__device__ __forceinline__ void march_body(const Geom &g, const StateP &s, const Prims &P,
+                                           const Flux &F, uint32_t *status, idx_t b)
 {
     constexpr int T = D == 1 ? 2 : 1;         // the transverse axis other than x
     constexpr bool kChar = RECON == VLCT_RECON_PLMC || RECON == VLCT_RECON_PPMC;
@@ -308,7 +349,6 @@ __global__ void __launch_bounds__(kBlock) k_flux_recon_march(Geom g, StateP s, P
     const idx_t cols = (idx_t)(g.n[0] + 2) * (g.n[T] + 2);
     const idx_t ncb = (cols + kBlock - 1) / kBlock;
     const int nseg = (nD + 1 + kMarch - 1) / kMarch;
-    const idx_t b = xcd_block(ncb * nseg);
     const int seg = (int)(b / ncb);
     const idx_t col = (b % ncb) * kBlock + threadIdx.x;
     if (seg >= nseg || col >= cols) return;
@@ -339,7 +379,7 @@ __global__ void __launch_bounds__(kBlock) k_flux_recon_march(Geom g, StateP s, P
     const int mi = map_cell(i, g.n[0], g.bc[0]);
     for (int c = s0 - 1; c < s1; ++c) {
         W7 fm, fp;
-        if (R == 1)
+        if constexpr (R == 1)
             plmc<kChar>(win[0], win[1], win[2], bnc[1], g.gamma, fm, fp);
         else
             ppmc<kChar>(win[0], win[1], win[2], win[3], win[4], bnc[2], g.gamma, fm, fp);
@@ -420,13 +460,11 @@ __device__ __forceinline__ double edge_emf(const Geom &g, const Flux &F, int i, 
 // plane's cells and the faces owned by them.  Same arithmetic as k_edges and
 // k_update, without the round trip of the edge arrays through HBM.
 // ---------------------------------------------------------------------------
-constexpr int kTx = 64, kTy = 8, kTz = 16;
-constexpr int kCt = kTx * kTy;  // threads of a CT block: one per column of the tile
 
 template <bool FULL>
-__global__ void __launch_bounds__(kCt) k_ct_update(Geom g, Prims P, Flux F, StateP base,
-                                                       StateW out, const double *dt_dev,
-                                                       uint32_t *status)
+__device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flux &F,
+                                        const StateP &base, const StateW &out,
+                                        const double *dt_dev, uint32_t *status, idx_t b)
 {
     __shared__ double sez[kTy + 1][kTx + 1];
     __shared__ double sex[2][kTy + 1][kTx];
@@ -438,7 +476,6 @@ __global__ void __launch_bounds__(kCt) k_ct_update(Geom g, Prims P, Flux F, Stat
     // positions owned by threads: cells/faces i in [0, ex), j in [0, ey)
     const int ex = nx + (g.bc[0] == VLCT_BC_OUTFLOW), ey = ny + (g.bc[1] == VLCT_BC_OUTFLOW);
     const int ntx = (ex + kTx - 1) / kTx, nty = (ey + kTy - 1) / kTy, ntz = (nz + kTz - 1) / kTz;
-    const idx_t b = xcd_block((idx_t)ntx * nty * ntz);
     if (b >= (idx_t)ntx * nty * ntz) return;
     const int bx = (int)(b % ntx), by = (int)((b / ntx) % nty), bz = (int)(b / ((idx_t)ntx * nty));
     const int i0 = bx * kTx, j0 = by * kTy, k0 = bz * kTz, k1 = min(k0 + kTz, nz);
@@ -592,12 +629,12 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-__global__ void __launch_bounds__(kBlock) k_dt_partial(Geom g, StateP s, double *partial,
-                                                       uint32_t *status)
+__device__ __forceinline__ void dt_partial_body(const Geom &g, const StateP &s, double *partial,
+                                                uint32_t *status, idx_t b)
 {
     __shared__ double red[kBlock / 64];
     const idx_t N = (idx_t)g.n[0] * g.n[1] * g.n[2];
-    const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const idx_t t = b * kBlock + threadIdx.x;
     double m = 0.0;
     if (t < N) {
         const int i = (int)(t % g.n[0]);
@@ -633,9 +670,9 @@ __global__ void __launch_bounds__(kBlock) k_dt_partial(Geom g, StateP s, double 
     if (lane == 0) red[wv] = m;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double b = red[0];
-        for (int q = 1; q < kBlock / 64; ++q) b = fmax(b, red[q]);
-        partial[blockIdx.x] = b;
+        double red_max = red[0];
+        for (int q = 1; q < kBlock / 64; ++q) red_max = fmax(red_max, red[q]);
+        partial[b] = red_max;
     }
 }
 
@@ -653,6 +690,212 @@ __global__ void __launch_bounds__(1024) k_dt_final(const double *partial, int n,
         double b = red[0];
         for (int q = 1; q < (int)(blockDim.x / 64); ++q) b = fmax(b, red[q]);
         dt_out[0] = cfl / b;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// single-instance kernels: the logical block comes from the XCD remap
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_prims(Geom g, StateP s, Prims P, uint32_t *status)
+{
+    prims_body(g, s, P, status, xcd_block(nblk_prims(g)));
+}
+
+template <int D, int RECON>
+__global__ void __launch_bounds__(kBlock) k_flux(Geom g, StateP s, Prims P, Flux F,
+                                                 uint32_t *status)
+{
+    flux_pcm_body<D, RECON>(g, s, P, F, status, xcd_block(nblk_flux(g, D)));
+}
+
+template <int RECON>
+__global__ void __launch_bounds__(kBlock) k_flux_recon_x(Geom g, StateP s, Prims P, Flux F,
+                                                          uint32_t *status)
+{
+    recon_x_body<RECON>(g, s, P, F, status, xcd_block(nblk_row(g)));
+}
+
+template <int D, int RECON>
+__global__ void __launch_bounds__(kBlock) k_flux_recon_march(Geom g, StateP s, Prims P, Flux F,
+                                                              uint32_t *status)
+{
+    march_body<D, RECON>(g, s, P, F, status, xcd_block(nblk_march(g, D)));
+}
+
+template <bool FULL>
+__global__ void __launch_bounds__(kCt) k_ct_update(Geom g, Prims P, Flux F, StateP base,
+                                                       StateW out, const double *dt_dev,
+                                                       uint32_t *status)
+{
+    ct_body<FULL>(g, P, F, base, out, dt_dev, status, xcd_block(nblk_ct(g)));
+}
+
+__global__ void __launch_bounds__(kBlock) k_dt_partial(Geom g, StateP s, double *partial,
+                                                       uint32_t *status)
+{
+    dt_partial_body(g, s, partial, status, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// batched step: independent instances (own sizes, gamma, dt, boundaries,
+// workspace) advanced by one launch per kernel for all of them.  Each launch
+// flattens the logical blocks of every instance; a block finds its instance
+// by binary search over the first block of each instance and runs the same
+// body as the single-instance kernel, so an instance's result equals its
+// single-instance step bit for bit.
+// ---------------------------------------------------------------------------
+enum Slot { kSlotPrims, kSlotFlux0, kSlotFlux1, kSlotFlux2, kSlotRow, kSlotMarch1, kSlotMarch2,
+            kSlotCt, kSlotDt, kSlots };
+
+struct Inst {
+    Geom g;
+    StateP in;       // U^n
+    StateW out;      // U^{n+1}
+    StateW half;     // U^{n+1/2} (workspace)
+    Prims P;         // primitives of the current stage (workspace)
+    Flux F;          // face fluxes of the current stage (workspace)
+    double *partial; // CFL partials (workspace)
+    const double *dt;
+    double *next_dt;
+    uint32_t *status;
+    idx_t start[kSlots];  // first flattened block of this instance in each launch
+};
+
+constexpr int kPackChunk = 4;  // records per pack launch (kernel-argument size)
+struct PackArgs {
+    Inst rec[kPackChunk];
+    Inst *tab;
+    int first, n;
+};
+
+// writes instance records into the device table (records travel as kernel
+// arguments, so a step needs no host-to-device copy and can be captured)
+__global__ void k_pack(PackArgs a)
+{
+    const int t = threadIdx.x;
+    if (t < a.n) a.tab[a.first + t] = a.rec[t];
+}
+
+__device__ __forceinline__ const Inst &find_inst(const Inst *tab, int count, int slot, idx_t gb,
+                                                 idx_t &lb)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].start[slot] <= gb) lo = mid; else hi = mid - 1;
+    }
+    lb = gb - tab[lo].start[slot];
+    return tab[lo];
+}
+
+__device__ __forceinline__ StateP const_view(const StateW &w)
+{
+    StateP p;
+    for (int f = 0; f < 5; ++f) p.u[f] = w.u[f];
+    for (int d = 0; d < 3; ++d) p.b[d] = w.b[d];
+    return p;
+}
+
+// half = 0: primitives of U^n, 1: of U^{n+1/2}
+__global__ void __launch_bounds__(kBlock) kb_prims(const Inst *tab, int count, idx_t total,
+                                                   int half)
+{
+    const idx_t gb = xcd_block(total);
+    if (gb >= total) return;
+    idx_t lb;
+    const Inst &I = find_inst(tab, count, kSlotPrims, gb, lb);
+    const Geom g = I.g;
+    const StateP st = half ? const_view(I.half) : I.in;
+    const Prims P = I.P;
+    prims_body(g, st, P, I.status, lb);
+}
+
+// half = 0: predictor on U^n, 1: PCM corrector on U^{n+1/2}
+template <int D>
+__global__ void __launch_bounds__(kBlock) kb_flux_pcm(const Inst *tab, int count, idx_t total,
+                                                      int half)
+{
+    const idx_t gb = xcd_block(total);
+    if (gb >= total) return;
+    idx_t lb;
+    const Inst &I = find_inst(tab, count, kSlotFlux0 + D, gb, lb);
+    const Geom g = I.g;
+    const StateP st = half ? const_view(I.half) : I.in;
+    const Prims P = I.P;
+    const Flux F = I.F;
+    flux_pcm_body<D, VLCT_RECON_PCM>(g, st, P, F, I.status, lb);
+}
+
+template <int RECON>
+__global__ void __launch_bounds__(kBlock) kb_recon_x(const Inst *tab, int count, idx_t total)
+{
+    const idx_t gb = xcd_block(total);
+    if (gb >= total) return;
+    idx_t lb;
+    const Inst &I = find_inst(tab, count, kSlotRow, gb, lb);
+    const Geom g = I.g;
+    const StateP st = const_view(I.half);
+    const Prims P = I.P;
+    const Flux F = I.F;
+    recon_x_body<RECON>(g, st, P, F, I.status, lb);
+}
+
+template <int D, int RECON>
+__global__ void __launch_bounds__(kBlock) kb_march(const Inst *tab, int count, idx_t total)
+{
+    const idx_t gb = xcd_block(total);
+    if (gb >= total) return;
+    idx_t lb;
+    const Inst &I = find_inst(tab, count, D == 1 ? kSlotMarch1 : kSlotMarch2, gb, lb);
+    const Geom g = I.g;
+    const StateP st = const_view(I.half);
+    const Prims P = I.P;
+    const Flux F = I.F;
+    march_body<D, RECON>(g, st, P, F, I.status, lb);
+}
+
+template <bool FULL>
+__global__ void __launch_bounds__(kCt) kb_ct(const Inst *tab, int count, idx_t total)
+{
+    const idx_t gb = xcd_block(total);
+    if (gb >= total) return;
+    idx_t lb;
+    const Inst &I = find_inst(tab, count, kSlotCt, gb, lb);
+    const Geom g = I.g;
+    const Prims P = I.P;
+    const Flux F = I.F;
+    const StateP base = I.in;
+    const StateW out = FULL ? I.out : I.half;
+    ct_body<FULL>(g, P, F, base, out, I.dt, I.status, lb);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_dt_partial(const Inst *tab, int count, idx_t total)
+{
+    // no XCD remap: the partial of block lb is written to partial[lb]
+    const idx_t gb = blockIdx.x;
+    if (gb >= total) return;
+    idx_t lb;
+    const Inst &I = find_inst(tab, count, kSlotDt, gb, lb);
+    const Geom g = I.g;
+    dt_partial_body(g, const_view(I.out), I.partial, I.status, lb);
+}
+
+// one block per instance: dt = cfl / max over that instance's partials
+__global__ void __launch_bounds__(1024) kb_dt_final(const Inst *tab)
+{
+    const Inst &I = tab[blockIdx.x];
+    const int n = (int)nblk_dt(I.g);
+    __shared__ double red[1024 / 64];
+    double m = 0.0;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) m = fmax(m, I.partial[q]);
+    m = wave_max(m);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) red[wv] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = red[0];
+        for (int q = 1; q < (int)(blockDim.x / 64); ++q) b = fmax(b, red[q]);
+        I.next_dt[0] = I.g.cfl / b;
     }
 }
 
@@ -812,36 +1055,29 @@ static StateW as_mut(const vlct_state *s)
 static int launch_stage_fluxes(const Geom &g, const StateP &st, const Bound &B, int recon,
                                uint32_t *status, hipStream_t s)
 {
-    const size_t np = (size_t)g.p[0] * g.p[1] * g.p[2];
     {
         Observe o(VLCT_KERNEL_PRIMS, s);
-        k_prims<<<xcd_grid(nblocks(np)), kBlock, 0, s>>>(g, st, B.P, status);
-    }
-    size_t nf[3];
-    for (int d = 0; d < 3; ++d)
-        nf[d] = (size_t)flux_dim(g.n, d, 0) * flux_dim(g.n, d, 1) * flux_dim(g.n, d, 2);
-    const int kid = recon == VLCT_RECON_PCM ? VLCT_KERNEL_FLUX_PCM : VLCT_KERNEL_FLUX_RECON;
-#define VLCT_FLUX(D, R)                                                            \
-    {                                                                              \
-        Observe o(kid, s);                                                         \
-        k_flux<D, R><<<xcd_grid(nblocks(nf[D])), kBlock, 0, s>>>(g, st, B.P, B.F, status); \
+        k_prims<<<xcd_grid(nblk_prims(g)), kBlock, 0, s>>>(g, st, B.P, status);
     }
     if (recon == VLCT_RECON_PCM) {
-        VLCT_FLUX(0, VLCT_RECON_PCM) VLCT_FLUX(1, VLCT_RECON_PCM) VLCT_FLUX(2, VLCT_RECON_PCM)
+        // predictor: one thread per face
+#define VLCT_FLUX(D)                                                                      \
+    {                                                                                     \
+        Observe o(VLCT_KERNEL_FLUX_PCM, s);                                               \
+        k_flux<D, VLCT_RECON_PCM><<<xcd_grid(nblk_flux(g, D)), kBlock, 0, s>>>(g, st, B.P, B.F, \
+                                                                                status);  \
+    }
+        VLCT_FLUX(0) VLCT_FLUX(1) VLCT_FLUX(2)
+#undef VLCT_FLUX
     } else {
-        // one reconstruction per cell and axis
-        const size_t items_x = (size_t)(g.n[0] + 2) * (g.n[1] + 2) * (g.n[2] + 2);
-        const unsigned gx = xcd_grid((items_x - 1 + kRowFaces - 1) / kRowFaces);
-        auto march_grid = [&](int D) {
-            const int T = D == 1 ? 2 : 1;
-            const size_t cols = (size_t)(g.n[0] + 2) * (g.n[T] + 2);
-            return xcd_grid(((cols + kBlock - 1) / kBlock) * ((g.n[D] + 1 + kMarch - 1) / kMarch));
-        };
+        // corrector: one reconstruction per cell and axis, x by rows, y and z
+        // by column marches
+        const int kid = VLCT_KERNEL_FLUX_RECON;
 #define VLCT_RECON3(R)                                                                        \
     {                                                                                         \
-        { Observe o(kid, s); k_flux_recon_x<R><<<gx, kBlock, 0, s>>>(g, st, B.P, B.F, status); } \
-        { Observe o(kid, s); k_flux_recon_march<1, R><<<march_grid(1), kBlock, 0, s>>>(g, st, B.P, B.F, status); } \
-        { Observe o(kid, s); k_flux_recon_march<2, R><<<march_grid(2), kBlock, 0, s>>>(g, st, B.P, B.F, status); } \
+        { Observe o(kid, s); k_flux_recon_x<R><<<xcd_grid(nblk_row(g)), kBlock, 0, s>>>(g, st, B.P, B.F, status); } \
+        { Observe o(kid, s); k_flux_recon_march<1, R><<<xcd_grid(nblk_march(g, 1)), kBlock, 0, s>>>(g, st, B.P, B.F, status); } \
+        { Observe o(kid, s); k_flux_recon_march<2, R><<<xcd_grid(nblk_march(g, 2)), kBlock, 0, s>>>(g, st, B.P, B.F, status); } \
     }
         switch (recon) {
         case VLCT_RECON_PLMC: VLCT_RECON3(VLCT_RECON_PLMC) break;
@@ -851,7 +1087,6 @@ static int launch_stage_fluxes(const Geom &g, const StateP &st, const Bound &B, 
         }
 #undef VLCT_RECON3
     }
-#undef VLCT_FLUX
     return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
 }
 
@@ -863,6 +1098,72 @@ static int launch_dt(const Geom &g, const StateP &st, const Bound &B, const Layo
     k_dt_partial<<<nblocks(N), kBlock, 0, s>>>(g, st, B.partial, status);
     k_dt_final<<<1, 1024, 0, s>>>(B.partial, (int)L.npartial, g.cfl, dt_out);
     return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
+}
+
+constexpr int kMaxBatch = 1 << 16;
+
+static size_t batch_table_bytes(int count) { return align_up((size_t)count * sizeof(Inst)); }
+
+// instance records with workspace regions and flattened block offsets;
+// returns the per-slot block totals through `total`
+static void batch_records(int count, const vlct_grid *grids, const vlct_state *in,
+                          const vlct_state *out, const double *dt_dev, double *next_dt_dev,
+                          uint32_t *status_dev, void *ws, std::vector<Inst> &rec,
+                          idx_t total[kSlots])
+{
+    rec.resize(count);
+    size_t off = batch_table_bytes(count);
+    for (int s = 0; s < kSlots; ++s) total[s] = 0;
+    for (int i = 0; i < count; ++i) {
+        const Geom g = make_geom(&grids[i]);
+        const Layout L = layout(g);
+        const Bound B = bind(L, static_cast<char *>(ws) + off);
+        off += L.total;
+        Inst &r = rec[i];
+        r.g = g;
+        r.in = as_const(&in[i]);
+        r.out = as_mut(&out[i]);
+        r.half = B.half;
+        r.P = B.P;
+        r.F = B.F;
+        r.partial = B.partial;
+        r.dt = dt_dev + i;
+        r.next_dt = next_dt_dev ? next_dt_dev + i : nullptr;
+        r.status = status_dev ? status_dev + i : nullptr;
+        const idx_t nb[kSlots] = {nblk_prims(g), nblk_flux(g, 0), nblk_flux(g, 1), nblk_flux(g, 2),
+                                  nblk_row(g), nblk_march(g, 1), nblk_march(g, 2), nblk_ct(g),
+                                  nblk_dt(g)};
+        for (int s = 0; s < kSlots; ++s) {
+            r.start[s] = total[s];
+            total[s] += nb[s];
+        }
+    }
+}
+
+// every output array belongs to one instance, and an input array is shared
+// only with the same field of its own instance's output (in-place)
+static bool batch_aliasing_ok(int count, const vlct_state *in, const vlct_state *out)
+{
+    std::unordered_map<const void *, long> owner;  // pointer -> instance * 8 + field
+    auto fields = [](const vlct_state &st, int f) -> const void * {
+        const double *p[8] = {st.rho, st.mx, st.my, st.mz, st.E, st.bx, st.by, st.bz};
+        return p[f];
+    };
+    for (int i = 0; i < count; ++i)
+        for (int f = 0; f < 8; ++f)
+            if (!owner.emplace(fields(out[i], f), (long)i * 8 + f).second) return false;
+    for (int i = 0; i < count; ++i)
+        for (int f = 0; f < 8; ++f) {
+            auto it = owner.find(fields(in[i], f));
+            if (it != owner.end() && it->second != (long)i * 8 + f) return false;
+        }
+    // an instance is either fully in place or fully out of place
+    for (int i = 0; i < count; ++i) {
+        int same = 0;
+        for (int f = 0; f < 8; ++f) same += fields(in[i], f) == fields(out[i], f);
+        if (same != 0 && same != 8) return false;
+    }
+    return true;
 }
 
 }  // namespace vlct
@@ -910,10 +1211,7 @@ int vlct_step(const vlct_grid *vg, const vlct_state *in, const vlct_state *out,
     const Bound B = bind(L, ws);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const StateP sin = as_const(in);
-    const int ntx = (g.n[0] + (g.bc[0] == VLCT_BC_OUTFLOW) + kTx - 1) / kTx;
-    const int nty = (g.n[1] + (g.bc[1] == VLCT_BC_OUTFLOW) + kTy - 1) / kTy;
-    const int ntz = (g.n[2] + kTz - 1) / kTz;
-    const unsigned gct = xcd_grid((size_t)ntx * nty * ntz);
+    const unsigned gct = xcd_grid(nblk_ct(g));
 
     // predictor (Steps 2-5)
     int rc = launch_stage_fluxes(g, sin, B, VLCT_RECON_PCM, status_dev, s);
@@ -954,6 +1252,106 @@ int vlct_set_launch_observer(vlct_launch_observer cb, void *user)
     g_observer = cb;
     g_observer_user = user;
     return VLCT_OK;
+}
+
+size_t vlct_batch_workspace_bytes(const vlct_grid *grids, int count)
+{
+    if (!grids || count < 1 || count > kMaxBatch) return 0;
+    size_t tot = batch_table_bytes(count);
+    for (int i = 0; i < count; ++i) {
+        if (!grid_ok(&grids[i])) return 0;
+        tot += layout(make_geom(&grids[i])).total;
+    }
+    return tot;
+}
+
+int vlct_step_batch(int count, const vlct_grid *grids, const vlct_state *in,
+                    const vlct_state *out, const double *dt_dev, double *next_dt_dev,
+                    uint32_t *status_dev, void *ws, size_t ws_bytes, void *stream)
+{
+    if (count < 1 || count > kMaxBatch || !grids || !in || !out || !dt_dev) return VLCT_EINVAL;
+    for (int i = 0; i < count; ++i)
+        if (!grid_ok(&grids[i]) || !state_ok(&in[i]) || !state_ok(&out[i])) return VLCT_EINVAL;
+    for (int i = 1; i < count; ++i)
+        if (grids[i].recon != grids[0].recon) return VLCT_EUNSUPPORTED;
+    if (!batch_aliasing_ok(count, in, out)) return VLCT_EINVAL;
+    const size_t need = vlct_batch_workspace_bytes(grids, count);
+    if (!ws || ws_bytes < need) return VLCT_EWORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<Inst> rec;
+    idx_t tot[kSlots];
+    batch_records(count, grids, in, out, dt_dev, next_dt_dev, status_dev, ws, rec, tot);
+    Inst *tab = static_cast<Inst *>(ws);
+    for (int first = 0; first < count; first += kPackChunk) {
+        PackArgs a;
+        a.tab = tab;
+        a.first = first;
+        a.n = std::min(kPackChunk, count - first);
+        for (int q = 0; q < a.n; ++q) a.rec[q] = rec[first + q];
+        k_pack<<<1, 64, 0, s>>>(a);
+    }
+    const int recon = grids[0].recon;
+    // predictor (Steps 2-5)
+    {
+        Observe o(VLCT_KERNEL_PRIMS, s);
+        kb_prims<<<xcd_grid(tot[kSlotPrims]), kBlock, 0, s>>>(tab, count, tot[kSlotPrims], 0);
+    }
+    {
+        Observe o(VLCT_KERNEL_FLUX_PCM, s);
+        kb_flux_pcm<0><<<xcd_grid(tot[kSlotFlux0]), kBlock, 0, s>>>(tab, count, tot[kSlotFlux0], 0);
+    }
+    {
+        Observe o(VLCT_KERNEL_FLUX_PCM, s);
+        kb_flux_pcm<1><<<xcd_grid(tot[kSlotFlux1]), kBlock, 0, s>>>(tab, count, tot[kSlotFlux1], 0);
+    }
+    {
+        Observe o(VLCT_KERNEL_FLUX_PCM, s);
+        kb_flux_pcm<2><<<xcd_grid(tot[kSlotFlux2]), kBlock, 0, s>>>(tab, count, tot[kSlotFlux2], 0);
+    }
+    {
+        Observe o(VLCT_KERNEL_UPDATE_HALF, s);
+        kb_ct<false><<<xcd_grid(tot[kSlotCt]), kCt, 0, s>>>(tab, count, tot[kSlotCt]);
+    }
+    // corrector (Steps 6-9)
+    {
+        Observe o(VLCT_KERNEL_PRIMS, s);
+        kb_prims<<<xcd_grid(tot[kSlotPrims]), kBlock, 0, s>>>(tab, count, tot[kSlotPrims], 1);
+    }
+#define VLCT_BRECON(R)                                                                        \
+    {                                                                                         \
+        { Observe o(VLCT_KERNEL_FLUX_RECON, s);                                                \
+          kb_recon_x<R><<<xcd_grid(tot[kSlotRow]), kBlock, 0, s>>>(tab, count, tot[kSlotRow]); } \
+        { Observe o(VLCT_KERNEL_FLUX_RECON, s);                                                \
+          kb_march<1, R><<<xcd_grid(tot[kSlotMarch1]), kBlock, 0, s>>>(tab, count, tot[kSlotMarch1]); } \
+        { Observe o(VLCT_KERNEL_FLUX_RECON, s);                                                \
+          kb_march<2, R><<<xcd_grid(tot[kSlotMarch2]), kBlock, 0, s>>>(tab, count, tot[kSlotMarch2]); } \
+    }
+    switch (recon) {
+    case VLCT_RECON_PCM:
+        for (int d = 0; d < 3; ++d) {
+            Observe o(VLCT_KERNEL_FLUX_PCM, s);
+            const idx_t n = tot[kSlotFlux0 + d];
+            if (d == 0) kb_flux_pcm<0><<<xcd_grid(n), kBlock, 0, s>>>(tab, count, n, 1);
+            if (d == 1) kb_flux_pcm<1><<<xcd_grid(n), kBlock, 0, s>>>(tab, count, n, 1);
+            if (d == 2) kb_flux_pcm<2><<<xcd_grid(n), kBlock, 0, s>>>(tab, count, n, 1);
+        }
+        break;
+    case VLCT_RECON_PLMC: VLCT_BRECON(VLCT_RECON_PLMC) break;
+    case VLCT_RECON_PPMC: VLCT_BRECON(VLCT_RECON_PPMC) break;
+    case VLCT_RECON_PLMP: VLCT_BRECON(VLCT_RECON_PLMP) break;
+    default: VLCT_BRECON(VLCT_RECON_PPMP) break;
+    }
+#undef VLCT_BRECON
+    {
+        Observe o(VLCT_KERNEL_UPDATE_FULL, s);
+        kb_ct<true><<<xcd_grid(tot[kSlotCt]), kCt, 0, s>>>(tab, count, tot[kSlotCt]);
+    }
+    if (next_dt_dev) {
+        Observe o(VLCT_KERNEL_DT, s);
+        kb_dt_partial<<<(unsigned)tot[kSlotDt], kBlock, 0, s>>>(tab, count, tot[kSlotDt]);
+        kb_dt_final<<<count, 1024, 0, s>>>(tab);
+    }
+    return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
 }
 
 const char *vlct_kernel_name(int kernel)

@@ -90,3 +90,63 @@ class Stepper:
 
     def status_bits(self) -> int:
         return int(self.status.item())
+
+
+class BatchStepper:
+    """Independent instances advanced together by vlct_step_batch (one launch
+    per kernel for all of them); per-instance dt, next dt and status live in
+    device arrays of len(grids) elements."""
+
+    def __init__(self, grids, device: str = "cuda:0", inplace: bool = False):
+        torch = _torch()
+        self.grids = list(grids)
+        n = len(self.grids)
+        self.device = device
+        self.cgs = [vlct.make_grid(g) for g in self.grids]
+        self.ws_bytes = vlct.vlct_batch_workspace_bytes(self.cgs)
+        if self.ws_bytes == 0:
+            raise ValueError("invalid grid descriptors")
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.cur = [DeviceState(g, device) for g in self.grids]
+        self.nxt = self.cur if inplace else [DeviceState(g, device) for g in self.grids]
+        self.dt = torch.zeros(n, dtype=torch.float64, device=device)
+        self.next_dt = torch.zeros(n, dtype=torch.float64, device=device)
+        self.status = torch.zeros(n, dtype=torch.int32, device=device)
+
+    def stream(self) -> int:
+        return _torch().cuda.current_stream().cuda_stream
+
+    def upload(self, states):
+        for d, s in zip(self.cur, states):
+            d.upload(s)
+        return self
+
+    def download(self):
+        return [d.download() for d in self.cur]
+
+    def set_dt(self, dts) -> None:
+        torch = _torch()
+        self.dt.copy_(torch.tensor([float(x) for x in dts], dtype=torch.float64))
+
+    def compute_dt(self) -> None:
+        """CFL step of every instance (one vlct_cfl_dt each; the batch
+        workspace is larger than any single instance needs)."""
+        for i, (cg, d) in enumerate(zip(self.cgs, self.cur)):
+            rc = vlct.vlct_cfl_dt(cg, d.c_state(), self.dt.data_ptr() + 8 * i,
+                                  self.ws.data_ptr(), self.ws_bytes, self.stream())
+            if rc:
+                raise vlct.VlctError(rc, "vlct_cfl_dt")
+
+    def step(self) -> None:
+        """One step of every instance; afterwards self.dt holds the next CFL steps."""
+        rc = vlct.vlct_step_batch(self.cgs, [d.c_state() for d in self.cur],
+                                  [d.c_state() for d in self.nxt], self.dt.data_ptr(),
+                                  self.next_dt.data_ptr(), self.status.data_ptr(),
+                                  self.ws.data_ptr(), self.ws_bytes, self.stream())
+        if rc:
+            raise vlct.VlctError(rc, "vlct_step_batch")
+        self.cur, self.nxt = self.nxt, self.cur
+        self.dt, self.next_dt = self.next_dt, self.dt
+
+    def status_bits(self):
+        return [int(x) for x in self.status.cpu()]

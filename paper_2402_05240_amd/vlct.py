@@ -29,7 +29,8 @@ VLCT_STATUS_DENSITY_FLOOR = 2
 VLCT_STATUS_NONFINITE = 4
 
 EXPORTED = ("vlct_workspace_bytes", "vlct_cfl_dt", "vlct_step", "vlct_strerror",
-            "vlct_abi_version", "vlct_set_launch_observer", "vlct_kernel_name")
+            "vlct_abi_version", "vlct_set_launch_observer", "vlct_kernel_name",
+            "vlct_batch_workspace_bytes", "vlct_step_batch")
 
 VLCT_KERNEL_PRIMS = 0
 VLCT_KERNEL_FLUX_PCM = 1
@@ -83,6 +84,13 @@ def load(path: str = LIB_PATH):
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                   ctypes.c_void_p]
         lib.vlct_step.restype = ctypes.c_int
+        lib.vlct_batch_workspace_bytes.argtypes = [ctypes.POINTER(vlct_grid), ctypes.c_int]
+        lib.vlct_batch_workspace_bytes.restype = ctypes.c_size_t
+        lib.vlct_step_batch.argtypes = [ctypes.c_int, ctypes.POINTER(vlct_grid),
+                                        ctypes.POINTER(vlct_state), ctypes.POINTER(vlct_state),
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        lib.vlct_step_batch.restype = ctypes.c_int
         lib.vlct_strerror.argtypes = [ctypes.c_int]
         lib.vlct_strerror.restype = ctypes.c_char_p
         lib.vlct_abi_version.argtypes = []
@@ -129,6 +137,24 @@ def vlct_step(grid: vlct_grid, state_in: vlct_state, state_out: vlct_state, dt_d
     return int(load().vlct_step(ctypes.byref(grid), ctypes.byref(state_in),
                                 ctypes.byref(state_out), dt_dev, next_dt_dev, status_dev, ws,
                                 ws_bytes, stream))
+
+
+def vlct_batch_workspace_bytes(grids) -> int:
+    """grids: sequence of vlct_grid."""
+    arr = (vlct_grid * len(grids))(*grids)
+    return int(load().vlct_batch_workspace_bytes(arr, len(grids)))
+
+
+def vlct_step_batch(grids, states_in, states_out, dt_dev: int, next_dt_dev: int,
+                    status_dev: int, ws: int, ws_bytes: int, stream: int) -> int:
+    """grids, states_in, states_out: sequences of vlct_grid / vlct_state (host
+    descriptors); dt_dev, next_dt_dev, status_dev: device arrays of len(grids)."""
+    n = len(grids)
+    g = (vlct_grid * n)(*grids)
+    a = (vlct_state * n)(*states_in)
+    b = (vlct_state * n)(*states_out)
+    return int(load().vlct_step_batch(n, g, a, b, dt_dev, next_dt_dev, status_dev, ws, ws_bytes,
+                                      stream))
 
 
 def vlct_strerror(code: int) -> str:

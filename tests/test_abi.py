@@ -76,6 +76,39 @@ def test_workspace_and_pointer_validation():
     assert vlct.vlct_step(g, fake, other, 64, 0, 0, 128, need, 0) == vlct.VLCT_EINVAL
 
 
+def test_batch_validation():
+    """vlct_step_batch rejects bad calls on the host, before any launch."""
+    _lib()
+    g1, g2 = _grid(), _grid(nx=12, ny=5, nz=7, bc=(1, 0, 1))
+    assert vlct.vlct_batch_workspace_bytes([]) == 0
+    one = vlct.vlct_batch_workspace_bytes([g1])
+    two = vlct.vlct_batch_workspace_bytes([g1, g2])
+    assert two > one > vlct.vlct_workspace_bytes(g1)
+    assert two >= vlct.vlct_workspace_bytes(g1) + vlct.vlct_workspace_bytes(g2)
+    assert vlct.vlct_batch_workspace_bytes([g1, _grid(nx=0)]) == 0
+
+    def st(base):
+        return vlct.make_state([base + 4096 * f for f in range(8)])
+    a, b, c, d = st(1 << 20), st(2 << 20), st(3 << 20), st(4 << 20)
+    ws = 1 << 30
+    # empty batch, NULL dt, invalid member
+    assert vlct.vlct_step_batch([], [], [], 64, 0, 0, ws, two, 0) == vlct.VLCT_EINVAL
+    assert vlct.vlct_step_batch([g1, g2], [a, b], [c, d], 0, 0, 0, ws, two, 0) == vlct.VLCT_EINVAL
+    assert vlct.vlct_step_batch([g1, _grid(dx=0.0)], [a, b], [c, d], 64, 0, 0, ws, two,
+                                0) == vlct.VLCT_EINVAL
+    # mixed reconstructions
+    assert vlct.vlct_step_batch([g1, _grid(recon=3)], [a, b], [c, d], 64, 0, 0, ws, two,
+                                0) == vlct.VLCT_EUNSUPPORTED
+    # an output shared by two instances, an input that is another instance's output
+    assert vlct.vlct_step_batch([g1, g2], [a, b], [c, c], 64, 0, 0, ws, two, 0) == vlct.VLCT_EINVAL
+    assert vlct.vlct_step_batch([g1, g2], [a, c], [c, d], 64, 0, 0, ws, two, 0) == vlct.VLCT_EINVAL
+    # workspace missing or short
+    assert vlct.vlct_step_batch([g1, g2], [a, b], [c, d], 64, 0, 0, 0, two,
+                                0) == vlct.VLCT_EWORKSPACE
+    assert vlct.vlct_step_batch([g1, g2], [a, b], [c, d], 64, 0, 0, ws, two - 1,
+                                0) == vlct.VLCT_EWORKSPACE
+
+
 def test_strerror_covers_codes():
     _lib()
     for c in range(5):
