@@ -173,6 +173,9 @@ def cpu_baseline(g, s, planes: int, steps: int, threads: int):
                           steps, g.nx, g.ny, planes, sec, threads)}
 
 
+BASELINE_METRIC = "FP64 cell updates/s (PLMC+HLLD, 256^3); % HBM peak; adjoint/forward cost"
+
+
 def load_traffic(workload):
     """Per-launch HBM bytes of each kernel family from the committed counter
     summary, when it was taken on this workload with these kernel sources."""
@@ -323,6 +326,54 @@ def summarize_trace(stats_csv, workload, command, out_dir):
     return path
 
 
+def ensemble_bench(count, steps, warmup):
+    """Config-4-style ensemble (`count` independent linear-wave runs of 16..96
+    cells per axis): one vlct_step_batch per step against the same instances
+    stepped one after another with vlct_step, both on the current stream with
+    dt chained on the device; the two must agree bit for bit."""
+    import numpy as np
+    import torch
+    from paper_2402_05240_amd import inputs as I
+    from paper_2402_05240_amd.device import BatchStepper, Stepper
+    ens = I.ensemble(count)
+    grids = [g for g, _, _ in ens]
+    states = [s for _, s, _ in ens]
+    ncell = sum(g.ncells for g in grids)
+    bs = BatchStepper(grids).upload(states)
+    bs.compute_dt()
+    singles = [Stepper(g).upload(s) for g, s in zip(grids, states)]
+    for st in singles:
+        st.compute_dt()
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(k):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / k
+
+    def seq_step():
+        for st in singles:
+            st.step()
+    for _ in range(warmup):
+        bs.step()
+        seq_step()
+    ms_batch = timed(bs.step, steps)
+    ms_seq = timed(seq_step, steps)
+    outs = bs.download()
+    same = all(np.array_equal(o[f], st.download()[f]) for o, st in zip(outs, singles)
+               for f in I.FIELDS)
+    return {"workload": "ensemble_linear_%d" % count, "instances": count,
+            "cells": ncell, "sizes": "16..96 per axis, non-cubic",
+            "recon": "PLMC", "steps": steps, "warmup": warmup,
+            "batched": {"ms_per_step": ms_batch, "cell_updates_per_s": ncell / (ms_batch * 1e-3)},
+            "sequential": {"ms_per_step": ms_seq, "cell_updates_per_s": ncell / (ms_seq * 1e-3)},
+            "speedup": ms_seq / ms_batch, "bitwise_equal": bool(same)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,6 +381,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="turbulence_plmc_256", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true",
+                    help="skip the batched-ensemble measurement (64 small runs)")
+    ap.add_argument("--ensemble-steps", type=int, default=10)
     ap.add_argument("--cpu-planes", type=int, default=256)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--cpu-threads", type=int, default=0)
@@ -441,8 +495,11 @@ def main():
         "wall_ms_per_step": (w1 - w0) * 1e3 / args.steps,
         "status": status,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_ensemble:
         del st
+        torch.cuda.empty_cache()
+        out["ensemble"] = ensemble_bench(64, args.ensemble_steps, 2)
+    if not args.no_cpu_baseline:
         torch.cuda.empty_cache()
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(g, s0, args.cpu_planes, args.cpu_steps, threads)

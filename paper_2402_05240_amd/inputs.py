@@ -515,6 +515,31 @@ def riemann(left, right, bn, gamma, n=128, axis=0, flip=False, transverse=4,
 
 
 # --------------------------------------------------------------------------
+# ensembles of independent small runs (batched stepping)
+# --------------------------------------------------------------------------
+
+def ensemble(count=64, seed=2402, nmin=16, nmax=96, recon=RECON_PLMC, cfl=0.4):
+    """`count` independent periodic linear-wave problems: sizes drawn uniformly
+    from nmin..nmax per axis (non-cubic), gamma uniform in [1.4, 5/3], the fast,
+    slow or Alfven family, a random grid-oblique direction (integer wavevector
+    with components in {-1, 0, 1}), amplitude log-uniform in [1e-6, 1e-4].
+    Returns [(grid, state, period)]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = tuple(int(v) for v in rng.integers(nmin, nmax + 1, size=3))
+        gamma = float(rng.uniform(1.4, 5.0 / 3.0))
+        wave = ("fast", "slow", "alfven")[int(rng.integers(0, 3))]
+        while True:
+            kvec = tuple(int(v) for v in rng.integers(-1, 2, size=3))
+            if any(kvec):
+                break
+        amp = float(10.0 ** rng.uniform(-6.0, -4.0))
+        out.append(oblique_wave(n, wave, amp=amp, kvec=kvec, gamma=gamma, recon=recon, cfl=cfl))
+    return out
+
+
+# --------------------------------------------------------------------------
 # named workloads
 # --------------------------------------------------------------------------
 
