@@ -109,3 +109,36 @@ def test_batch_inplace_equals_out_of_place():
     for a, b in zip(*res):
         for f in FIELDS:
             assert np.array_equal(a[f], b[f]), f
+
+
+def test_batch_steps_replayed_from_hip_graph():
+    """Two batched steps captured into one graph (A -> B -> A) and replayed
+    three times, with eager work and a synchronisation between replays; every
+    replay equals eager stepping bit for bit."""
+    _need_gpu()
+    from paper_2402_05240_amd.device import BatchStepper
+    import torch
+    inst = _instances(2)[:4]
+    grids = [g for g, _ in inst]
+    dts = [ref.cfl_dt(g, s) for g, s in inst]
+    eager = BatchStepper(grids).upload([s for _, s in inst])
+    eager.set_dt(dts)
+    graphed = BatchStepper(grids).upload([s for _, s in inst])
+    graphed.set_dt(dts)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        graphed.step()
+        graphed.step()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        _say("replay %d" % rep)
+        graph.replay()
+        eager.step()
+        eager.step()
+        torch.cuda.synchronize()
+        a, b = graphed.download(), eager.download()
+        for q in range(len(inst)):
+            for f in FIELDS:
+                assert np.array_equal(a[q][f], b[q][f]), (rep, q, f)
+        assert torch.equal(graphed.dt, eager.dt)
