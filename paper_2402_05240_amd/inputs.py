@@ -324,6 +324,108 @@ def field_loop_2d(n=32, amp=1e-3, radius=0.3, v=(2.0, 1.0, 0.0), rho=1.0, p=1.0,
 
 
 # --------------------------------------------------------------------------
+# circularly polarised Alfven wave (Sec. 3.1.2), Orszag-Tang vortex (Sec. 3.1.6),
+# tilted spherical field loop (Sec. 3.1.3)
+# --------------------------------------------------------------------------
+
+def _centres(g: Grid, origin=(0.0, 0.0, 0.0), off=(0.5, 0.5, 0.5)):
+    """Physical coordinates (x, y, z) broadcastable to (nz, ny, nx) of the points
+    at index offsets `off` (0.5 = cell centre, 0 = lower face)."""
+    x = origin[0] + (np.arange(g.nx) + off[0]) * g.dx
+    y = origin[1] + (np.arange(g.ny) + off[1]) * g.dy
+    z = origin[2] + (np.arange(g.nz) + off[2]) * g.dz
+    return x[None, None, :], y[None, :, None], z[:, None, None]
+
+
+def cpaw(N=16, standing=False, amp=0.1, wavelength=1.0, gamma=5.0 / 3.0, recon=RECON_PLMC,
+         cfl=0.4) -> Tuple[Grid, State, float]:
+    """Circularly polarised Alfven wave on the periodic 3.0 x 1.5 x 1.5 box at
+    2N x N x N.  In the wave frame rho = 1, P = 0.1, v = (v_par, A sin phi,
+    A cos phi), B = (1, A sin phi, A cos phi), phi = 2 pi x1 / lambda, with v_par
+    = 0 (travelling) or -1 (standing).  The wave frame is the lab frame rotated
+    by sin(alpha) = 2/3, sin(beta) = 2/sqrt(5), so the wave vector
+    (1/3, 2/3, 2/3) fits the box once along every axis.  The field perturbation
+    comes from an edge-centred vector potential.  Returns (grid, state, period)."""
+    g = Grid(2 * N, N, N, 3.0 / (2 * N), 1.5 / N, 1.5 / N, gamma, cfl, recon, (0, 0, 0))
+    sa, ca = 2.0 / 3.0, math.sqrt(5.0) / 3.0
+    sb, cb = 2.0 / math.sqrt(5.0), 1.0 / math.sqrt(5.0)
+    e1 = np.array([ca * cb, ca * sb, sa])
+    e2 = np.array([-sb, cb, 0.0])
+    e3 = np.array([-sa * cb, -sa * sb, ca])
+    kw = 2.0 * math.pi / wavelength
+
+    def phase(off):
+        x, y, z = _centres(g, off=off)
+        return kw * (e1[0] * x + e1[1] * y + e1[2] * z)
+    ph = phase((0.5, 0.5, 0.5))
+    rho, p, b1 = 1.0, 0.1, 1.0
+    vpar = -1.0 if standing else 0.0
+    s = empty_state(g)
+    v = [vpar * e1[c] + amp * (np.sin(ph) * e2[c] + np.cos(ph) * e3[c]) for c in range(3)]
+    s["rho"] = np.full(g.shape, rho)
+    s["mx"], s["my"], s["mz"] = rho * v[0], rho * v[1], rho * v[2]
+    a = amp / kw       # curl of a (sin phi e2 + cos phi e3) = A (sin phi e2 + cos phi e3)
+    ax = a * (np.sin(phase((0.5, 0.0, 0.0))) * e2[0] + np.cos(phase((0.5, 0.0, 0.0))) * e3[0])
+    ay = a * (np.sin(phase((0.0, 0.5, 0.0))) * e2[1] + np.cos(phase((0.0, 0.5, 0.0))) * e3[1])
+    az = a * (np.sin(phase((0.0, 0.0, 0.5))) * e2[2] + np.cos(phase((0.0, 0.0, 0.5))) * e3[2])
+    ax, ay, az = (np.broadcast_to(q, g.shape).copy() for q in (ax, ay, az))
+    bxf, byf, bzf = curl_edge_potential(g, ax, ay, az)
+    s["bx"], s["by"], s["bz"] = bxf + b1 * e1[0], byf + b1 * e1[1], bzf + b1 * e1[2]
+    _periodic_face_copy(g, s)
+    s["E"] = _cell_energy(g, s["rho"], v[0], v[1], v[2], p, s["bx"], s["by"], s["bz"])
+    return g, s, wavelength / (b1 / math.sqrt(rho))
+
+
+def orszag_tang(n=(64, 64, 2), gamma=5.0 / 3.0, recon=RECON_PLMC, cfl=0.4) -> Tuple[Grid, State]:
+    """Orszag-Tang vortex on the periodic unit box (z-independent):
+    rho = 25/(36 pi), P = 5/(12 pi), v = (sin 2 pi y, -sin 2 pi x, 0) and
+    A_z = B0/(4 pi) (cos 4 pi x + 2 cos 2 pi y) with B0 = 1/sqrt(4 pi)."""
+    nx, ny, nz = n
+    g = Grid(nx, ny, nz, 1.0 / nx, 1.0 / ny, 1.0 / nz, gamma, cfl, recon, (0, 0, 0))
+    rho, p = 25.0 / (36.0 * math.pi), 5.0 / (12.0 * math.pi)
+    b0 = 1.0 / math.sqrt(4.0 * math.pi)
+    x, y, _ = _centres(g)
+    vx = np.broadcast_to(np.sin(2.0 * math.pi * y), g.shape).copy()
+    vy = np.broadcast_to(-np.sin(2.0 * math.pi * x), g.shape).copy()
+    vz = np.zeros(g.shape)
+    xe, ye, _ = _centres(g, off=(0.0, 0.0, 0.5))
+    az = np.broadcast_to(b0 / (4.0 * math.pi) * (np.cos(4.0 * math.pi * xe)
+                                                 + 2.0 * np.cos(2.0 * math.pi * ye)),
+                         g.shape).copy()
+    zero = np.zeros(g.shape)
+    s = empty_state(g)
+    s["rho"] = np.full(g.shape, rho)
+    s["mx"], s["my"], s["mz"] = rho * vx, rho * vy, rho * vz
+    s["bx"], s["by"], s["bz"] = curl_edge_potential(g, zero, zero, az)
+    s["E"] = _cell_energy(g, s["rho"], vx, vy, vz, p, s["bx"], s["by"], s["bz"])
+    return g, s
+
+
+def field_loop_3d(N=16, amp=1e-3, radius=0.3, v=(1.0, 1.0, 2.0), rho=1.0, p=1.0,
+                  gamma=5.0 / 3.0, recon=RECON_PLMC, cfl=0.4) -> Tuple[Grid, State]:
+    """Tilted spherical field loop: A_y = A_z = amp (R - r) inside r < R (r from
+    the box centre, A_x = 0), carried by v = (1, 1, 2) across the periodic
+    1 x 1 x 2 box centred at 0 on N x N x 2N cells (one period every unit of
+    time)."""
+    g = Grid(N, N, 2 * N, 1.0 / N, 1.0 / N, 1.0 / N, gamma, cfl, recon, (0, 0, 0))
+    org = (-0.5, -0.5, -1.0)
+
+    def pot(off):
+        x, y, z = _centres(g, origin=org, off=off)
+        r = np.sqrt(x * x + y * y + z * z)
+        return np.where(r < radius, amp * (radius - r), 0.0)
+    ax = np.zeros(g.shape)
+    ay = np.broadcast_to(pot((0.0, 0.5, 0.0)), g.shape).copy()
+    az = np.broadcast_to(pot((0.0, 0.0, 0.5)), g.shape).copy()
+    s = empty_state(g)
+    s["rho"] = np.full(g.shape, rho)
+    s["mx"], s["my"], s["mz"] = (np.full(g.shape, rho * v[c]) for c in range(3))
+    s["bx"], s["by"], s["bz"] = curl_edge_potential(g, ax, ay, az)
+    s["E"] = _cell_energy(g, s["rho"], v[0], v[1], v[2], p, s["bx"], s["by"], s["bz"])
+    return g, s
+
+
+# --------------------------------------------------------------------------
 # decaying MHD turbulence
 # --------------------------------------------------------------------------
 

@@ -183,6 +183,26 @@ def test_riemann_problem_to_tmax(name, axis, flip, recon):
     _check(g, s0, gpu, orc, elem=1e-9)
 
 
+@pytest.mark.parametrize("case", ["cpaw_16", "orszag_tang_32", "field_loop_16"])
+def test_validation_problem(case):
+    """The rest of the paper's validation suite: the circularly polarised
+    Alfven wave for one period (32 x 16 x 16), the Orszag-Tang vortex to
+    t = 0.5 (32 x 32 x 2) and the tilted field loop to t = 0.5 (16 x 16 x 32)."""
+    _need_gpu()
+    if case == "cpaw_16":
+        g, s0, t_end = I.cpaw(16)
+    elif case == "orszag_tang_32":
+        (g, s0), t_end = I.orszag_tang((32, 32, 2)), 0.5
+    else:
+        (g, s0), t_end = I.field_loop_3d(16), 0.5
+    _say("oracle: %s" % case)
+    orc, dts, _, st_ref = _oracle_run(g, s0, t_end=t_end)
+    _say("gpu: %d steps" % len(dts))
+    gpu, _, status = _gpu_run(g, s0, dts)
+    assert status == st_ref == 0
+    _check(g, s0, gpu, orc, elem=1e-9)
+
+
 def test_single_step_tight():
     """One step: only rounding separates the two."""
     _need_gpu()
