@@ -137,6 +137,35 @@ int vlct_step_batch(int count, const vlct_grid *grids, const vlct_state *in,
                     const vlct_state *out, const double *dt_dev, double *next_dt_dev,
                     uint32_t *status_dev, void *ws, size_t ws_bytes, void *stream);
 
+/* --- adjoint of one step --------------------------------------------------
+ * Reverse derivative of the VL+CT step of Sec. 2.2 (Steps 2-9) at the state
+ * `in`, for the step size *dt_dev held fixed:
+ *     lam_in = (d out / d in)^T lam_out
+ * where `out` is what vlct_step(g, in, out, dt_dev, ...) writes.  Each state
+ * element (cells and every stored face, the periodic duplicate face
+ * included) is one coordinate: lam_out and lam_in use the vlct_state layout
+ * of the state.  The output's duplicate face n is a copy of face 0, so its
+ * cotangent acts on face 0; the step never reads the input's duplicate face,
+ * so lam_in is zero there.  Every branch of the step (HLLD wave regions,
+ * limiter cases, CT upwind sides, floors) is taken as in the forward step at
+ * `in`; at a branch boundary the result is the one-sided derivative of the
+ * branch taken.
+ *
+ * Bytes of device workspace vlct_step_adjoint needs for this grid (0 if the
+ * descriptor is invalid).  The workspace holds the forward intermediates
+ * (primitives, fluxes, half-step state) and the cotangents of each stage. */
+size_t vlct_adjoint_workspace_bytes(const vlct_grid *g);
+
+/* Writes lam_in (device arrays, none shared with `in` or `lam_out`, else
+ * VLCT_EINVAL).  in, lam_out: device, read only.  dt_dev: device pointer to
+ * the step size.  Periodic boundaries on every axis and the PCM, PLMC and
+ * PLMP correctors only (else VLCT_EUNSUPPORTED).  VLCT_EWORKSPACE if
+ * ws_bytes < vlct_adjoint_workspace_bytes(g).  Stream-ordered; no
+ * allocation and no host synchronisation. */
+int vlct_step_adjoint(const vlct_grid *g, const vlct_state *in, const vlct_state *lam_out,
+                      const vlct_state *lam_in, const double *dt_dev, void *ws, size_t ws_bytes,
+                      void *stream);
+
 /* --- diagnostics ----------------------------------------------------------
  * Launch observer: when set, every vlct_step / vlct_cfl_dt call invokes
  * cb(user, kernel, phase, stream) on the calling host thread immediately

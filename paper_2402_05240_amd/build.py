@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libvlct.so")
-SOURCES = [os.path.join(HERE, "csrc", "vlct.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "vlct.hip"), os.path.join(HERE, "csrc", "vlct_adjoint.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # no packed-FP32 instructions in any generated code

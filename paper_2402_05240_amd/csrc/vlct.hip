@@ -15,103 +15,10 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../include/vlct.h"
+#include "vlct_common.hpp"
 #include "mhd_physics.hpp"
 
 namespace vlct {
-
-constexpr int kGhost = 3;          // ghost layers of the primitive workspace
-constexpr int kBlock = 256;        // threads per block (4 wave64s)
-constexpr int kMaxN = 4096;
-
-using idx_t = long long;
-
-// MI355X dispatches consecutive workgroups round-robin to its 8 XCDs, each with
-// its own L2.  Kernels launched on xcd_grid(n) blocks read their logical block
-// from xcd_block(n): hardware block b works on logical block
-// (b mod 8) * ceil(n/8) + b / 8, so every XCD sweeps one contiguous slab of
-// the domain and neighbouring rows and planes meet in the same L2.
-constexpr int kXcd = 8;
-__host__ __device__ __forceinline__ idx_t xcd_per(idx_t n) { return (n + kXcd - 1) / kXcd; }
-__device__ __forceinline__ idx_t xcd_block(idx_t n)
-{
-    const idx_t b = blockIdx.x;
-    return (b % kXcd) * xcd_per(n) + b / kXcd;
-}
-
-// ---------------------------------------------------------------------------
-// geometry shared by every kernel
-// ---------------------------------------------------------------------------
-struct Geom {
-    int n[3];
-    int bc[3];
-    double dl[3];
-    double gamma, gm1i, cfl;
-    int p[3];  // padded primitive dims n + 2G
-};
-
-__host__ __device__ __forceinline__ int map_cell(int i, int n, int bc)
-{
-    if (bc == VLCT_BC_PERIODIC) {
-        // one period either side without an integer division
-        if (i >= 0 && i < n) return i;
-        if (i < 0 && i >= -n) return i + n;
-        if (i >= n && i < 2 * n) return i - n;
-        const int m = i % n;
-        return m < 0 ? m + n : m;
-    }
-    return i < 0 ? 0 : (i >= n ? n - 1 : i);
-}
-// normal-face index: periodic faces wrap into [0, n-1], outflow clamps into [0, n]
-__host__ __device__ __forceinline__ int map_face(int i, int n, int bc)
-{
-    if (bc == VLCT_BC_PERIODIC) return map_cell(i, n, bc);
-    return i < 0 ? 0 : (i > n ? n : i);
-}
-
-// stored face arrays of the state: axis d has n_d + 1 faces along d
-__device__ __forceinline__ idx_t face_store(const Geom &g, int d, int i, int j, int k)
-{
-    const idx_t nx = g.n[0] + (d == 0), ny = g.n[1] + (d == 1);
-    return ((idx_t)k * ny + j) * nx + i;
-}
-
-__device__ __forceinline__ idx_t cell_store(const Geom &g, int i, int j, int k)
-{
-    return ((idx_t)k * g.n[1] + j) * g.n[0] + i;
-}
-
-// padded primitive index, i,j,k in [-G, n+G-1]
-__device__ __forceinline__ idx_t pidx(const Geom &g, int i, int j, int k)
-{
-    return ((idx_t)(k + kGhost) * g.p[1] + (j + kGhost)) * g.p[0] + (i + kGhost);
-}
-
-// flux arrays of axis d: normal index in [0, n_d], transverse in [-1, n_e]
-__host__ __device__ __forceinline__ idx_t flux_dim(const int n[3], int d, int e)
-{
-    return n[e] + (e == d ? 1 : 2);
-}
-__device__ __forceinline__ idx_t fidx(const Geom &g, int d, int i, int j, int k)
-{
-    const idx_t X = flux_dim(g.n, d, 0), Y = flux_dim(g.n, d, 1);
-    return ((idx_t)(k + (d != 2)) * Y + (j + (d != 1))) * X + (i + (d != 0));
-}
-
-struct StateP {
-    const double *u[5];
-    const double *b[3];
-};
-struct StateW {
-    double *u[5];
-    double *b[3];
-};
-struct Prims {
-    double *w[8];  // rho, vx, vy, vz, P, Bcx, Bcy, Bcz on padded cells
-};
-struct Flux {
-    double *f[3][8];  // per axis: 7 sweep-frame components + upwind indicator
-};
 
 // ---------------------------------------------------------------------------
 // logical block counts of the kernels (host launches and batch offsets)
@@ -902,49 +809,9 @@ __global__ void __launch_bounds__(1024) kb_dt_final(const Inst *tab)
 // ---------------------------------------------------------------------------
 // host side: validation, workspace carving, launches
 // ---------------------------------------------------------------------------
-static bool grid_ok(const vlct_grid *g)
-{
-    if (!g) return false;
-    const int n[3] = {g->nx, g->ny, g->nz};
-    for (int d = 0; d < 3; ++d) {
-        if (n[d] < 1 || n[d] > kMaxN) return false;
-        if (g->bc[d] != VLCT_BC_PERIODIC && g->bc[d] != VLCT_BC_OUTFLOW) return false;
-    }
-    if (!(g->dx > 0.0) || !(g->dy > 0.0) || !(g->dz > 0.0)) return false;
-    if (!(g->gamma > 1.0) || !(g->cfl > 0.0 && g->cfl <= 0.5)) return false;
-    if (g->recon < VLCT_RECON_PCM || g->recon > VLCT_RECON_PPMP) return false;
-    return true;
-}
 
-static Geom make_geom(const vlct_grid *vg)
-{
-    Geom g;
-    g.n[0] = vg->nx;
-    g.n[1] = vg->ny;
-    g.n[2] = vg->nz;
-    for (int d = 0; d < 3; ++d) {
-        g.bc[d] = vg->bc[d];
-        g.p[d] = g.n[d] + 2 * kGhost;
-    }
-    g.dl[0] = vg->dx;
-    g.dl[1] = vg->dy;
-    g.dl[2] = vg->dz;
-    g.gamma = vg->gamma;
-    g.gm1i = 1.0 / (vg->gamma - 1.0);
-    g.cfl = vg->cfl;
-    return g;
-}
 
-static size_t field_len(const int n[3], int f)
-{
-    size_t nx = n[0], ny = n[1], nz = n[2];
-    if (f < 5) return nx * ny * nz;
-    if (f == 5) return (nx + 1) * ny * nz;
-    if (f == 6) return nx * (ny + 1) * nz;
-    return nx * ny * (nz + 1);
-}
 
-static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t half[8], prims, flux[3], partial, total;
@@ -975,9 +842,6 @@ static Layout layout(const Geom &g)
     return L;
 }
 
-static unsigned nblocks(size_t work) { return (unsigned)((work + kBlock - 1) / kBlock); }
-// grid size (multiple of the XCD count) for a kernel that remaps with xcd_block
-static unsigned xcd_grid(size_t logical_blocks) { return (unsigned)(kXcd * xcd_per(logical_blocks)); }
 
 // launch observer (diagnostics, see vlct_set_launch_observer)
 static vlct_launch_observer g_observer = nullptr;
@@ -1021,63 +885,37 @@ static Bound bind(const Layout &L, void *ws)
     return B;
 }
 
-static bool state_ok(const vlct_state *s)
+
+
+int launch_prims(const Geom &g, const StateP &st, const Prims &P, uint32_t *status,
+                 hipStream_t s)
 {
-    if (!s) return false;
-    const double *p[8] = {s->rho, s->mx, s->my, s->mz, s->E, s->bx, s->by, s->bz};
-    for (int f = 0; f < 8; ++f)
-        if (!p[f]) return false;
-    return true;
+    Observe o(VLCT_KERNEL_PRIMS, s);
+    k_prims<<<xcd_grid(nblk_prims(g)), kBlock, 0, s>>>(g, st, P, status);
+    return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
 }
 
-static StateP as_const(const vlct_state *s)
+// face fluxes of a stage from its primitives P (and its stored face fields)
+int launch_fluxes(const Geom &g, const StateP &st, const Prims &P, const Flux &F, int recon,
+                  uint32_t *status, hipStream_t s)
 {
-    StateP p;
-    p.u[0] = s->rho; p.u[1] = s->mx; p.u[2] = s->my; p.u[3] = s->mz; p.u[4] = s->E;
-    p.b[0] = s->bx; p.b[1] = s->by; p.b[2] = s->bz;
-    return p;
-}
-static StateP as_const(const StateW &s)
-{
-    StateP p;
-    for (int f = 0; f < 5; ++f) p.u[f] = s.u[f];
-    for (int d = 0; d < 3; ++d) p.b[d] = s.b[d];
-    return p;
-}
-static StateW as_mut(const vlct_state *s)
-{
-    StateW p;
-    p.u[0] = s->rho; p.u[1] = s->mx; p.u[2] = s->my; p.u[3] = s->mz; p.u[4] = s->E;
-    p.b[0] = s->bx; p.b[1] = s->by; p.b[2] = s->bz;
-    return p;
-}
-
-static int launch_stage_fluxes(const Geom &g, const StateP &st, const Bound &B, int recon,
-                               uint32_t *status, hipStream_t s)
-{
-    {
-        Observe o(VLCT_KERNEL_PRIMS, s);
-        k_prims<<<xcd_grid(nblk_prims(g)), kBlock, 0, s>>>(g, st, B.P, status);
-    }
     if (recon == VLCT_RECON_PCM) {
-        // predictor: one thread per face
+        // one thread per face
 #define VLCT_FLUX(D)                                                                      \
     {                                                                                     \
         Observe o(VLCT_KERNEL_FLUX_PCM, s);                                               \
-        k_flux<D, VLCT_RECON_PCM><<<xcd_grid(nblk_flux(g, D)), kBlock, 0, s>>>(g, st, B.P, B.F, \
-                                                                                status);  \
+        k_flux<D, VLCT_RECON_PCM><<<xcd_grid(nblk_flux(g, D)), kBlock, 0, s>>>(g, st, P, F, status); \
     }
         VLCT_FLUX(0) VLCT_FLUX(1) VLCT_FLUX(2)
 #undef VLCT_FLUX
     } else {
-        // corrector: one reconstruction per cell and axis, x by rows, y and z
-        // by column marches
+        // one reconstruction per cell and axis, x by rows, y and z by column marches
         const int kid = VLCT_KERNEL_FLUX_RECON;
 #define VLCT_RECON3(R)                                                                        \
     {                                                                                         \
-        { Observe o(kid, s); k_flux_recon_x<R><<<xcd_grid(nblk_row(g)), kBlock, 0, s>>>(g, st, B.P, B.F, status); } \
-        { Observe o(kid, s); k_flux_recon_march<1, R><<<xcd_grid(nblk_march(g, 1)), kBlock, 0, s>>>(g, st, B.P, B.F, status); } \
-        { Observe o(kid, s); k_flux_recon_march<2, R><<<xcd_grid(nblk_march(g, 2)), kBlock, 0, s>>>(g, st, B.P, B.F, status); } \
+        { Observe o(kid, s); k_flux_recon_x<R><<<xcd_grid(nblk_row(g)), kBlock, 0, s>>>(g, st, P, F, status); } \
+        { Observe o(kid, s); k_flux_recon_march<1, R><<<xcd_grid(nblk_march(g, 1)), kBlock, 0, s>>>(g, st, P, F, status); } \
+        { Observe o(kid, s); k_flux_recon_march<2, R><<<xcd_grid(nblk_march(g, 2)), kBlock, 0, s>>>(g, st, P, F, status); } \
     }
         switch (recon) {
         case VLCT_RECON_PLMC: VLCT_RECON3(VLCT_RECON_PLMC) break;
@@ -1087,6 +925,19 @@ static int launch_stage_fluxes(const Geom &g, const StateP &st, const Bound &B, 
         }
 #undef VLCT_RECON3
     }
+    return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
+}
+
+// CT edge fields + update: full = false is the half step into `out` (Steps
+// 4-5), full = true the full step from `base` (Steps 8-9)
+int launch_ct(const Geom &g, bool full, const Prims &P, const Flux &F, const StateP &base,
+              const StateW &out, const double *dt_dev, uint32_t *status, hipStream_t s)
+{
+    Observe o(full ? VLCT_KERNEL_UPDATE_FULL : VLCT_KERNEL_UPDATE_HALF, s);
+    if (full)
+        k_ct_update<true><<<xcd_grid(nblk_ct(g)), kCt, 0, s>>>(g, P, F, base, out, dt_dev, status);
+    else
+        k_ct_update<false><<<xcd_grid(nblk_ct(g)), kCt, 0, s>>>(g, P, F, base, out, dt_dev, status);
     return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
 }
 
@@ -1211,24 +1062,16 @@ int vlct_step(const vlct_grid *vg, const vlct_state *in, const vlct_state *out,
     const Bound B = bind(L, ws);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const StateP sin = as_const(in);
-    const unsigned gct = xcd_grid(nblk_ct(g));
-
     // predictor (Steps 2-5)
-    int rc = launch_stage_fluxes(g, sin, B, VLCT_RECON_PCM, status_dev, s);
-    if (rc) return rc;
-    {
-        Observe o(VLCT_KERNEL_UPDATE_HALF, s);
-        k_ct_update<false><<<gct, kCt, 0, s>>>(g, B.P, B.F, sin, B.half, dt_dev, status_dev);
-    }
+    int rc = launch_prims(g, sin, B.P, status_dev, s);
+    if (!rc) rc = launch_fluxes(g, sin, B.P, B.F, VLCT_RECON_PCM, status_dev, s);
+    if (!rc) rc = launch_ct(g, false, B.P, B.F, sin, B.half, dt_dev, status_dev, s);
     // corrector (Steps 6-9)
-    rc = launch_stage_fluxes(g, as_const(B.half), B, vg->recon, status_dev, s);
+    const StateP half = as_const(B.half);
+    if (!rc) rc = launch_prims(g, half, B.P, status_dev, s);
+    if (!rc) rc = launch_fluxes(g, half, B.P, B.F, vg->recon, status_dev, s);
+    if (!rc) rc = launch_ct(g, true, B.P, B.F, sin, as_mut(out), dt_dev, status_dev, s);
     if (rc) return rc;
-    {
-        Observe o(VLCT_KERNEL_UPDATE_FULL, s);
-        k_ct_update<true><<<gct, kCt, 0, s>>>(g, B.P, B.F, sin, as_mut(out), dt_dev,
-                                                 status_dev);
-    }
-    if (hipGetLastError() != hipSuccess) return VLCT_EHIP;
     if (next_dt_dev) return launch_dt(g, as_const(out), B, L, next_dt_dev, status_dev, s);
     return VLCT_OK;
 }

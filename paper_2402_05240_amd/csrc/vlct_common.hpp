@@ -1,0 +1,201 @@
+// vlct_common.hpp -- definitions shared by the step kernels (vlct.hip) and
+// the adjoint kernels (vlct_adjoint.hip): launch geometry, index maps of the
+// state and workspace arrays, state views and argument checks.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+
+#include "../../include/vlct.h"
+
+namespace vlct {
+
+constexpr int kGhost = 3;          // ghost layers of the primitive workspace
+constexpr int kBlock = 256;        // threads per block (4 wave64s)
+constexpr int kMaxN = 4096;
+
+using idx_t = long long;
+
+// MI355X dispatches consecutive workgroups round-robin to its 8 XCDs, each with
+// its own L2.  Kernels launched on xcd_grid(n) blocks read their logical block
+// from xcd_block(n): hardware block b works on logical block
+// (b mod 8) * ceil(n/8) + b / 8, so every XCD sweeps one contiguous slab of
+// the domain and neighbouring rows and planes meet in the same L2.
+constexpr int kXcd = 8;
+__host__ __device__ __forceinline__ idx_t xcd_per(idx_t n) { return (n + kXcd - 1) / kXcd; }
+__device__ __forceinline__ idx_t xcd_block(idx_t n)
+{
+    const idx_t b = blockIdx.x;
+    return (b % kXcd) * xcd_per(n) + b / kXcd;
+}
+
+// ---------------------------------------------------------------------------
+// geometry shared by every kernel
+// ---------------------------------------------------------------------------
+struct Geom {
+    int n[3];
+    int bc[3];
+    double dl[3];
+    double gamma, gm1i, cfl;
+    int p[3];  // padded primitive dims n + 2G
+};
+
+__host__ __device__ __forceinline__ int map_cell(int i, int n, int bc)
+{
+    if (bc == VLCT_BC_PERIODIC) {
+        // one period either side without an integer division
+        if (i >= 0 && i < n) return i;
+        if (i < 0 && i >= -n) return i + n;
+        if (i >= n && i < 2 * n) return i - n;
+        const int m = i % n;
+        return m < 0 ? m + n : m;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+// normal-face index: periodic faces wrap into [0, n-1], outflow clamps into [0, n]
+__host__ __device__ __forceinline__ int map_face(int i, int n, int bc)
+{
+    if (bc == VLCT_BC_PERIODIC) return map_cell(i, n, bc);
+    return i < 0 ? 0 : (i > n ? n : i);
+}
+
+// stored face arrays of the state: axis d has n_d + 1 faces along d
+__device__ __forceinline__ idx_t face_store(const Geom &g, int d, int i, int j, int k)
+{
+    const idx_t nx = g.n[0] + (d == 0), ny = g.n[1] + (d == 1);
+    return ((idx_t)k * ny + j) * nx + i;
+}
+
+__device__ __forceinline__ idx_t cell_store(const Geom &g, int i, int j, int k)
+{
+    return ((idx_t)k * g.n[1] + j) * g.n[0] + i;
+}
+
+// padded primitive index, i,j,k in [-G, n+G-1]
+__device__ __forceinline__ idx_t pidx(const Geom &g, int i, int j, int k)
+{
+    return ((idx_t)(k + kGhost) * g.p[1] + (j + kGhost)) * g.p[0] + (i + kGhost);
+}
+
+// flux arrays of axis d: normal index in [0, n_d], transverse in [-1, n_e]
+__host__ __device__ __forceinline__ idx_t flux_dim(const int n[3], int d, int e)
+{
+    return n[e] + (e == d ? 1 : 2);
+}
+__device__ __forceinline__ idx_t fidx(const Geom &g, int d, int i, int j, int k)
+{
+    const idx_t X = flux_dim(g.n, d, 0), Y = flux_dim(g.n, d, 1);
+    return ((idx_t)(k + (d != 2)) * Y + (j + (d != 1))) * X + (i + (d != 0));
+}
+
+struct StateP {
+    const double *u[5];
+    const double *b[3];
+};
+struct StateW {
+    double *u[5];
+    double *b[3];
+};
+struct Prims {
+    double *w[8];  // rho, vx, vy, vz, P, Bcx, Bcy, Bcz on padded cells
+};
+struct Flux {
+    double *f[3][8];  // per axis: 7 sweep-frame components + upwind indicator
+};
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+inline bool grid_ok(const vlct_grid *g)
+{
+    if (!g) return false;
+    const int n[3] = {g->nx, g->ny, g->nz};
+    for (int d = 0; d < 3; ++d) {
+        if (n[d] < 1 || n[d] > kMaxN) return false;
+        if (g->bc[d] != VLCT_BC_PERIODIC && g->bc[d] != VLCT_BC_OUTFLOW) return false;
+    }
+    if (!(g->dx > 0.0) || !(g->dy > 0.0) || !(g->dz > 0.0)) return false;
+    if (!(g->gamma > 1.0) || !(g->cfl > 0.0 && g->cfl <= 0.5)) return false;
+    if (g->recon < VLCT_RECON_PCM || g->recon > VLCT_RECON_PPMP) return false;
+    return true;
+}
+
+inline Geom make_geom(const vlct_grid *vg)
+{
+    Geom g;
+    g.n[0] = vg->nx;
+    g.n[1] = vg->ny;
+    g.n[2] = vg->nz;
+    for (int d = 0; d < 3; ++d) {
+        g.bc[d] = vg->bc[d];
+        g.p[d] = g.n[d] + 2 * kGhost;
+    }
+    g.dl[0] = vg->dx;
+    g.dl[1] = vg->dy;
+    g.dl[2] = vg->dz;
+    g.gamma = vg->gamma;
+    g.gm1i = 1.0 / (vg->gamma - 1.0);
+    g.cfl = vg->cfl;
+    return g;
+}
+
+inline size_t field_len(const int n[3], int f)
+{
+    size_t nx = n[0], ny = n[1], nz = n[2];
+    if (f < 5) return nx * ny * nz;
+    if (f == 5) return (nx + 1) * ny * nz;
+    if (f == 6) return nx * (ny + 1) * nz;
+    return nx * ny * (nz + 1);
+}
+
+inline bool state_ok(const vlct_state *s)
+{
+    if (!s) return false;
+    const double *p[8] = {s->rho, s->mx, s->my, s->mz, s->E, s->bx, s->by, s->bz};
+    for (int f = 0; f < 8; ++f)
+        if (!p[f]) return false;
+    return true;
+}
+
+inline StateP as_const(const vlct_state *s)
+{
+    StateP p;
+    p.u[0] = s->rho; p.u[1] = s->mx; p.u[2] = s->my; p.u[3] = s->mz; p.u[4] = s->E;
+    p.b[0] = s->bx; p.b[1] = s->by; p.b[2] = s->bz;
+    return p;
+}
+
+inline StateP as_const(const StateW &s)
+{
+    StateP p;
+    for (int f = 0; f < 5; ++f) p.u[f] = s.u[f];
+    for (int d = 0; d < 3; ++d) p.b[d] = s.b[d];
+    return p;
+}
+
+inline StateW as_mut(const vlct_state *s)
+{
+    StateW p;
+    p.u[0] = s->rho; p.u[1] = s->mx; p.u[2] = s->my; p.u[3] = s->mz; p.u[4] = s->E;
+    p.b[0] = s->bx; p.b[1] = s->by; p.b[2] = s->bz;
+    return p;
+}
+
+inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+inline unsigned nblocks(size_t work) { return (unsigned)((work + kBlock - 1) / kBlock); }
+
+// grid size (multiple of the XCD count) for a kernel that remaps with xcd_block
+inline unsigned xcd_grid(size_t logical_blocks) { return (unsigned)(kXcd * xcd_per(logical_blocks)); }
+
+// launches of the step kernels (vlct.hip), also used by the adjoint to
+// recompute the forward intermediates
+int launch_prims(const Geom &g, const StateP &st, const Prims &P, uint32_t *status,
+                 hipStream_t s);
+int launch_fluxes(const Geom &g, const StateP &st, const Prims &P, const Flux &F, int recon,
+                  uint32_t *status, hipStream_t s);
+int launch_ct(const Geom &g, bool full, const Prims &P, const Flux &F, const StateP &base,
+              const StateW &out, const double *dt_dev, uint32_t *status, hipStream_t s);
+
+}  // namespace vlct

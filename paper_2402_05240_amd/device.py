@@ -150,3 +150,42 @@ class BatchStepper:
 
     def status_bits(self):
         return [int(x) for x in self.status.cpu()]
+
+
+class Adjoint:
+    """Reverse derivative of one step (vlct_step_adjoint): for a state at the
+    start of a step of fixed size dt, maps the cotangent of the step's output
+    to the cotangent of its input.  Owns the workspace and three states."""
+
+    def __init__(self, grid: Grid, device: str = "cuda:0"):
+        torch = _torch()
+        self.grid = grid
+        self.cg = vlct.make_grid(grid)
+        self.ws_bytes = vlct.vlct_adjoint_workspace_bytes(self.cg)
+        if self.ws_bytes == 0:
+            raise ValueError("invalid grid descriptor")
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.state = DeviceState(grid, device)
+        self.lam_out = DeviceState(grid, device)
+        self.lam_in = DeviceState(grid, device)
+        self.dt = torch.zeros(1, dtype=torch.float64, device=device)
+
+    def stream(self) -> int:
+        return _torch().cuda.current_stream().cuda_stream
+
+    def run(self) -> None:
+        """lam_in = (d step / d state)^T lam_out on the device-resident arrays."""
+        rc = vlct.vlct_step_adjoint(self.cg, self.state.c_state(), self.lam_out.c_state(),
+                                    self.lam_in.c_state(), self.dt.data_ptr(),
+                                    self.ws.data_ptr(), self.ws_bytes, self.stream())
+        if rc:
+            raise vlct.VlctError(rc, "vlct_step_adjoint")
+
+    def vjp(self, s: Dict[str, np.ndarray], lam_out: Dict[str, np.ndarray],
+            dt: float) -> Dict[str, np.ndarray]:
+        """Host round trip: upload the state and lam_out, run, download lam_in."""
+        self.state.upload(s)
+        self.lam_out.upload(lam_out)
+        self.dt.fill_(float(dt))
+        self.run()
+        return self.lam_in.download()

@@ -30,7 +30,8 @@ VLCT_STATUS_NONFINITE = 4
 
 EXPORTED = ("vlct_workspace_bytes", "vlct_cfl_dt", "vlct_step", "vlct_strerror",
             "vlct_abi_version", "vlct_set_launch_observer", "vlct_kernel_name",
-            "vlct_batch_workspace_bytes", "vlct_step_batch")
+            "vlct_batch_workspace_bytes", "vlct_step_batch", "vlct_adjoint_workspace_bytes",
+            "vlct_step_adjoint")
 
 VLCT_KERNEL_PRIMS = 0
 VLCT_KERNEL_FLUX_PCM = 1
@@ -91,6 +92,13 @@ def load(path: str = LIB_PATH):
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         lib.vlct_step_batch.restype = ctypes.c_int
+        lib.vlct_adjoint_workspace_bytes.argtypes = [ctypes.POINTER(vlct_grid)]
+        lib.vlct_adjoint_workspace_bytes.restype = ctypes.c_size_t
+        lib.vlct_step_adjoint.argtypes = [ctypes.POINTER(vlct_grid), ctypes.POINTER(vlct_state),
+                                          ctypes.POINTER(vlct_state), ctypes.POINTER(vlct_state),
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                          ctypes.c_void_p]
+        lib.vlct_step_adjoint.restype = ctypes.c_int
         lib.vlct_strerror.argtypes = [ctypes.c_int]
         lib.vlct_strerror.restype = ctypes.c_char_p
         lib.vlct_abi_version.argtypes = []
@@ -155,6 +163,18 @@ def vlct_step_batch(grids, states_in, states_out, dt_dev: int, next_dt_dev: int,
     b = (vlct_state * n)(*states_out)
     return int(load().vlct_step_batch(n, g, a, b, dt_dev, next_dt_dev, status_dev, ws, ws_bytes,
                                       stream))
+
+
+def vlct_adjoint_workspace_bytes(grid: vlct_grid) -> int:
+    return int(load().vlct_adjoint_workspace_bytes(ctypes.byref(grid)))
+
+
+def vlct_step_adjoint(grid: vlct_grid, state_in: vlct_state, lam_out: vlct_state,
+                      lam_in: vlct_state, dt_dev: int, ws: int, ws_bytes: int,
+                      stream: int) -> int:
+    return int(load().vlct_step_adjoint(ctypes.byref(grid), ctypes.byref(state_in),
+                                        ctypes.byref(lam_out), ctypes.byref(lam_in), dt_dev, ws,
+                                        ws_bytes, stream))
 
 
 def vlct_strerror(code: int) -> str:

@@ -109,6 +109,36 @@ def test_batch_validation():
                                 0) == vlct.VLCT_EWORKSPACE
 
 
+def test_adjoint_validation():
+    """vlct_step_adjoint rejects bad calls on the host, before any launch."""
+    _lib()
+    g = _grid()
+    need = vlct.vlct_adjoint_workspace_bytes(g)
+    assert need > vlct.vlct_workspace_bytes(g)
+    assert vlct.vlct_adjoint_workspace_bytes(_grid(nx=0)) == 0
+
+    def st(base):
+        return vlct.make_state([base + 8192 * f for f in range(8)])
+    a, b, c = st(1 << 20), st(2 << 20), st(3 << 20)
+    ws = 1 << 30
+    assert vlct.vlct_step_adjoint(g, a, b, c, 0, ws, need, 0) == vlct.VLCT_EINVAL
+    assert vlct.vlct_step_adjoint(_grid(dx=0.0), a, b, c, 64, ws, need, 0) == vlct.VLCT_EINVAL
+    # outflow boundaries and the parabolic reconstructions are not differentiated
+    assert vlct.vlct_step_adjoint(_grid(bc=(0, 1, 0)), a, b, c, 64, ws, need,
+                                  0) == vlct.VLCT_EUNSUPPORTED
+    for recon in (3, 5):
+        assert vlct.vlct_step_adjoint(_grid(recon=recon), a, b, c, 64, ws, need,
+                                      0) == vlct.VLCT_EUNSUPPORTED
+    # lam_in overlapping the state, lam_out or itself
+    assert vlct.vlct_step_adjoint(g, a, b, a, 64, ws, need, 0) == vlct.VLCT_EINVAL
+    assert vlct.vlct_step_adjoint(g, a, b, st((2 << 20) + 8), 64, ws, need, 0) == vlct.VLCT_EINVAL
+    same = vlct.make_state([3 << 20] * 8)
+    assert vlct.vlct_step_adjoint(g, a, b, same, 64, ws, need, 0) == vlct.VLCT_EINVAL
+    # workspace missing or short
+    assert vlct.vlct_step_adjoint(g, a, b, c, 64, 0, need, 0) == vlct.VLCT_EWORKSPACE
+    assert vlct.vlct_step_adjoint(g, a, b, c, 64, ws, need - 1, 0) == vlct.VLCT_EWORKSPACE
+
+
 def test_strerror_covers_codes():
     _lib()
     for c in range(5):
