@@ -387,6 +387,48 @@ def ensemble_bench(count, steps, warmup):
             "speedup": ms_seq / ms_batch, "bitwise_equal": bool(same)}
 
 
+def adjoint_bench(n, steps, warmup):
+    """Cost of the adjoint of one step against one forward step on decaying
+    turbulence at n^3 (PLMC): the forward step is vlct_step with the next-dt
+    reduction, the adjoint is vlct_step_adjoint (which recomputes the forward
+    intermediates it needs); both timed with events on the current stream."""
+    import torch
+    from paper_2402_05240_amd import inputs as I
+    from paper_2402_05240_amd.device import Adjoint, Stepper
+    g, s = I.turbulence((n, n, n))
+    fwd = Stepper(g).upload(s)
+    fwd.compute_dt()
+    dt = float(fwd.dt.item())
+    adj = Adjoint(g)
+    adj.state.upload(s)
+    for f in I.FIELDS:
+        adj.lam_out.t[f].normal_()
+    adj.dt.fill_(dt)
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(k):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / k
+
+    def fstep():
+        fwd.set_dt(dt)
+        fwd.step()
+    for _ in range(warmup):
+        fstep()
+        adj.run()
+    ms_f = timed(fstep, steps)
+    ms_a = timed(adj.run, steps)
+    return {"workload": "turbulence_plmc_%d" % n, "grid": [n, n, n], "recon": "PLMC",
+            "steps": steps, "forward_ms": ms_f, "adjoint_ms": ms_a, "ratio": ms_a / ms_f,
+            "workspace_bytes": adj.ws_bytes,
+            "note": "adjoint includes the recomputation of the step's intermediates"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -397,6 +439,11 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the batched-ensemble measurement (64 small runs)")
     ap.add_argument("--ensemble-steps", type=int, default=10)
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint/forward cost measurement")
+    ap.add_argument("--adjoint-n", type=int, nargs="*", default=[128],
+                    help="cells per axis of the adjoint cost measurement(s)")
+    ap.add_argument("--adjoint-steps", type=int, default=10)
     ap.add_argument("--cpu-planes", type=int, default=256)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--cpu-threads", type=int, default=0)
@@ -508,8 +555,13 @@ def main():
         "wall_ms_per_step": (w1 - w0) * 1e3 / args.steps,
         "status": status,
     }
+    del st
+    torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        costs = [adjoint_bench(n, args.adjoint_steps, 2) for n in args.adjoint_n]
+        out["adjoint_forward_cost"] = costs[0] if len(costs) == 1 else costs
+        torch.cuda.empty_cache()
     if not args.no_ensemble:
-        del st
         torch.cuda.empty_cache()
         out["ensemble"] = ensemble_bench(64, args.ensemble_steps, 2)
     if not args.no_cpu_baseline:
