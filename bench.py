@@ -12,6 +12,7 @@ on) and a CPU baseline (the oracle on a bounded sample of the same workload).
 from __future__ import annotations
 
 import argparse
+import math
 import ctypes
 import json
 import os
@@ -429,6 +430,54 @@ def adjoint_bench(n, steps, warmup):
             "note": "adjoint includes the recomputation of the step's intermediates"}
 
 
+def inverse_bench(n, steps):
+    """Differentiable turbulence inverse problem at n^3 (PLMC): parameters are
+    the initial conserved variables and the edge vector potential A (B = b0 +
+    curl_h A), the forward pass runs `steps` steps on the recorded CFL chain
+    with sqrt(steps) checkpoints, loss = mean((rho_final - target)^2) for a
+    seeded target field; the backward pass recomputes each segment and runs
+    the step adjoints.  Times both passes with events on the current stream."""
+    import numpy as np
+    import torch
+    from paper_2402_05240_amd import autograd as AG
+    from paper_2402_05240_amd import inputs as I
+    g, s, A, b0 = I.turbulence_potential((n, n, n))
+    rng = np.random.default_rng(5240)
+    x, y, z = I._centres(g)
+    ph = rng.uniform(0.0, 2.0 * np.pi, 3)
+    target = 1.0 + 0.05 * np.sin(2 * np.pi * x + ph[0]) * np.sin(2 * np.pi * y + ph[1]) \
+        * np.sin(2 * np.pi * z + ph[2])
+    sim = AG.Simulator(g)
+    tgt = torch.from_numpy(target).cuda()
+
+    def run(nsteps):
+        cons = [torch.from_numpy(s[f]).cuda().requires_grad_(True)
+                for f in ("rho", "mx", "my", "mz", "E")]
+        pot = [torch.from_numpy(a).cuda().requires_grad_(True) for a in A]
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        bf = AG.curl(sim, *pot)
+        out, _ = AG.rollout(sim, cons + [bf[0] + b0[0], bf[1], bf[2]], nsteps=nsteps)
+        loss = ((out[0] - tgt) ** 2).mean()
+        e[1].record()
+        loss.backward()
+        e[2].record()
+        torch.cuda.synchronize()
+        gn = math.sqrt(sum(float((q.grad ** 2).sum()) for q in cons + pot))
+        return e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), float(loss.item()), gn
+
+    run(2)  # warm-up: workspaces and allocator
+    torch.cuda.reset_peak_memory_stats()
+    ms_f, ms_b, loss, gnorm = run(steps)
+    seg = int(math.ceil(math.sqrt(steps)))
+    return {"workload": "inverse_turbulence_plmc_%d" % n, "grid": [n, n, n], "steps": steps,
+            "checkpoint_segment": seg, "forward_ms": ms_f, "backward_ms": ms_b,
+            "ratio": ms_b / ms_f, "loss": loss, "grad_norm": gnorm,
+            "peak_device_bytes": int(torch.cuda.max_memory_allocated()),
+            "note": "backward = segment recomputation + one adjoint per step"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -444,6 +493,10 @@ def main():
     ap.add_argument("--adjoint-n", type=int, nargs="*", default=[128],
                     help="cells per axis of the adjoint cost measurement(s)")
     ap.add_argument("--adjoint-steps", type=int, default=10)
+    ap.add_argument("--no-inverse", action="store_true",
+                    help="skip the differentiable inverse-problem measurement")
+    ap.add_argument("--inverse-n", type=int, default=128)
+    ap.add_argument("--inverse-steps", type=int, default=200)
     ap.add_argument("--cpu-planes", type=int, default=256)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--cpu-threads", type=int, default=0)
@@ -560,6 +613,9 @@ def main():
     if not args.no_adjoint:
         costs = [adjoint_bench(n, args.adjoint_steps, 2) for n in args.adjoint_n]
         out["adjoint_forward_cost"] = costs[0] if len(costs) == 1 else costs
+        torch.cuda.empty_cache()
+    if not args.no_inverse:
+        out["inverse_problem"] = inverse_bench(args.inverse_n, args.inverse_steps)
         torch.cuda.empty_cache()
     if not args.no_ensemble:
         torch.cuda.empty_cache()

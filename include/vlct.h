@@ -166,6 +166,23 @@ int vlct_step_adjoint(const vlct_grid *g, const vlct_state *in, const vlct_state
                       const vlct_state *lam_in, const double *dt_dev, void *ws, size_t ws_bytes,
                       void *stream);
 
+/* Face fields of an edge-centred vector potential, B = curl_h A, on a periodic
+ * grid (the vertex/edge potential of the CT scheme, Sec. 2.2; its discrete
+ * divergence vanishes to rounding).  ax[k][j][i] sits at (i, j-1/2, k-1/2),
+ * ay at (i-1/2, j, k-1/2), az at (i-1/2, j-1/2, k); each is a device array of
+ * nz*ny*nx doubles.  bx, by, bz: device face arrays in the vlct_state layout,
+ * written completely (the duplicate periodic plane n equals plane 0).
+ * VLCT_EUNSUPPORTED unless every axis is periodic. */
+int vlct_curl_potential(const vlct_grid *g, const double *ax, const double *ay, const double *az,
+                        double *bx, double *by, double *bz, void *stream);
+
+/* Transpose of vlct_curl_potential: (lax, lay, laz) = curl_h^T (lbx, lby, lbz),
+ * with the cotangent of each duplicate face plane acting on plane 0 (the face
+ * it copies).  Overwrites lax, lay, laz; device arrays; periodic only. */
+int vlct_curl_potential_adjoint(const vlct_grid *g, const double *lbx, const double *lby,
+                                const double *lbz, double *lax, double *lay, double *laz,
+                                void *stream);
+
 /* --- diagnostics ----------------------------------------------------------
  * Launch observer: when set, every vlct_step / vlct_cfl_dt call invokes
  * cb(user, kernel, phase, stream) on the calling host thread immediately

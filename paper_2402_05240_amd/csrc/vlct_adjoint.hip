@@ -499,11 +499,98 @@ static AdLayout ad_layout(const Geom &g)
     return L;
 }
 
+// ---------------------------------------------------------------------------
+// face fields from an edge-centred vector potential, B = curl_h A (periodic),
+// and the transpose of that map.  A_x at (i, j-1/2, k-1/2), A_y at
+// (i-1/2, j, k-1/2), A_z at (i-1/2, j-1/2, k), each stored like a cell array.
+// ---------------------------------------------------------------------------
+__global__ void k_curl_potential(Geom g, const double *ax, const double *ay, const double *az,
+                                 double *bx, double *by, double *bz)
+{
+    const idx_t N = (idx_t)g.n[0] * g.n[1] * g.n[2];
+    const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    int x[3];
+    cell_coords(g, t, x);
+    const int i = x[0], j = x[1], k = x[2];
+    const idx_t ip = cell_of(g, i + 1, j, k), jp = cell_of(g, i, j + 1, k),
+                kp = cell_of(g, i, j, k + 1);
+    const double vx = (az[jp] - az[t]) / g.dl[1] - (ay[kp] - ay[t]) / g.dl[2];
+    const double vy = (ax[kp] - ax[t]) / g.dl[2] - (az[ip] - az[t]) / g.dl[0];
+    const double vz = (ay[ip] - ay[t]) / g.dl[0] - (ax[jp] - ax[t]) / g.dl[1];
+    bx[face_store(g, 0, i, j, k)] = vx;
+    by[face_store(g, 1, i, j, k)] = vy;
+    bz[face_store(g, 2, i, j, k)] = vz;
+    // the duplicate periodic face planes
+    if (i == 0) bx[face_store(g, 0, g.n[0], j, k)] = vx;
+    if (j == 0) by[face_store(g, 1, i, g.n[1], k)] = vy;
+    if (k == 0) bz[face_store(g, 2, i, j, g.n[2])] = vz;
+}
+
+__global__ void k_curl_potential_adjoint(Geom g, const double *lbx, const double *lby,
+                                         const double *lbz, double *lax, double *lay, double *laz)
+{
+    const idx_t N = (idx_t)g.n[0] * g.n[1] * g.n[2];
+    const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    int x[3];
+    cell_coords(g, t, x);
+    const int i = x[0], j = x[1], k = x[2];
+    // cotangent of face (d; a, b, c) with the duplicate plane's folded onto plane 0
+    auto lb = [&](int d, const double *p, int a, int b2, int c2) {
+        const int q[3] = {wrapc(a, g.n[0]), wrapc(b2, g.n[1]), wrapc(c2, g.n[2])};
+        double v = p[face_store(g, d, q[0], q[1], q[2])];
+        if (q[d] == 0) {
+            int r[3] = {q[0], q[1], q[2]};
+            r[d] = g.n[d];
+            v += p[face_store(g, d, r[0], r[1], r[2])];
+        }
+        return v;
+    };
+    lax[t] = (lb(1, lby, i, j, k - 1) - lb(1, lby, i, j, k)) / g.dl[2]
+             + (lb(2, lbz, i, j, k) - lb(2, lbz, i, j - 1, k)) / g.dl[1];
+    lay[t] = (lb(0, lbx, i, j, k) - lb(0, lbx, i, j, k - 1)) / g.dl[2]
+             + (lb(2, lbz, i - 1, j, k) - lb(2, lbz, i, j, k)) / g.dl[0];
+    laz[t] = (lb(0, lbx, i, j - 1, k) - lb(0, lbx, i, j, k)) / g.dl[1]
+             + (lb(1, lby, i, j, k) - lb(1, lby, i - 1, j, k)) / g.dl[0];
+}
+
 }  // namespace vlct
 
 using namespace vlct;
 
 extern "C" {
+
+static bool periodic_grid(const vlct_grid *g)
+{
+    return grid_ok(g) && g->bc[0] == VLCT_BC_PERIODIC && g->bc[1] == VLCT_BC_PERIODIC &&
+           g->bc[2] == VLCT_BC_PERIODIC;
+}
+
+int vlct_curl_potential(const vlct_grid *vg, const double *ax, const double *ay, const double *az,
+                        double *bx, double *by, double *bz, void *stream)
+{
+    if (!grid_ok(vg) || !ax || !ay || !az || !bx || !by || !bz) return VLCT_EINVAL;
+    if (!periodic_grid(vg)) return VLCT_EUNSUPPORTED;
+    const Geom g = make_geom(vg);
+    const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+    k_curl_potential<<<nblocks(N), kBlock, 0, static_cast<hipStream_t>(stream)>>>(g, ax, ay, az,
+                                                                                 bx, by, bz);
+    return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
+}
+
+int vlct_curl_potential_adjoint(const vlct_grid *vg, const double *lbx, const double *lby,
+                                const double *lbz, double *lax, double *lay, double *laz,
+                                void *stream)
+{
+    if (!grid_ok(vg) || !lbx || !lby || !lbz || !lax || !lay || !laz) return VLCT_EINVAL;
+    if (!periodic_grid(vg)) return VLCT_EUNSUPPORTED;
+    const Geom g = make_geom(vg);
+    const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+    k_curl_potential_adjoint<<<nblocks(N), kBlock, 0, static_cast<hipStream_t>(stream)>>>(
+        g, lbx, lby, lbz, lax, lay, laz);
+    return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
+}
 
 size_t vlct_adjoint_workspace_bytes(const vlct_grid *g)
 {

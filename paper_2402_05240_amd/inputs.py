@@ -471,11 +471,22 @@ def _eval_modes(ks, coef, n, offset) -> np.ndarray:
 
 def turbulence(n=(256, 256, 256), seed_v=2402, seed_a=5240, mach=1.0, beta=1.0,
                db_rms=0.1, gamma=5.0 / 3.0, recon=RECON_PLMC, cfl=0.4) -> Tuple[Grid, State]:
+    """Decaying MHD turbulence (see turbulence_potential)."""
+    g, s, _, _ = turbulence_potential(n, seed_v, seed_a, mach, beta, db_rms, gamma, recon, cfl)
+    return g, s
+
+
+def turbulence_potential(n=(256, 256, 256), seed_v=2402, seed_a=5240, mach=1.0, beta=1.0,
+                         db_rms=0.1, gamma=5.0 / 3.0, recon=RECON_PLMC, cfl=0.4):
     """Decaying MHD turbulence on the periodic unit box: rho = 1, sound speed 1
     (P = 1/gamma), velocity a Gaussian random field with E(k) ~ k^-2 on
     1 <= |k| <= 4 scaled to rms |v| = mach, uniform B_x with plasma beta `beta`
     plus a divergence-free perturbation B = curl A of an edge-centred random vector
-    potential, scaled to rms |dB_cc| = db_rms * B_x0."""
+    potential, scaled to rms |dB_cc| = db_rms * B_x0.
+
+    Returns (grid, state, A, b0): the face field of the state is
+    b0 + curl_h A with A = (ax, ay, az) the scaled edge potential (cell-shaped
+    arrays, ax at (i, j-1/2, k-1/2) and cyclically) and b0 = (B_x0, 0, 0)."""
     nx, ny, nz = n
     g = Grid(nx, ny, nz, 1.0 / nx, 1.0 / ny, 1.0 / nz, gamma, cfl, recon, (0, 0, 0))
     rho = 1.0
@@ -517,7 +528,7 @@ def turbulence(n=(256, 256, 256), seed_v=2402, seed_a=5240, mach=1.0, beta=1.0,
     s["my"] = rho * vy
     s["mz"] = rho * vz
     s["E"] = _cell_energy(g, s["rho"], vx, vy, vz, p, s["bx"], s["by"], s["bz"])
-    return g, s
+    return g, s, [sc * a for a in pot], (bx0, 0.0, 0.0)
 
 
 def curl_edge_potential(g: Grid, ax: np.ndarray, ay: np.ndarray, az: np.ndarray):

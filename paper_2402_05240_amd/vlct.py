@@ -31,7 +31,7 @@ VLCT_STATUS_NONFINITE = 4
 EXPORTED = ("vlct_workspace_bytes", "vlct_cfl_dt", "vlct_step", "vlct_strerror",
             "vlct_abi_version", "vlct_set_launch_observer", "vlct_kernel_name",
             "vlct_batch_workspace_bytes", "vlct_step_batch", "vlct_adjoint_workspace_bytes",
-            "vlct_step_adjoint")
+            "vlct_step_adjoint", "vlct_curl_potential", "vlct_curl_potential_adjoint")
 
 VLCT_KERNEL_PRIMS = 0
 VLCT_KERNEL_FLUX_PCM = 1
@@ -99,6 +99,10 @@ def load(path: str = LIB_PATH):
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                           ctypes.c_void_p]
         lib.vlct_step_adjoint.restype = ctypes.c_int
+        for name in ("vlct_curl_potential", "vlct_curl_potential_adjoint"):
+            fn = getattr(lib, name)
+            fn.argtypes = [ctypes.POINTER(vlct_grid)] + [ctypes.c_void_p] * 7
+            fn.restype = ctypes.c_int
         lib.vlct_strerror.argtypes = [ctypes.c_int]
         lib.vlct_strerror.restype = ctypes.c_char_p
         lib.vlct_abi_version.argtypes = []
@@ -175,6 +179,17 @@ def vlct_step_adjoint(grid: vlct_grid, state_in: vlct_state, lam_out: vlct_state
     return int(load().vlct_step_adjoint(ctypes.byref(grid), ctypes.byref(state_in),
                                         ctypes.byref(lam_out), ctypes.byref(lam_in), dt_dev, ws,
                                         ws_bytes, stream))
+
+
+def vlct_curl_potential(grid: vlct_grid, ax: int, ay: int, az: int, bx: int, by: int, bz: int,
+                        stream: int) -> int:
+    return int(load().vlct_curl_potential(ctypes.byref(grid), ax, ay, az, bx, by, bz, stream))
+
+
+def vlct_curl_potential_adjoint(grid: vlct_grid, lbx: int, lby: int, lbz: int, lax: int,
+                                lay: int, laz: int, stream: int) -> int:
+    return int(load().vlct_curl_potential_adjoint(ctypes.byref(grid), lbx, lby, lbz, lax, lay,
+                                                  laz, stream))
 
 
 def vlct_strerror(code: int) -> str:

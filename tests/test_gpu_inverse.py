@@ -1,0 +1,229 @@
+"""Differentiable rollouts on the GPU (paper_2402_05240_amd.autograd): the
+vector-potential map B = curl_h A and its transpose, the step and rollout
+autograd functions with sqrt(N) checkpointing, and the gradient of a
+turbulence inverse problem (loss = mean square of the final density against a
+target field, with respect to the initial conserved variables and the vector
+potential) against central differences of the oracle's steps."""
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2402_05240_amd import inputs as I
+from parity_util import FIELDS, gpu_available
+
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _grid(n, recon=I.RECON_PLMC):
+    return I.Grid(n[0], n[1], n[2], 1.0 / n[0], 1.0 / n[1], 1.0 / n[2], 5.0 / 3.0, 0.4, recon,
+                  (0, 0, 0))
+
+
+def _smooth(g, rng, nmodes=4, kmax=2):
+    """Sum of a few random low-k Fourier modes at the cell positions."""
+    x, y, z = I._centres(g)
+    f = np.zeros((g.nz, g.ny, g.nx))
+    for _ in range(nmodes):
+        k = rng.integers(-kmax, kmax + 1, 3)
+        ph = rng.uniform(0, 2 * np.pi)
+        f = f + rng.normal() * np.cos(2 * np.pi * (k[0] * x + k[1] * y + k[2] * z) + ph)
+    return f
+
+
+def _params(g, seed):
+    """Initial conserved variables (rho, m, E) and an edge vector potential:
+    smooth density and pressure, Mach ~0.5 velocities, B = B_x0 + curl A."""
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + 0.1 * _smooth(g, rng)
+    v = [0.3 * _smooth(g, rng) for _ in range(3)]
+    p = 0.6 * (1.0 + 0.1 * _smooth(g, rng))
+    # the periodic part of the field; the mean field B_x0 is added separately
+    A = [0.05 * _smooth(g, rng) for _ in range(3)]
+    return rho, v, p, A
+
+
+def _state_from(g, rho, v, p, A, b0=(0.8, 0.0, 0.0)):
+    bx, by, bz = I.curl_edge_potential(g, *A)
+    bx, by, bz = bx + b0[0], by + b0[1], bz + b0[2]
+    s = {"rho": rho, "mx": rho * v[0], "my": rho * v[1], "mz": rho * v[2],
+         "bx": bx, "by": by, "bz": bz}
+    s["E"] = I._cell_energy(g, rho, v[0], v[1], v[2], p, bx, by, bz)
+    return s
+
+
+def test_curl_matches_definition_and_is_divergence_free():
+    _need_gpu()
+    import torch
+    from paper_2402_05240_amd.autograd import Simulator
+    g = _grid((12, 10, 9))
+    rng = np.random.default_rng(1)
+    A = [rng.standard_normal((g.nz, g.ny, g.nx)) for _ in range(3)]
+    sim = Simulator(g)
+    b = sim.curl(*[torch.from_numpy(a).cuda() for a in A])
+    torch.cuda.synchronize()
+    want = I.curl_edge_potential(g, *A)
+    for got, w in zip(b, want):
+        got = got.cpu().numpy()
+        assert np.abs(got - w).max() <= 1e-13 * np.abs(w).max()
+    bx, by, bz = [t.cpu().numpy() for t in b]
+    div = ((bx[:, :, 1:] - bx[:, :, :-1]) / g.dx + (by[:, 1:, :] - by[:, :-1, :]) / g.dy
+           + (bz[1:] - bz[:-1]) / g.dz)
+    scale = max(np.abs(bx).max(), np.abs(by).max(), np.abs(bz).max()) / g.dx
+    assert np.abs(div).max() <= 1e-13 * scale
+
+
+def test_curl_adjoint_dot_product_identity():
+    """<lam_B, curl A> = <curl^T lam_B, A> for random A and lam_B (the
+    duplicate face planes included on the B side)."""
+    _need_gpu()
+    import torch
+    from paper_2402_05240_amd.autograd import Simulator
+    g = _grid((11, 9, 10))
+    rng = np.random.default_rng(2)
+    A = [torch.from_numpy(rng.standard_normal((g.nz, g.ny, g.nx))).cuda() for _ in range(3)]
+    lb = [torch.from_numpy(rng.standard_normal(g.field_shape(f))).cuda() for f in ("bx", "by", "bz")]
+    sim = Simulator(g)
+    b = sim.curl(*A)
+    la = sim.curl_adjoint(*lb)
+    lhs = sum(float((x * y).sum()) for x, y in zip(lb, b))
+    rhs = sum(float((x * y).sum()) for x, y in zip(la, A))
+    scale = sum(float((x * y).abs().sum()) for x, y in zip(lb, b))
+    assert abs(lhs - rhs) <= 1e-13 * scale, (lhs, rhs)
+
+
+def test_step_function_backward_is_the_adjoint():
+    _need_gpu()
+    import torch
+    from paper_2402_05240_amd import autograd as AG
+    g = _grid((10, 9, 9))
+    rho, v, p, A = _params(g, 3)
+    s = _state_from(g, rho, v, p, A)
+    sim = AG.Simulator(g)
+    fields = [torch.from_numpy(s[f]).cuda().requires_grad_(True) for f in FIELDS]
+    dt = sim.cfl_dt(fields)
+    rng = np.random.default_rng(4)
+    lam = [torch.from_numpy(rng.standard_normal(g.field_shape(f))).cuda() for f in FIELDS]
+    out = AG.step(sim, fields, dt)
+    torch.autograd.backward(out, lam)
+    want = sim.adjoint([f.detach() for f in fields], lam, dt)
+    torch.cuda.synchronize()
+    for f, w, name in zip(fields, want, FIELDS):
+        scale = float(w.abs().max())
+        assert float((f.grad - w).abs().max()) <= 1e-13 * scale, name
+
+
+def test_checkpointed_rollout_gradient_independent_of_segment():
+    """9 steps with a checkpoint every 1, 3 (sqrt) and 9 steps: the same final
+    state (bit for bit) and the same gradient (to the summation-order
+    rounding of the adjoint's atomic accumulations)."""
+    _need_gpu()
+    import torch
+    from paper_2402_05240_amd import autograd as AG
+    g = _grid((10, 9, 11))
+    rho, v, p, A = _params(g, 5)
+    s = _state_from(g, rho, v, p, A)
+    sim = AG.Simulator(g)
+    rng = np.random.default_rng(6)
+    lam = [torch.from_numpy(rng.standard_normal(g.field_shape(f))).cuda() for f in FIELDS]
+    outs, grads, dts0 = [], [], None
+    for seg in (1, 3, 9):
+        fields = [torch.from_numpy(s[f]).cuda().requires_grad_(True) for f in FIELDS]
+        out, dts = AG.rollout(sim, fields, nsteps=9, segment=seg)
+        torch.autograd.backward(out, lam)
+        torch.cuda.synchronize()
+        outs.append([o.detach().cpu().numpy() for o in out])
+        grads.append([f.grad.cpu().numpy() for f in fields])
+        d = [float(x.item()) for x in dts]
+        if dts0 is None:
+            dts0 = d
+        assert d == dts0
+    for k in (1, 2):
+        for a, b in zip(outs[0], outs[k]):
+            assert np.array_equal(a, b)
+        for a, b, name in zip(grads[0], grads[k], FIELDS):
+            assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max(), name
+
+
+def _oracle_loss(g, rho, m, E, A, b0, dts, target):
+    bx, by, bz = I.curl_edge_potential(g, *A)
+    s = {"rho": rho, "mx": m[0], "my": m[1], "mz": m[2], "E": E,
+         "bx": bx + b0[0], "by": by + b0[1], "bz": bz + b0[2]}
+    for dt in dts:
+        s, _, st = ref.step(g, s, dt, nthreads=4)
+        assert st == 0
+    return float(np.mean((s["rho"] - target) ** 2))
+
+
+def test_inverse_problem_gradient_matches_oracle_differences():
+    """16^3 turbulence-like state, 6 PLMC steps on the recorded CFL chain,
+    loss = mean((rho_final - target)^2).  The gradient with respect to
+    (rho, m, E) at t = 0 and to the vector potential A, from the checkpointed
+    adjoint rollout, element by element (6 sampled coordinates of each of the
+    8 parameter arrays) against central differences of the oracle's loss:
+    within 1e-6 relative.  The rollout is piecewise smooth; a coordinate whose
+    difference quotients at h and h/4 disagree has a branch point of the
+    6-step map within its stencil and is not compared (at most 10%)."""
+    _need_gpu()
+    import torch
+    from paper_2402_05240_amd import autograd as AG
+    g = _grid((16, 16, 16))
+    rho, v, p, A = _params(g, 7)
+    b0 = (0.8, 0.0, 0.0)
+    s0 = _state_from(g, rho, v, p, A, b0)
+    rng = np.random.default_rng(8)
+    target = s0["rho"] * (1.0 + 0.05 * _smooth(g, rng))
+    sim = AG.Simulator(g)
+
+    names = ("rho", "mx", "my", "mz", "E")
+    cons = [torch.from_numpy(s0[f]).cuda().requires_grad_(True) for f in names]
+    pot = [torch.from_numpy(a).cuda().requires_grad_(True) for a in A]
+    bfaces = AG.curl(sim, *pot)
+    fields = cons + [b + c for b, c in zip(bfaces, b0)]
+    out, dts = AG.rollout(sim, fields, nsteps=6)
+    tgt = torch.from_numpy(target).cuda()
+    loss = ((out[0] - tgt) ** 2).mean()
+    loss.backward()
+    torch.cuda.synchronize()
+    dts = [float(x.item()) for x in dts]
+    grads = [c.grad.cpu().numpy() for c in cons] + [a.grad.cpu().numpy() for a in pot]
+    params = [s0[f] for f in names] + list(A)
+    base = _oracle_loss(g, params[0], params[1:4], params[4], params[5:], b0, dts, target)
+    _say("loss %.12e (GPU %.12e), dts %s" % (base, float(loss.item()), dts))
+    assert abs(base - float(loss.item())) <= 1e-10 * base
+
+    def fd(which, idx, h):
+        vals = []
+        for sgn in (1.0, -1.0):
+            q = [x.copy() if k == which else x for k, x in enumerate(params)]
+            q[which][idx] += sgn * h
+            vals.append(_oracle_loss(g, q[0], q[1:4], q[4], q[5:], b0, dts, target))
+        return (vals[0] - vals[1]) / (2 * h)
+
+    checked = skipped = 0
+    worst = 0.0
+    for which, gr in enumerate(grads):
+        floor = 1e-2 * float(np.sqrt(np.mean(gr ** 2)))
+        # an edge of A moves four faces by h / dx: scale its step to move B by ~1e-5
+        H = 1e-5 * (g.dx if which >= 5 else 1.0)
+        for _ in range(6):
+            idx = tuple(int(rng.integers(0, m)) for m in gr.shape)
+            f1, f2 = fd(which, idx, H), fd(which, idx, H / 4)
+            den = max(abs(f1), floor)
+            if abs(f1 - f2) > 1e-6 * den:
+                skipped += 1
+                continue
+            err = abs(float(gr[idx]) - f1) / den
+            worst = max(worst, err)
+            checked += 1
+            assert err <= 1e-6, (which, idx, float(gr[idx]), f1)
+    _say("checked %d, skipped %d (branch point), worst rel err %.2e" % (checked, skipped, worst))
+    assert skipped <= 0.1 * (checked + skipped)
