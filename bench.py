@@ -419,15 +419,36 @@ def adjoint_bench(n, steps, warmup):
     def fstep():
         fwd.set_dt(dt)
         fwd.step()
+    # taped forward step and the adjoint from its tape
+    from paper_2402_05240_amd import autograd as AG
+    sim = AG.Simulator(g)
+    fields = [adj.state.t[f] for f in I.FIELDS]
+    lam = [adj.lam_out.t[f] for f in I.FIELDS]
+    tape = sim.new_tape()
+
+    def ftaped():
+        sim.step_taped(fields, adj.dt, tape)
+
+    def ataped():
+        sim.adjoint_taped(fields, lam, adj.dt, tape)
     for _ in range(warmup):
         fstep()
         adj.run()
+        ftaped()
+        ataped()
     ms_f = timed(fstep, steps)
     ms_a = timed(adj.run, steps)
+    ms_ft = timed(ftaped, steps)
+    ftaped()
+    ms_at = timed(ataped, steps)
     return {"workload": "turbulence_plmc_%d" % n, "grid": [n, n, n], "recon": "PLMC",
             "steps": steps, "forward_ms": ms_f, "adjoint_ms": ms_a, "ratio": ms_a / ms_f,
+            "taped_forward_ms": ms_ft, "taped_adjoint_ms": ms_at,
+            "ratio_taped": ms_at / ms_f, "tape_bytes": sim.tape_bytes,
             "workspace_bytes": adj.ws_bytes,
-            "note": "adjoint includes the recomputation of the step's intermediates"}
+            "note": "ratio: self-contained adjoint (recomputes the step's fluxes) / forward "
+                    "step; ratio_taped: adjoint from the tape of a taped forward step "
+                    "(vlct_step_taped, same kernels as the step plus the tape) / forward step"}
 
 
 def inverse_bench(n, steps):

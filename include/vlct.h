@@ -166,6 +166,35 @@ int vlct_step_adjoint(const vlct_grid *g, const vlct_state *in, const vlct_state
                       const vlct_state *lam_in, const double *dt_dev, void *ws, size_t ws_bytes,
                       void *stream);
 
+/* --- taped steps ----------------------------------------------------------
+ * A taped step is vlct_step (same kernels, same results bit for bit) that
+ * also keeps, in a caller-owned device buffer, what the adjoint would
+ * otherwise recompute: the half-step state U^{n+1/2} and the upwind side of
+ * every face of both stages (one byte each).  The adjoint of that step can
+ * then skip the recomputation of the fluxes.
+ *
+ * Bytes of one step's tape (0 if the descriptor is invalid). */
+size_t vlct_tape_bytes(const vlct_grid *g);
+
+/* vlct_step (same arguments and rules) writing the step's tape to `tape`
+ * (device, tape_bytes >= vlct_tape_bytes(g), else VLCT_EWORKSPACE).  The tape
+ * stays valid while `in` is unchanged. */
+int vlct_step_taped(const vlct_grid *g, const vlct_state *in, const vlct_state *out,
+                    const double *dt_dev, double *next_dt_dev, uint32_t *status_dev, void *ws,
+                    size_t ws_bytes, void *tape, size_t tape_bytes, void *stream);
+
+/* Bytes of device workspace vlct_step_adjoint_taped needs (0 if invalid). */
+size_t vlct_adjoint_taped_workspace_bytes(const vlct_grid *g);
+
+/* vlct_step_adjoint for the step vlct_step_taped(g, in, ..., dt_dev, ...)
+ * wrote `tape` for (same in, same *dt_dev): same result (up to the summation
+ * order of accumulations), without recomputing the step's fluxes.  tape:
+ * device, read only.  Same argument rules and codes as vlct_step_adjoint;
+ * VLCT_EWORKSPACE also for a short tape. */
+int vlct_step_adjoint_taped(const vlct_grid *g, const vlct_state *in, const vlct_state *lam_out,
+                            const vlct_state *lam_in, const double *dt_dev, const void *tape,
+                            size_t tape_bytes, void *ws, size_t ws_bytes, void *stream);
+
 /* Face fields of an edge-centred vector potential, B = curl_h A, on a periodic
  * grid (the vertex/edge potential of the CT scheme, Sec. 2.2; its discrete
  * divergence vanishes to rounding).  ax[k][j][i] sits at (i, j-1/2, k-1/2),

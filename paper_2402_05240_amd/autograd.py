@@ -12,7 +12,10 @@ reuses exactly those values when it recomputes states for the backward pass.
 
 Memory: a rollout of N steps keeps its input and one state every `segment`
 steps (default ceil(sqrt(N))); the backward pass recomputes one segment at a
-time from its checkpoint, so at most about 2 sqrt(N) states are alive.
+time from its checkpoint with taped steps (vlct_step_taped: the half-step
+state and the faces' upwind sides of each step, so the adjoint need not
+recompute the fluxes), so at most about sqrt(N) states and sqrt(N) tapes are
+alive.
 """
 from __future__ import annotations
 
@@ -48,6 +51,9 @@ class Simulator:
             raise ValueError("invalid grid descriptor")
         self.ws_step = torch.empty(self.ws_step_bytes, dtype=torch.uint8, device=device)
         self._ws_adj = None
+        self._ws_adj_taped = None
+        self.tape_bytes = vlct.vlct_tape_bytes(self.cg)
+        self.ws_adj_taped_bytes = vlct.vlct_adjoint_taped_workspace_bytes(self.cg)
         self.status = torch.zeros(1, dtype=torch.int32, device=device)
 
     def _stream(self) -> int:
@@ -58,6 +64,17 @@ class Simulator:
             torch = _torch()
             self._ws_adj = torch.empty(self.ws_adj_bytes, dtype=torch.uint8, device=self.device)
         return self._ws_adj
+
+    def ws_adj_taped(self):
+        if self._ws_adj_taped is None:
+            torch = _torch()
+            self._ws_adj_taped = torch.empty(self.ws_adj_taped_bytes, dtype=torch.uint8,
+                                             device=self.device)
+        return self._ws_adj_taped
+
+    def new_tape(self):
+        torch = _torch()
+        return torch.empty(self.tape_bytes, dtype=torch.uint8, device=self.device)
 
     def empty_state(self) -> Fields:
         torch = _torch()
@@ -100,6 +117,33 @@ class Simulator:
         if rc:
             raise vlct.VlctError(rc, "vlct_step")
         return out
+
+    def step_taped(self, fields: Sequence, dt, tape, next_dt=None) -> Fields:
+        """step() that also writes the step's tape (see vlct_step_taped)."""
+        fields = self._check(fields)
+        out = self.empty_state()
+        rc = vlct.vlct_step_taped(self.cg, self.c_state(fields), self.c_state(out), dt.data_ptr(),
+                                  next_dt.data_ptr() if next_dt is not None else 0,
+                                  self.status.data_ptr(), self.ws_step.data_ptr(),
+                                  self.ws_step_bytes, tape.data_ptr(), self.tape_bytes,
+                                  self._stream())
+        if rc:
+            raise vlct.VlctError(rc, "vlct_step_taped")
+        return out
+
+    def adjoint_taped(self, fields: Sequence, lam_out: Sequence, dt, tape) -> Fields:
+        """adjoint() of a step whose tape step_taped() wrote."""
+        fields = self._check(fields)
+        lam_out = self._check(lam_out)
+        lam_in = self.empty_state()
+        ws = self.ws_adj_taped()
+        rc = vlct.vlct_step_adjoint_taped(self.cg, self.c_state(fields), self.c_state(lam_out),
+                                          self.c_state(lam_in), dt.data_ptr(), tape.data_ptr(),
+                                          self.tape_bytes, ws.data_ptr(), self.ws_adj_taped_bytes,
+                                          self._stream())
+        if rc:
+            raise vlct.VlctError(rc, "vlct_step_adjoint_taped")
+        return lam_in
 
     def adjoint(self, fields: Sequence, lam_out: Sequence, dt) -> Fields:
         """lam_in = (d step(fields) / d fields)^T lam_out into new arrays."""
@@ -171,7 +215,7 @@ def _make_functions():
         `record` is set: CFL chain starting from the input state)."""
 
         @staticmethod
-        def forward(ctx, sim, dts, segment, record, *fields):
+        def forward(ctx, sim, dts, segment, record, taped, *fields):
             cur = sim._check(fields)
             nsteps = len(dts)
             if record:
@@ -183,6 +227,7 @@ def _make_functions():
                 if (i + 1) % segment == 0 and i + 1 < nsteps:
                     ckpts.append(cur)
             ctx.sim, ctx.dts, ctx.segment, ctx.nck = sim, list(dts), segment, len(ckpts)
+            ctx.taped = taped
             ctx.save_for_backward(*[t for c in ckpts for t in c])
             return cur
 
@@ -196,12 +241,23 @@ def _make_functions():
             for s in reversed(range(len(ckpts))):
                 start, stop = s * seg, min((s + 1) * seg, nsteps)
                 states = [ckpts[s]]
-                for i in range(start, stop - 1):
-                    states.append(sim.step(states[-1], dts[i]))
-                for i in reversed(range(start, stop)):
-                    lam = sim.adjoint(states[i - start], lam, dts[i])
+                if ctx.taped:
+                    tapes = []
+                    for i in range(start, stop):
+                        tapes.append(sim.new_tape())
+                        nxt = sim.step_taped(states[-1], dts[i], tapes[-1])
+                        if i + 1 < stop:
+                            states.append(nxt)
+                    for i in reversed(range(start, stop)):
+                        lam = sim.adjoint_taped(states[i - start], lam, dts[i], tapes[i - start])
+                    del tapes
+                else:
+                    for i in range(start, stop - 1):
+                        states.append(sim.step(states[-1], dts[i]))
+                    for i in reversed(range(start, stop)):
+                        lam = sim.adjoint(states[i - start], lam, dts[i])
                 del states
-            return (None, None, None, None) + tuple(lam)
+            return (None, None, None, None, None) + tuple(lam)
 
     class CurlFn(torch.autograd.Function):
         """Face fields of an edge-centred vector potential, B = curl_h A."""
@@ -239,10 +295,12 @@ def step(sim: Simulator, fields: Sequence, dt) -> Fields:
 
 
 def rollout(sim: Simulator, fields: Sequence, nsteps: int = None, dts: Optional[List] = None,
-            segment: Optional[int] = None):
+            segment: Optional[int] = None, taped: bool = True):
     """Differentiable rollout with sqrt(N) checkpointing.  Either `dts` (list
     of 1-element device tensors) or `nsteps` (CFL chain recorded by the
-    forward pass).  Returns (fields, dts); the backward pass reuses the dts."""
+    forward pass).  Returns (fields, dts); the backward pass reuses the dts.
+    taped=False recomputes each step's fluxes inside its adjoint instead of
+    keeping a tape per step of the segment being reversed."""
     torch = _torch()
     record = dts is None
     if record:
@@ -251,7 +309,7 @@ def rollout(sim: Simulator, fields: Sequence, nsteps: int = None, dts: Optional[
         dts = [torch.zeros(1, dtype=torch.float64, device=sim.device) for _ in range(nsteps)]
     n = len(dts)
     seg = segment or max(1, int(math.ceil(math.sqrt(n))))
-    out = _funcs()[1].apply(sim, dts, seg, record, *fields)
+    out = _funcs()[1].apply(sim, dts, seg, record, bool(taped), *fields)
     return out, dts
 
 

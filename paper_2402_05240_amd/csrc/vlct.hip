@@ -941,6 +941,25 @@ int launch_ct(const Geom &g, bool full, const Prims &P, const Flux &F, const Sta
     return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
 }
 
+__global__ void k_pack_sides(Geom g, Flux F, uint8_t *s0, uint8_t *s1, uint8_t *s2)
+{
+    const idx_t N = (idx_t)g.n[0] * g.n[1] * g.n[2];
+    const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    const int i = (int)(t % g.n[0]), j = (int)((t / g.n[0]) % g.n[1]),
+              k = (int)(t / ((idx_t)g.n[0] * g.n[1]));
+    s0[t] = side_code(F.f[0][7][fidx(g, 0, i, j, k)]);
+    s1[t] = side_code(F.f[1][7][fidx(g, 1, i, j, k)]);
+    s2[t] = side_code(F.f[2][7][fidx(g, 2, i, j, k)]);
+}
+
+int launch_pack_sides(const Geom &g, const Flux &F, uint8_t *const side[3], hipStream_t s)
+{
+    const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+    k_pack_sides<<<nblocks(N), kBlock, 0, s>>>(g, F, side[0], side[1], side[2]);
+    return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
+}
+
 static int launch_dt(const Geom &g, const StateP &st, const Bound &B, const Layout &L,
                      double *dt_out, uint32_t *status, hipStream_t s)
 {
@@ -1070,6 +1089,60 @@ int vlct_step(const vlct_grid *vg, const vlct_state *in, const vlct_state *out,
     const StateP half = as_const(B.half);
     if (!rc) rc = launch_prims(g, half, B.P, status_dev, s);
     if (!rc) rc = launch_fluxes(g, half, B.P, B.F, vg->recon, status_dev, s);
+    if (!rc) rc = launch_ct(g, true, B.P, B.F, sin, as_mut(out), dt_dev, status_dev, s);
+    if (rc) return rc;
+    if (next_dt_dev) return launch_dt(g, as_const(out), B, L, next_dt_dev, status_dev, s);
+    return VLCT_OK;
+}
+
+size_t vlct_tape_bytes(const vlct_grid *g)
+{
+    if (!grid_ok(g)) return 0;
+    const int n[3] = {g->nx, g->ny, g->nz};
+    return tape_layout(n).total;
+}
+
+int vlct_step_taped(const vlct_grid *vg, const vlct_state *in, const vlct_state *out,
+                    const double *dt_dev, double *next_dt_dev, uint32_t *status_dev, void *ws,
+                    size_t ws_bytes, void *tape, size_t tape_bytes, void *stream)
+{
+    if (!grid_ok(vg) || !state_ok(in) || !state_ok(out) || !dt_dev) return VLCT_EINVAL;
+    {
+        const double *pi[8] = {in->rho, in->mx, in->my, in->mz, in->E, in->bx, in->by, in->bz};
+        const double *po[8] = {out->rho, out->mx, out->my, out->mz, out->E, out->bx, out->by, out->bz};
+        bool all_same = true;
+        for (int f = 0; f < 8; ++f) all_same &= (pi[f] == po[f]);
+        if (!all_same)
+            for (int f = 0; f < 8; ++f)
+                for (int h = 0; h < 8; ++h)
+                    if (po[f] == pi[h]) return VLCT_EINVAL;
+    }
+    const Geom g = make_geom(vg);
+    const Layout L = layout(g);
+    const TapeLayout T = tape_layout(g.n);
+    if (!ws || ws_bytes < L.total || !tape || tape_bytes < T.total) return VLCT_EWORKSPACE;
+    const Bound B = bind(L, ws);
+    char *tb = static_cast<char *>(tape);
+    StateW half;
+    for (int f = 0; f < 8; ++f) {
+        double *a = reinterpret_cast<double *>(tb + T.half[f]);
+        if (f < 5) half.u[f] = a; else half.b[f - 5] = a;
+    }
+    uint8_t *side[2][3];
+    for (int h = 0; h < 2; ++h)
+        for (int d = 0; d < 3; ++d) side[h][d] = reinterpret_cast<uint8_t *>(tb + T.side[h][d]);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const StateP sin = as_const(in);
+    // the steps of vlct_step with the half-step state and both stages' upwind
+    // sides kept in the tape
+    int rc = launch_prims(g, sin, B.P, status_dev, s);
+    if (!rc) rc = launch_fluxes(g, sin, B.P, B.F, VLCT_RECON_PCM, status_dev, s);
+    if (!rc) rc = launch_pack_sides(g, B.F, side[0], s);
+    if (!rc) rc = launch_ct(g, false, B.P, B.F, sin, half, dt_dev, status_dev, s);
+    const StateP hc = as_const(half);
+    if (!rc) rc = launch_prims(g, hc, B.P, status_dev, s);
+    if (!rc) rc = launch_fluxes(g, hc, B.P, B.F, vg->recon, status_dev, s);
+    if (!rc) rc = launch_pack_sides(g, B.F, side[1], s);
     if (!rc) rc = launch_ct(g, true, B.P, B.F, sin, as_mut(out), dt_dev, status_dev, s);
     if (rc) return rc;
     if (next_dt_dev) return launch_dt(g, as_const(out), B, L, next_dt_dev, status_dev, s);

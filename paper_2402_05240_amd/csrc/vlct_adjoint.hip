@@ -35,8 +35,9 @@ namespace vlct {
 // cotangent arrays of one stage's transposes (interior cells, cell_store order)
 struct AdStage {
     double *le[3];        // edge fields E_A at the edge indexed like its cell
+    uint32_t *wcode;      // upwind sides of the edges' four faces, 8 bits per component
     double *lw[8];        // primitives (rho, v, P, B_cc)
-    double *lrec[3][14];  // reconstruction outputs per axis: fm (7), fp (7)
+    double *lrec[3][14];  // interface states per axis: low face (7), high face (7)
 };
 
 __device__ __forceinline__ int wrapc(int i, int n) { return map_cell(i, n, VLCT_BC_PERIODIC); }
@@ -49,12 +50,6 @@ __device__ __forceinline__ idx_t cell_of(const Geom &g, const int x[3])
 {
     return cell_of(g, x[0], x[1], x[2]);
 }
-// flux-array index of the interior image of face (axis d) at x
-__device__ __forceinline__ idx_t fwrap(const Geom &g, int d, const int x[3])
-{
-    return fidx(g, d, wrapc(x[0], g.n[0]), wrapc(x[1], g.n[1]), wrapc(x[2], g.n[2]));
-}
-
 __device__ __forceinline__ void cell_coords(const Geom &g, idx_t t, int x[3])
 {
     x[0] = (int)(t % g.n[0]);
@@ -84,26 +79,37 @@ __device__ __forceinline__ W7 w7_at(const Prims &P, int d, idx_t o)
               P.w[4][o], P.w[lab_slot(d, 5)][o], P.w[lab_slot(d, 6)][o]};
 }
 
-__device__ __forceinline__ void upwind_weights(double s, double &lo, double &hi)
-{
-    lo = s > 0.0 ? 1.0 : (s < 0.0 ? 0.0 : 0.5);
-    hi = 1.0 - lo;
-}
+// upwind sides of one stage's interior faces (side_code, per axis, at the
+// index of the cell whose low face it is)
+struct Sides {
+    const uint8_t *s[3];
+};
 
-// upwind weights of edge (A, x0): w[0..7] = w1l, w1h, w2l, w2h, w3l, w3h, w4l, w4h
-// from the indicators of the faces F_B(x0), F_B(x0 - e_C), F_C(x0), F_C(x0 - e_B)
+// 8-bit code of edge (A, x0): the sides of the faces F_B(x0), F_B(x0 - e_C),
+// F_C(x0), F_C(x0 - e_B) (the four upwind terms of the edge field)
 template <int A>
-__device__ __forceinline__ void edge_weights(const Geom &g, const Flux &F, const int x0[3],
-                                             double w[8])
+__device__ __forceinline__ uint32_t edge_code(const Geom &g, const Sides &sd, const int x0[3])
 {
     constexpr int B = (A + 1) % 3, C = (A + 2) % 3;
     int xb[3] = {x0[0], x0[1], x0[2]}, xc[3] = {x0[0], x0[1], x0[2]};
     xb[B] -= 1;
     xc[C] -= 1;
-    upwind_weights(F.f[B][7][fwrap(g, B, x0)], w[0], w[1]);
-    upwind_weights(F.f[B][7][fwrap(g, B, xc)], w[2], w[3]);
-    upwind_weights(F.f[C][7][fwrap(g, C, x0)], w[4], w[5]);
-    upwind_weights(F.f[C][7][fwrap(g, C, xb)], w[6], w[7]);
+    return (uint32_t)sd.s[B][cell_of(g, x0)] | ((uint32_t)sd.s[B][cell_of(g, xc)] << 2) |
+           ((uint32_t)sd.s[C][cell_of(g, x0)] << 4) | ((uint32_t)sd.s[C][cell_of(g, xb)] << 6);
+}
+
+// upwind weights of edge (A, x0): w[0..7] = w1l, w1h, w2l, w2h, w3l, w3h, w4l, w4h
+template <int A>
+__device__ __forceinline__ void edge_weights(const Geom &g, const AdStage &S, const int x0[3],
+                                             double w[8])
+{
+    const uint32_t c = S.wcode[cell_of(g, x0)] >> (8 * A);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t k = (c >> (2 * q)) & 3u;
+        w[2 * q] = k == 0u ? 1.0 : (k == 1u ? 0.0 : 0.5);
+        w[2 * q + 1] = 1.0 - w[2 * q];
+    }
 }
 
 __global__ void k_ad_fill(double *p, idx_t n)
@@ -157,7 +163,8 @@ __global__ void k_ad_add(Geom g, StateW acc, StateP add)
 
 // edge-field cotangents (curl of the face update transposed): the face update
 // is b_x -= cy (Ez(j+1) - Ez(j)) - cz (Ey(k+1) - Ey(k)) and cyclically
-__global__ void k_ad_edges(Geom g, StateP lout, AdStage S, const double *dt_dev, double factor)
+__global__ void k_ad_edges(Geom g, StateP lout, Sides sd, AdStage S, const double *dt_dev,
+                           double factor)
 {
     const idx_t N = (idx_t)g.n[0] * g.n[1] * g.n[2];
     const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -173,11 +180,12 @@ __global__ void k_ad_edges(Geom g, StateP lout, AdStage S, const double *dt_dev,
     S.le[0][t] = cz * (lb(1, i, j, k) - lb(1, i, j, k - 1)) + cy * (lb(2, i, j - 1, k) - lb(2, i, j, k));
     S.le[1][t] = cz * (lb(0, i, j, k - 1) - lb(0, i, j, k)) + cx * (lb(2, i, j, k) - lb(2, i - 1, j, k));
     S.le[2][t] = cy * (lb(0, i, j, k) - lb(0, i, j - 1, k)) + cx * (lb(1, i - 1, j, k) - lb(1, i, j, k));
+    S.wcode[t] = edge_code<0>(g, sd, x) | (edge_code<1>(g, sd, x) << 8) | (edge_code<2>(g, sd, x) << 16);
 }
 
 // cotangents of the 7 fluxes of the face of axis D at x (the low face of cell x)
 template <int D>
-__device__ __forceinline__ void flux_cotangent(const Geom &g, const StateP &lout, const Flux &F,
+__device__ __forceinline__ void flux_cotangent(const Geom &g, const StateP &lout,
                                                const AdStage &S, const int x[3], idx_t t,
                                                double c, double lf[7])
 {
@@ -195,11 +203,11 @@ __device__ __forceinline__ void flux_cotangent(const Geom &g, const StateP &lout
     {
         constexpr int A = (D + 2) % 3, C = (A + 2) % 3;
         double w[8];
-        edge_weights<A>(g, F, x, w);
+        edge_weights<A>(g, S, x, w);
         double acc = -0.25 * (1.0 + w[5] + w[7]) * S.le[A][t];
         int y[3] = {x[0], x[1], x[2]};
         y[C] += 1;
-        edge_weights<A>(g, F, y, w);
+        edge_weights<A>(g, S, y, w);
         acc += -0.25 * (1.0 + w[4] + w[6]) * S.le[A][cell_of(g, y)];
         lf[5] = acc;
     }
@@ -208,23 +216,24 @@ __device__ __forceinline__ void flux_cotangent(const Geom &g, const StateP &lout
     {
         constexpr int A = (D + 1) % 3, B = (A + 1) % 3;
         double w[8];
-        edge_weights<A>(g, F, x, w);
+        edge_weights<A>(g, S, x, w);
         double acc = 0.25 * (1.0 + w[1] + w[3]) * S.le[A][t];
         int y[3] = {x[0], x[1], x[2]};
         y[B] += 1;
-        edge_weights<A>(g, F, y, w);
+        edge_weights<A>(g, S, y, w);
         acc += 0.25 * (1.0 + w[0] + w[2]) * S.le[A][cell_of(g, y)];
         lf[6] = acc;
     }
 }
 
 // faces of axis D: flux cotangents, then HLLD reversed at the forward states.
-// PCM: the states are the cell primitives (atomics into their cotangents);
-// otherwise they are the (floored) reconstruction outputs of the two cells,
-// whose cotangents are stored for the reconstruction transpose.
+// PCM: the states are the cell primitives; otherwise they are the (floored)
+// reconstruction outputs of the two cells.  Either way the cotangents of the
+// face's two states are stored per cell and axis (as the high state of the
+// left cell and the low state of the right cell) for the next transpose.
 template <int D, int RECON>
 __global__ __launch_bounds__(kBlock) void k_ad_faces(Geom g, Prims P, StateP st, StateP lout,
-                                                     Flux F, AdStage S, StateW lacc,
+                                                     AdStage S, StateW lacc,
                                                      const double *dt_dev, double factor)
 {
     const idx_t N = (idx_t)g.n[0] * g.n[1] * g.n[2];
@@ -233,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_ad_faces(Geom g, Prims P, StateP st,
     int x[3];
     cell_coords(g, t, x);
     double lf[7];
-    flux_cotangent<D>(g, lout, F, S, x, t, factor * dt_dev[0] / g.dl[D], lf);
+    flux_cotangent<D>(g, lout, S, x, t, factor * dt_dev[0] / g.dl[D], lf);
     auto at = [&](int off) {
         int q[3] = {x[0], x[1], x[2]};
         q[D] += off;
@@ -264,24 +273,16 @@ __global__ __launch_bounds__(kBlock) void k_ad_faces(Geom g, Prims P, StateP st,
     const idx_t cl = cell_of(g, l);
     const double vl[7] = {aL.d, aL.u, aL.v, aL.w, aL.p, aL.by, aL.bz};
     const double vr[7] = {aR.d, aR.u, aR.v, aR.w, aR.p, aR.by, aR.bz};
-    if (RECON == VLCT_RECON_PCM) {
+    // a floored interface component is a constant (no floors on PCM states)
 #pragma unroll
-        for (int s = 0; s < 7; ++s) {
-            atomicAdd(&S.lw[lab_slot(D, s)][cl], vl[s]);
-            atomicAdd(&S.lw[lab_slot(D, s)][t], vr[s]);
-        }
-    } else {
-        // a floored interface component is a constant
-#pragma unroll
-        for (int s = 0; s < 7; ++s) {
-            double a = vl[s], b = vr[s];
-            if (s == 0 && (fl & kStatusDensityFloor)) a = 0.0;
-            if (s == 4 && (fl & kStatusPressureFloor)) a = 0.0;
-            if (s == 0 && (fr & kStatusDensityFloor)) b = 0.0;
-            if (s == 4 && (fr & kStatusPressureFloor)) b = 0.0;
-            S.lrec[D][7 + s][cl] = a;  // high face (fp) of the left cell
-            S.lrec[D][s][t] = b;       // low face (fm) of the right cell
-        }
+    for (int s = 0; s < 7; ++s) {
+        double a = vl[s], b = vr[s];
+        if (s == 0 && (fl & kStatusDensityFloor)) a = 0.0;
+        if (s == 4 && (fl & kStatusPressureFloor)) a = 0.0;
+        if (s == 0 && (fr & kStatusDensityFloor)) b = 0.0;
+        if (s == 4 && (fr & kStatusPressureFloor)) b = 0.0;
+        S.lrec[D][7 + s][cl] = a;  // high face of the left cell
+        S.lrec[D][s][t] = b;       // low face of the right cell
     }
 }
 
@@ -329,33 +330,35 @@ __global__ __launch_bounds__(kBlock) void k_ad_recon(Geom g, Prims P, AdStage S)
 
 // cotangent of -(v x B)_A at cell x from the four A-edges around it
 template <int A>
-__device__ __forceinline__ double eref_cotangent(const Geom &g, const Flux &F, const AdStage &S,
-                                                 const int x[3])
+__device__ __forceinline__ double eref_cotangent(const Geom &g, const AdStage &S, const int x[3])
 {
     constexpr int B = (A + 1) % 3, C = (A + 2) % 3;
     double w[8], acc;
     // the cell is r00 of edge x, r10 of edge x + e_B, r01 of edge x + e_C and
     // r11 of edge x + e_B + e_C
-    edge_weights<A>(g, F, x, w);
+    edge_weights<A>(g, S, x, w);
     acc = (w[1] + w[5]) * S.le[A][cell_of(g, x)];
     int y[3] = {x[0], x[1], x[2]};
     y[B] += 1;
-    edge_weights<A>(g, F, y, w);
+    edge_weights<A>(g, S, y, w);
     acc += (w[0] + w[7]) * S.le[A][cell_of(g, y)];
     y[B] -= 1;
     y[C] += 1;
-    edge_weights<A>(g, F, y, w);
+    edge_weights<A>(g, S, y, w);
     acc += (w[3] + w[4]) * S.le[A][cell_of(g, y)];
     y[B] += 1;
-    edge_weights<A>(g, F, y, w);
+    edge_weights<A>(g, S, y, w);
     acc += (w[2] + w[6]) * S.le[A][cell_of(g, y)];
     return -0.25 * acc;
 }
 
 // reference fields -(v x B) and primitive recovery (Sec. 2.1; B_cc = face
 // average) reversed into the cotangents of the stage's conserved cells and
-// faces; a floored quantity is a constant
-__global__ void k_ad_prims(Geom g, StateP st, Prims P, Flux F, AdStage S, StateW lacc)
+// faces; a floored quantity is a constant.  GATHER (PCM stage): the primitive
+// cotangents are the sums of the stored face-state cotangents of the cell;
+// otherwise the reconstruction transposes have accumulated them.
+template <bool GATHER>
+__global__ __launch_bounds__(kBlock) void k_ad_prims(Geom g, StateP st, Prims P, AdStage S, StateW lacc)
 {
     const idx_t N = (idx_t)g.n[0] * g.n[1] * g.n[2];
     const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -364,14 +367,24 @@ __global__ void k_ad_prims(Geom g, StateP st, Prims P, Flux F, AdStage S, StateW
     cell_coords(g, t, x);
     const int i = x[0], j = x[1], k = x[2];
     double lw[8];
+    if (GATHER) {
 #pragma unroll
-    for (int f = 0; f < 8; ++f) lw[f] = S.lw[f][t];
+        for (int f = 0; f < 8; ++f) lw[f] = 0.0;
+#pragma unroll
+        for (int D = 0; D < 3; ++D)
+#pragma unroll
+            for (int q = 0; q < 7; ++q)
+                lw[lab_slot(D, q)] += S.lrec[D][q][t] + S.lrec[D][7 + q][t];
+    } else {
+#pragma unroll
+        for (int f = 0; f < 8; ++f) lw[f] = S.lw[f][t];
+    }
     {
         const idx_t o = pidx(g, i, j, k);
         const double vx = P.w[1][o], vy = P.w[2][o], vz = P.w[3][o];
         const double bx = P.w[5][o], by = P.w[6][o], bz = P.w[7][o];
-        const double ex = eref_cotangent<0>(g, F, S, x), ey = eref_cotangent<1>(g, F, S, x),
-                     ez = eref_cotangent<2>(g, F, S, x);
+        const double ex = eref_cotangent<0>(g, S, x), ey = eref_cotangent<1>(g, S, x),
+                     ez = eref_cotangent<2>(g, S, x);
         lw[1] += bz * ey - by * ez;
         lw[2] += -bz * ex + bx * ez;
         lw[3] += by * ex - bx * ey;
@@ -418,20 +431,20 @@ static void fill(double *p, size_t n, hipStream_t s)
 }
 
 // transposes of one stage: lout is the cotangent of the stage's output state,
-// st/P/F the stage's input state, primitives and forward fluxes; the result
+// st/P/sd the stage's input state, primitives and upwind sides; the result
 // is added to lacc (the cotangent of the stage's input state).  lw_span is
 // the number of doubles of the contiguous span of the 8 primitive cotangents.
 static void stage_adjoint(const Geom &g, double factor, const StateP &lout, const StateP &st,
-                          const Prims &P, const Flux &F, int recon, const AdStage &S,
+                          const Prims &P, const Sides &sd, int recon, const AdStage &S,
                           size_t lw_span, const StateW &lacc, const double *dt, hipStream_t s)
 {
     const unsigned gc = nblocks((size_t)g.n[0] * g.n[1] * g.n[2]);
-    fill(S.lw[0], lw_span, s);
-    k_ad_edges<<<gc, kBlock, 0, s>>>(g, lout, S, dt, factor);
+    if (recon != VLCT_RECON_PCM) fill(S.lw[0], lw_span, s);
+    k_ad_edges<<<gc, kBlock, 0, s>>>(g, lout, sd, S, dt, factor);
 #define VLCT_AD_FACES(R)                                                                   \
-    k_ad_faces<0, R><<<gc, kBlock, 0, s>>>(g, P, st, lout, F, S, lacc, dt, factor);        \
-    k_ad_faces<1, R><<<gc, kBlock, 0, s>>>(g, P, st, lout, F, S, lacc, dt, factor);        \
-    k_ad_faces<2, R><<<gc, kBlock, 0, s>>>(g, P, st, lout, F, S, lacc, dt, factor);
+    k_ad_faces<0, R><<<gc, kBlock, 0, s>>>(g, P, st, lout, S, lacc, dt, factor);           \
+    k_ad_faces<1, R><<<gc, kBlock, 0, s>>>(g, P, st, lout, S, lacc, dt, factor);           \
+    k_ad_faces<2, R><<<gc, kBlock, 0, s>>>(g, P, st, lout, S, lacc, dt, factor);
 #define VLCT_AD_RECON(R)                                                                   \
     k_ad_recon<0, R><<<gc, kBlock, 0, s>>>(g, P, S);                                       \
     k_ad_recon<1, R><<<gc, kBlock, 0, s>>>(g, P, S);                                       \
@@ -447,16 +460,21 @@ static void stage_adjoint(const Geom &g, double factor, const StateP &lout, cons
     }
 #undef VLCT_AD_FACES
 #undef VLCT_AD_RECON
-    k_ad_prims<<<gc, kBlock, 0, s>>>(g, st, P, F, S, lacc);
+    if (recon == VLCT_RECON_PCM)
+        k_ad_prims<true><<<gc, kBlock, 0, s>>>(g, st, P, S, lacc);
+    else
+        k_ad_prims<false><<<gc, kBlock, 0, s>>>(g, st, P, S, lacc);
 }
 
-// workspace of the adjoint: forward intermediates and cotangents
+// workspace of the adjoint: forward intermediates and cotangents.  Without a
+// tape it also holds the recomputed fluxes, half-step state and upwind sides.
 struct AdLayout {
-    size_t prims[2], half[8], flux[2][3], lnext[8], lhalf[8], le, lw, lrec, total;
+    size_t prims[2], half[8], flux[2][3], side[2][3], le, wcode, lw, lrec, total;
     size_t prims_len, flux_len[3], cell_pitch, lhalf_span, lw_span;
+    size_t lnext[8], lhalf[8];
 };
 
-static AdLayout ad_layout(const Geom &g)
+static AdLayout ad_layout(const Geom &g, bool taped)
 {
     AdLayout L;
     size_t off = 0;
@@ -467,17 +485,24 @@ static AdLayout ad_layout(const Geom &g)
         L.prims[h] = off;
         off += 8 * align_up(L.prims_len * 8);
     }
-    for (int f = 0; f < 8; ++f) {
-        L.half[f] = off;
-        off += align_up(field_len(g.n, f) * 8);
-    }
     for (int d = 0; d < 3; ++d)
         L.flux_len[d] = (size_t)flux_dim(g.n, d, 0) * flux_dim(g.n, d, 1) * flux_dim(g.n, d, 2);
-    for (int h = 0; h < 2; ++h)
-        for (int d = 0; d < 3; ++d) {
-            L.flux[h][d] = off;
-            off += 8 * align_up(L.flux_len[d] * 8);
+    if (!taped) {
+        for (int f = 0; f < 8; ++f) {
+            L.half[f] = off;
+            off += align_up(field_len(g.n, f) * 8);
         }
+        for (int h = 0; h < 2; ++h)
+            for (int d = 0; d < 3; ++d) {
+                L.flux[h][d] = off;
+                off += 8 * align_up(L.flux_len[d] * 8);
+            }
+        for (int h = 0; h < 2; ++h)
+            for (int d = 0; d < 3; ++d) {
+                L.side[h][d] = off;
+                off += align_up(N);
+            }
+    }
     for (int f = 0; f < 8; ++f) {
         L.lnext[f] = off;
         off += align_up(field_len(g.n, f) * 8);
@@ -490,6 +515,8 @@ static AdLayout ad_layout(const Geom &g)
     L.lhalf_span = (off - lhalf0) / 8;
     L.le = off;
     off += 3 * L.cell_pitch;
+    L.wcode = off;
+    off += align_up(N * sizeof(uint32_t));
     L.lw = off;
     off += 8 * L.cell_pitch;
     L.lw_span = L.cell_pitch;  // 8 arrays of cell_pitch bytes = cell_pitch doubles
@@ -497,6 +524,82 @@ static AdLayout ad_layout(const Geom &g)
     off += 42 * L.cell_pitch;
     L.total = off;
     return L;
+}
+
+// argument checks shared by both adjoint entry points
+static int adjoint_args(const vlct_grid *vg, const vlct_state *in, const vlct_state *lam_out,
+                        const vlct_state *lam_in, const double *dt_dev)
+{
+    if (!grid_ok(vg) || !state_ok(in) || !state_ok(lam_out) || !state_ok(lam_in) || !dt_dev)
+        return VLCT_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        if (vg->bc[d] != VLCT_BC_PERIODIC) return VLCT_EUNSUPPORTED;
+    if (vg->recon != VLCT_RECON_PCM && vg->recon != VLCT_RECON_PLMC && vg->recon != VLCT_RECON_PLMP)
+        return VLCT_EUNSUPPORTED;
+    // no array of lam_in may overlap an array of `in` or `lam_out`, nor another of lam_in
+    const int n[3] = {vg->nx, vg->ny, vg->nz};
+    const vlct_state *sts[3] = {lam_in, in, lam_out};
+    uintptr_t lo[3][8], hi[3][8];
+    for (int q = 0; q < 3; ++q) {
+        const double *p[8] = {sts[q]->rho, sts[q]->mx, sts[q]->my, sts[q]->mz, sts[q]->E,
+                              sts[q]->bx, sts[q]->by, sts[q]->bz};
+        for (int f = 0; f < 8; ++f) {
+            lo[q][f] = reinterpret_cast<uintptr_t>(p[f]);
+            hi[q][f] = lo[q][f] + field_len(n, f) * sizeof(double);
+        }
+    }
+    for (int f = 0; f < 8; ++f)
+        for (int q = 0; q < 3; ++q)
+            for (int h = 0; h < 8; ++h) {
+                if (q == 0 && h == f) continue;
+                if (lo[0][f] < hi[q][h] && lo[q][h] < hi[0][f]) return VLCT_EINVAL;
+            }
+    return VLCT_OK;
+}
+
+// the adjoint of one step given the half-step state and both stages' upwind
+// sides (from a tape, or recomputed into the workspace by the caller, who
+// then has also computed both stages' primitives: have_prims)
+static int adjoint_core(const vlct_grid *vg, const Geom &g, const AdLayout &L, char *b,
+                        const StateP &sin, const StateP &hc, const Sides sides[2],
+                        bool have_prims, const vlct_state *lam_out, const vlct_state *lam_in,
+                        const double *dt_dev, hipStream_t s)
+{
+    auto arr = [&](size_t off) { return reinterpret_cast<double *>(b + off); };
+    Prims P[2];
+    for (int h = 0; h < 2; ++h)
+        for (int f = 0; f < 8; ++f) P[h].w[f] = arr(L.prims[h] + f * align_up(L.prims_len * 8));
+    StateW lnext, lhalf;
+    for (int f = 0; f < 8; ++f) {
+        double *c = arr(L.lnext[f]), *e = arr(L.lhalf[f]);
+        if (f < 5) { lnext.u[f] = c; lhalf.u[f] = e; }
+        else { lnext.b[f - 5] = c; lhalf.b[f - 5] = e; }
+    }
+    AdStage S;
+    for (int a = 0; a < 3; ++a) S.le[a] = arr(L.le + a * L.cell_pitch);
+    S.wcode = reinterpret_cast<uint32_t *>(b + L.wcode);
+    for (int f = 0; f < 8; ++f) S.lw[f] = arr(L.lw + f * L.cell_pitch);
+    for (int d = 0; d < 3; ++d)
+        for (int c = 0; c < 14; ++c) S.lrec[d][c] = arr(L.lrec + (14 * d + c) * L.cell_pitch);
+
+    // primitives of both stages' input states (same kernel as the step)
+    if (!have_prims) {
+        int rc = launch_prims(g, sin, P[0], nullptr, s);
+        if (!rc) rc = launch_prims(g, hc, P[1], nullptr, s);
+        if (rc) return rc;
+    }
+
+    // reverse: corrector stage into mu = lhalf, then lam_in += mu + predictor^T mu
+    const StateW lin = as_mut(lam_in);
+    const unsigned gf = nblocks((size_t)(g.n[0] + 1) * (g.n[1] + 1) * (g.n[2] + 1));
+    k_ad_init<<<gf, kBlock, 0, s>>>(g, as_const(lam_out), lnext, lin);
+    fill(lhalf.u[0], L.lhalf_span, s);
+    stage_adjoint(g, 1.0, as_const(lnext), hc, P[1], sides[1], vg->recon, S, L.lw_span, lhalf,
+                  dt_dev, s);
+    k_ad_add<<<gf, kBlock, 0, s>>>(g, lin, as_const(lhalf));
+    stage_adjoint(g, 0.5, as_const(lhalf), sin, P[0], sides[0], VLCT_RECON_PCM, S, L.lw_span, lin,
+                  dt_dev, s);
+    return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
 }
 
 // ---------------------------------------------------------------------------
@@ -595,41 +698,23 @@ int vlct_curl_potential_adjoint(const vlct_grid *vg, const double *lbx, const do
 size_t vlct_adjoint_workspace_bytes(const vlct_grid *g)
 {
     if (!grid_ok(g)) return 0;
-    return ad_layout(make_geom(g)).total;
+    return ad_layout(make_geom(g), false).total;
+}
+
+size_t vlct_adjoint_taped_workspace_bytes(const vlct_grid *g)
+{
+    if (!grid_ok(g)) return 0;
+    return ad_layout(make_geom(g), true).total;
 }
 
 int vlct_step_adjoint(const vlct_grid *vg, const vlct_state *in, const vlct_state *lam_out,
                       const vlct_state *lam_in, const double *dt_dev, void *ws, size_t ws_bytes,
                       void *stream)
 {
-    if (!grid_ok(vg) || !state_ok(in) || !state_ok(lam_out) || !state_ok(lam_in) || !dt_dev)
-        return VLCT_EINVAL;
-    for (int d = 0; d < 3; ++d)
-        if (vg->bc[d] != VLCT_BC_PERIODIC) return VLCT_EUNSUPPORTED;
-    if (vg->recon != VLCT_RECON_PCM && vg->recon != VLCT_RECON_PLMC && vg->recon != VLCT_RECON_PLMP)
-        return VLCT_EUNSUPPORTED;
-    {
-        // no array of lam_in may overlap an array of `in` or `lam_out`, nor another of lam_in
-        const int n[3] = {vg->nx, vg->ny, vg->nz};
-        const vlct_state *sts[3] = {lam_in, in, lam_out};
-        uintptr_t lo[3][8], hi[3][8];
-        for (int q = 0; q < 3; ++q) {
-            const double *p[8] = {sts[q]->rho, sts[q]->mx, sts[q]->my, sts[q]->mz, sts[q]->E,
-                                  sts[q]->bx, sts[q]->by, sts[q]->bz};
-            for (int f = 0; f < 8; ++f) {
-                lo[q][f] = reinterpret_cast<uintptr_t>(p[f]);
-                hi[q][f] = lo[q][f] + field_len(n, f) * sizeof(double);
-            }
-        }
-        for (int f = 0; f < 8; ++f)
-            for (int q = 0; q < 3; ++q)
-                for (int h = 0; h < 8; ++h) {
-                    if (q == 0 && h == f) continue;
-                    if (lo[0][f] < hi[q][h] && lo[q][h] < hi[0][f]) return VLCT_EINVAL;
-                }
-    }
+    int rc = adjoint_args(vg, in, lam_out, lam_in, dt_dev);
+    if (rc) return rc;
     const Geom g = make_geom(vg);
-    const AdLayout L = ad_layout(g);
+    const AdLayout L = ad_layout(g, false);
     if (!ws || ws_bytes < L.total) return VLCT_EWORKSPACE;
     char *b = static_cast<char *>(ws);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -637,44 +722,56 @@ int vlct_step_adjoint(const vlct_grid *vg, const vlct_state *in, const vlct_stat
     Prims P[2];
     for (int h = 0; h < 2; ++h)
         for (int f = 0; f < 8; ++f) P[h].w[f] = arr(L.prims[h] + f * align_up(L.prims_len * 8));
-    StateW half, lnext, lhalf;
+    StateW half;
     for (int f = 0; f < 8; ++f) {
-        double *a = arr(L.half[f]), *c = arr(L.lnext[f]), *e = arr(L.lhalf[f]);
-        if (f < 5) { half.u[f] = a; lnext.u[f] = c; lhalf.u[f] = e; }
-        else { half.b[f - 5] = a; lnext.b[f - 5] = c; lhalf.b[f - 5] = e; }
+        if (f < 5) half.u[f] = arr(L.half[f]); else half.b[f - 5] = arr(L.half[f]);
     }
     Flux F[2];
-    for (int h = 0; h < 2; ++h)
-        for (int d = 0; d < 3; ++d)
+    uint8_t *side[2][3];
+    Sides sides[2];
+    for (int h = 0; h < 2; ++h) {
+        for (int d = 0; d < 3; ++d) {
             for (int c = 0; c < 8; ++c)
                 F[h].f[d][c] = arr(L.flux[h][d] + c * align_up(L.flux_len[d] * 8));
-    AdStage S;
-    for (int a = 0; a < 3; ++a) S.le[a] = arr(L.le + a * L.cell_pitch);
-    for (int f = 0; f < 8; ++f) S.lw[f] = arr(L.lw + f * L.cell_pitch);
-    for (int d = 0; d < 3; ++d)
-        for (int c = 0; c < 14; ++c) S.lrec[d][c] = arr(L.lrec + (14 * d + c) * L.cell_pitch);
-
-    // forward intermediates at U^n (same kernels as vlct_step)
+            side[h][d] = reinterpret_cast<uint8_t *>(b + L.side[h][d]);
+            sides[h].s[d] = side[h][d];
+        }
+    }
+    // forward intermediates at U^n (the kernels of vlct_step)
     const StateP sin = as_const(in);
-    int rc = launch_prims(g, sin, P[0], nullptr, s);
+    rc = launch_prims(g, sin, P[0], nullptr, s);
     if (!rc) rc = launch_fluxes(g, sin, P[0], F[0], VLCT_RECON_PCM, nullptr, s);
+    if (!rc) rc = launch_pack_sides(g, F[0], side[0], s);
     if (!rc) rc = launch_ct(g, false, P[0], F[0], sin, half, dt_dev, nullptr, s);
     const StateP hc = as_const(half);
     if (!rc) rc = launch_prims(g, hc, P[1], nullptr, s);
     if (!rc) rc = launch_fluxes(g, hc, P[1], F[1], vg->recon, nullptr, s);
+    if (!rc) rc = launch_pack_sides(g, F[1], side[1], s);
     if (rc) return rc;
+    return adjoint_core(vg, g, L, b, sin, hc, sides, true, lam_out, lam_in, dt_dev, s);
+}
 
-    // reverse: corrector stage into mu = lhalf, then lam_in += mu + predictor^T mu
-    const StateW lin = as_mut(lam_in);
-    const unsigned gf = nblocks((size_t)(g.n[0] + 1) * (g.n[1] + 1) * (g.n[2] + 1));
-    k_ad_init<<<gf, kBlock, 0, s>>>(g, as_const(lam_out), lnext, lin);
-    fill(lhalf.u[0], L.lhalf_span, s);
-    stage_adjoint(g, 1.0, as_const(lnext), hc, P[1], F[1], vg->recon, S, L.lw_span, lhalf,
-                  dt_dev, s);
-    k_ad_add<<<gf, kBlock, 0, s>>>(g, lin, as_const(lhalf));
-    stage_adjoint(g, 0.5, as_const(lhalf), sin, P[0], F[0], VLCT_RECON_PCM, S, L.lw_span, lin,
-                  dt_dev, s);
-    return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
+int vlct_step_adjoint_taped(const vlct_grid *vg, const vlct_state *in, const vlct_state *lam_out,
+                            const vlct_state *lam_in, const double *dt_dev, const void *tape,
+                            size_t tape_bytes, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = adjoint_args(vg, in, lam_out, lam_in, dt_dev);
+    if (rc) return rc;
+    const Geom g = make_geom(vg);
+    const AdLayout L = ad_layout(g, true);
+    const TapeLayout T = tape_layout(g.n);
+    if (!ws || ws_bytes < L.total || !tape || tape_bytes < T.total) return VLCT_EWORKSPACE;
+    const char *tb = static_cast<const char *>(tape);
+    StateP hc;
+    for (int f = 0; f < 8; ++f) {
+        const double *a = reinterpret_cast<const double *>(tb + T.half[f]);
+        if (f < 5) hc.u[f] = a; else hc.b[f - 5] = a;
+    }
+    Sides sides[2];
+    for (int h = 0; h < 2; ++h)
+        for (int d = 0; d < 3; ++d) sides[h].s[d] = reinterpret_cast<const uint8_t *>(tb + T.side[h][d]);
+    return adjoint_core(vg, g, L, static_cast<char *>(ws), as_const(in), hc, sides, false,
+                        lam_out, lam_in, dt_dev, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -189,6 +189,38 @@ inline unsigned nblocks(size_t work) { return (unsigned)((work + kBlock - 1) / k
 // grid size (multiple of the XCD count) for a kernel that remaps with xcd_block
 inline unsigned xcd_grid(size_t logical_blocks) { return (unsigned)(kXcd * xcd_per(logical_blocks)); }
 
+// upwind side of a face from its CT indicator (the sign of S_M, Eq. emf-upwind):
+// 0 for S_M > 0, 1 for S_M < 0, 2 for neither
+__device__ __forceinline__ uint8_t side_code(double s)
+{
+    return s > 0.0 ? (uint8_t)0 : (s < 0.0 ? (uint8_t)1 : (uint8_t)2);
+}
+
+// tape of one step (vlct_step_taped): the half-step state and the upwind side
+// of every interior face of both stages (one byte, at the index of the cell
+// whose low face it is)
+struct TapeLayout {
+    size_t half[8], side[2][3], total;
+};
+
+inline TapeLayout tape_layout(const int n[3])
+{
+    TapeLayout T;
+    size_t off = 0;
+    for (int f = 0; f < 8; ++f) {
+        T.half[f] = off;
+        off += align_up(field_len(n, f) * sizeof(double));
+    }
+    const size_t N = (size_t)n[0] * n[1] * n[2];
+    for (int h = 0; h < 2; ++h)
+        for (int d = 0; d < 3; ++d) {
+            T.side[h][d] = off;
+            off += align_up(N);
+        }
+    T.total = off;
+    return T;
+}
+
 // launches of the step kernels (vlct.hip), also used by the adjoint to
 // recompute the forward intermediates
 int launch_prims(const Geom &g, const StateP &st, const Prims &P, uint32_t *status,
@@ -197,5 +229,7 @@ int launch_fluxes(const Geom &g, const StateP &st, const Prims &P, const Flux &F
                   uint32_t *status, hipStream_t s);
 int launch_ct(const Geom &g, bool full, const Prims &P, const Flux &F, const StateP &base,
               const StateW &out, const double *dt_dev, uint32_t *status, hipStream_t s);
+// upwind sides of the interior faces of F, per axis
+int launch_pack_sides(const Geom &g, const Flux &F, uint8_t *const side[3], hipStream_t s);
 
 }  // namespace vlct

@@ -31,7 +31,9 @@ VLCT_STATUS_NONFINITE = 4
 EXPORTED = ("vlct_workspace_bytes", "vlct_cfl_dt", "vlct_step", "vlct_strerror",
             "vlct_abi_version", "vlct_set_launch_observer", "vlct_kernel_name",
             "vlct_batch_workspace_bytes", "vlct_step_batch", "vlct_adjoint_workspace_bytes",
-            "vlct_step_adjoint", "vlct_curl_potential", "vlct_curl_potential_adjoint")
+            "vlct_step_adjoint", "vlct_curl_potential", "vlct_curl_potential_adjoint",
+            "vlct_tape_bytes", "vlct_step_taped", "vlct_adjoint_taped_workspace_bytes",
+            "vlct_step_adjoint_taped")
 
 VLCT_KERNEL_PRIMS = 0
 VLCT_KERNEL_FLUX_PCM = 1
@@ -99,6 +101,19 @@ def load(path: str = LIB_PATH):
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                           ctypes.c_void_p]
         lib.vlct_step_adjoint.restype = ctypes.c_int
+        for name in ("vlct_tape_bytes", "vlct_adjoint_taped_workspace_bytes"):
+            fn = getattr(lib, name)
+            fn.argtypes = [ctypes.POINTER(vlct_grid)]
+            fn.restype = ctypes.c_size_t
+        lib.vlct_step_taped.argtypes = [ctypes.POINTER(vlct_grid), ctypes.POINTER(vlct_state),
+                                        ctypes.POINTER(vlct_state), ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        lib.vlct_step_taped.restype = ctypes.c_int
+        lib.vlct_step_adjoint_taped.argtypes = [ctypes.POINTER(vlct_grid)] + \
+            [ctypes.POINTER(vlct_state)] * 3 + [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                                ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        lib.vlct_step_adjoint_taped.restype = ctypes.c_int
         for name in ("vlct_curl_potential", "vlct_curl_potential_adjoint"):
             fn = getattr(lib, name)
             fn.argtypes = [ctypes.POINTER(vlct_grid)] + [ctypes.c_void_p] * 7
@@ -179,6 +194,30 @@ def vlct_step_adjoint(grid: vlct_grid, state_in: vlct_state, lam_out: vlct_state
     return int(load().vlct_step_adjoint(ctypes.byref(grid), ctypes.byref(state_in),
                                         ctypes.byref(lam_out), ctypes.byref(lam_in), dt_dev, ws,
                                         ws_bytes, stream))
+
+
+def vlct_tape_bytes(grid: vlct_grid) -> int:
+    return int(load().vlct_tape_bytes(ctypes.byref(grid)))
+
+
+def vlct_adjoint_taped_workspace_bytes(grid: vlct_grid) -> int:
+    return int(load().vlct_adjoint_taped_workspace_bytes(ctypes.byref(grid)))
+
+
+def vlct_step_taped(grid: vlct_grid, state_in: vlct_state, state_out: vlct_state, dt_dev: int,
+                    next_dt_dev: int, status_dev: int, ws: int, ws_bytes: int, tape: int,
+                    tape_bytes: int, stream: int) -> int:
+    return int(load().vlct_step_taped(ctypes.byref(grid), ctypes.byref(state_in),
+                                      ctypes.byref(state_out), dt_dev, next_dt_dev, status_dev,
+                                      ws, ws_bytes, tape, tape_bytes, stream))
+
+
+def vlct_step_adjoint_taped(grid: vlct_grid, state_in: vlct_state, lam_out: vlct_state,
+                            lam_in: vlct_state, dt_dev: int, tape: int, tape_bytes: int, ws: int,
+                            ws_bytes: int, stream: int) -> int:
+    return int(load().vlct_step_adjoint_taped(ctypes.byref(grid), ctypes.byref(state_in),
+                                              ctypes.byref(lam_out), ctypes.byref(lam_in), dt_dev,
+                                              tape, tape_bytes, ws, ws_bytes, stream))
 
 
 def vlct_curl_potential(grid: vlct_grid, ax: int, ay: int, az: int, bx: int, by: int, bz: int,

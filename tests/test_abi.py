@@ -139,6 +139,32 @@ def test_adjoint_validation():
     assert vlct.vlct_step_adjoint(g, a, b, c, 64, ws, need - 1, 0) == vlct.VLCT_EWORKSPACE
 
 
+def test_taped_validation():
+    """vlct_step_taped / vlct_step_adjoint_taped reject bad calls on the host."""
+    _lib()
+    g = _grid()
+    tb = vlct.vlct_tape_bytes(g)
+    assert tb > 0 and vlct.vlct_tape_bytes(_grid(nx=0)) == 0
+    wt = vlct.vlct_adjoint_taped_workspace_bytes(g)
+    assert 0 < wt < vlct.vlct_adjoint_workspace_bytes(g)
+    ws_step = vlct.vlct_workspace_bytes(g)
+
+    def st(base):
+        return vlct.make_state([base + 8192 * f for f in range(8)])
+    a, b, c = st(1 << 20), st(2 << 20), st(3 << 20)
+    big = 1 << 30
+    assert vlct.vlct_step_taped(g, a, b, 64, 0, 0, big, ws_step, big, tb - 1, 0) == vlct.VLCT_EWORKSPACE
+    assert vlct.vlct_step_taped(g, a, b, 64, 0, 0, big, ws_step, 0, tb, 0) == vlct.VLCT_EWORKSPACE
+    assert vlct.vlct_step_taped(g, a, b, 0, 0, 0, big, ws_step, big, tb, 0) == vlct.VLCT_EINVAL
+    assert vlct.vlct_step_adjoint_taped(g, a, b, c, 64, big, tb - 1, big, wt,
+                                        0) == vlct.VLCT_EWORKSPACE
+    assert vlct.vlct_step_adjoint_taped(g, a, b, c, 64, big, tb, big, wt - 1,
+                                        0) == vlct.VLCT_EWORKSPACE
+    assert vlct.vlct_step_adjoint_taped(_grid(bc=(1, 0, 0)), a, b, c, 64, big, tb, big, wt,
+                                        0) == vlct.VLCT_EUNSUPPORTED
+    assert vlct.vlct_step_adjoint_taped(g, a, b, a, 64, big, tb, big, wt, 0) == vlct.VLCT_EINVAL
+
+
 def test_strerror_covers_codes():
     _lib()
     for c in range(5):

@@ -153,6 +153,59 @@ def test_checkpointed_rollout_gradient_independent_of_segment():
             assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max(), name
 
 
+def test_taped_step_and_adjoint_equal_untaped():
+    """vlct_step_taped writes exactly what vlct_step writes (state and next
+    dt); the adjoint from its tape equals the self-contained adjoint up to the
+    summation order of accumulations; PCM, PLMC and PLMP."""
+    _need_gpu()
+    import torch
+    from paper_2402_05240_amd import autograd as AG
+    for recon in (I.RECON_PCM, I.RECON_PLMC, I.RECON_PLMP):
+        g = _grid((12, 10, 9), recon)
+        rho, v, p, A = _params(g, 9)
+        s = _state_from(g, rho, v, p, A)
+        sim = AG.Simulator(g)
+        fields = [torch.from_numpy(s[f]).cuda() for f in FIELDS]
+        dt = sim.cfl_dt(fields)
+        n1 = torch.zeros(1, dtype=torch.float64, device="cuda")
+        n2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+        tape = sim.new_tape()
+        a = sim.step(fields, dt, n1)
+        b = sim.step_taped(fields, dt, tape, n2)
+        torch.cuda.synchronize()
+        for x, y, name in zip(a, b, FIELDS):
+            assert torch.equal(x, y), (recon, name)
+        assert torch.equal(n1, n2)
+        rng = np.random.default_rng(10)
+        lam = [torch.from_numpy(rng.standard_normal(g.field_shape(f))).cuda() for f in FIELDS]
+        la = sim.adjoint(fields, lam, dt)
+        lb = sim.adjoint_taped(fields, lam, dt, tape)
+        torch.cuda.synchronize()
+        for x, y, name in zip(la, lb, FIELDS):
+            assert float((x - y).abs().max()) <= 1e-13 * float(x.abs().max()), (recon, name)
+
+
+def test_rollout_taped_and_untaped_gradients_agree():
+    _need_gpu()
+    import torch
+    from paper_2402_05240_amd import autograd as AG
+    g = _grid((9, 11, 10))
+    rho, v, p, A = _params(g, 11)
+    s = _state_from(g, rho, v, p, A)
+    sim = AG.Simulator(g)
+    rng = np.random.default_rng(12)
+    lam = [torch.from_numpy(rng.standard_normal(g.field_shape(f))).cuda() for f in FIELDS]
+    grads = []
+    for taped in (True, False):
+        fields = [torch.from_numpy(s[f]).cuda().requires_grad_(True) for f in FIELDS]
+        out, _ = AG.rollout(sim, fields, nsteps=7, taped=taped)
+        torch.autograd.backward(out, lam)
+        torch.cuda.synchronize()
+        grads.append([f.grad.cpu().numpy() for f in fields])
+    for a, b, name in zip(grads[0], grads[1], FIELDS):
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max(), name
+
+
 def _oracle_loss(g, rho, m, E, A, b0, dts, target):
     bx, by, bz = I.curl_edge_potential(g, *A)
     s = {"rho": rho, "mx": m[0], "my": m[1], "mz": m[2], "E": E,
