@@ -41,8 +41,8 @@ BYTES_PER_UNIT = {"prims": 16 * F64, "ct_update": 46 * F64, "dt": 8 * F64}
 # a fully fused step would move the state in and out once
 STEP_MIN_BYTES_PER_CELL = 16 * F64
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "hbm_counters_turbulence_plmc_256.json")
-SOURCES = ("paper_2402_05240_amd/csrc/vlct.hip", "paper_2402_05240_amd/csrc/mhd_physics.hpp",
-           "include/vlct.h")
+SOURCES = ("paper_2402_05240_amd/csrc/vlct.hip", "paper_2402_05240_amd/csrc/vlct_common.hpp",
+           "paper_2402_05240_amd/csrc/mhd_physics.hpp")
 
 
 def source_hash():
@@ -238,6 +238,16 @@ def rooflines(g, kern, steps, workload=None):
 
 def kernel_family(name):
     """Kernel family of a device kernel name as rocprofv3 prints it."""
+    if "k_ad_" in name or "k_curl" in name or "k_pack_sides" in name:
+        for key, fam in (("k_ad_faces", "adj_faces"), ("k_ad_recon", "adj_recon"),
+                         ("k_ad_prims", "adj_prims"), ("k_ad_edges", "adj_edges"),
+                         ("k_pack_sides", "tape_sides"), ("k_curl", "curl")):
+            if key in name:
+                if fam == "adj_faces":
+                    targs = name[name.index("<") + 1:name.index(">")].replace(" ", "").split(",")
+                    return "adj_faces_pcm" if targs[-1] == "1" else "adj_faces_recon"
+                return fam
+        return "adj_other"
     if "k_prims" in name:
         return "prims"
     if "k_ct_update" in name:
@@ -307,7 +317,8 @@ def summarize_counters(fetch_csv, write_csv, copy_bytes, workload, commands, out
 
 
 def summarize_trace(stats_csv, workload, command, out_dir):
-    """rocprofv3 --kernel-trace --stats kernel table -> markdown summary."""
+    """rocprofv3 --kernel-trace --stats kernel table -> markdown summary
+    (profiles/kernel_trace_<workload>.md)."""
     import csv
     rows = list(csv.DictReader(open(stats_csv)))
     lines = ["# Kernel durations, %s" % workload, "", "    " + command, "",
@@ -529,6 +540,8 @@ def main():
                          "rocprofv3 --pmc runs (no GPU needed)")
     ap.add_argument("--summarize-trace", metavar="KERNEL_STATS_CSV",
                     help="write profiles/kernel_trace_<workload>.md (no GPU needed)")
+    ap.add_argument("--trace-name", default=None,
+                    help="name of the --summarize-trace output (default: the workload)")
     ap.add_argument("--commands", nargs="*", default=[],
                     help="the rocprofv3 command lines the summarised files came from")
     args = ap.parse_args()
@@ -540,7 +553,7 @@ def main():
                                int(args.copy_calibration_gib * (1 << 30)) or (1 << 30),
                                args.workload, args.commands[:2], out_dir)
         if args.summarize_trace:
-            summarize_trace(args.summarize_trace, args.workload,
+            summarize_trace(args.summarize_trace, args.trace_name or args.workload,
                             args.commands[-1] if args.commands else "", out_dir)
         return
     if args.gpus != 1:
