@@ -447,15 +447,20 @@ def adjoint_bench(n, steps, warmup):
         adj.run()
         ftaped()
         ataped()
-    ms_f = timed(fstep, steps)
-    ms_a = timed(adj.run, steps)
-    ms_ft = timed(ftaped, steps)
-    ftaped()
-    ms_at = timed(ataped, steps)
+    # interleaved rounds, the minimum of each
+    rounds = {"forward": [], "adjoint": [], "taped_forward": [], "taped_adjoint": []}
+    for _ in range(3):
+        rounds["forward"].append(timed(fstep, steps))
+        rounds["adjoint"].append(timed(adj.run, steps))
+        rounds["taped_forward"].append(timed(ftaped, steps))
+        rounds["taped_adjoint"].append(timed(ataped, steps))
+    ms_f, ms_a = min(rounds["forward"]), min(rounds["adjoint"])
+    ms_ft, ms_at = min(rounds["taped_forward"]), min(rounds["taped_adjoint"])
     return {"workload": "turbulence_plmc_%d" % n, "grid": [n, n, n], "recon": "PLMC",
             "steps": steps, "forward_ms": ms_f, "adjoint_ms": ms_a, "ratio": ms_a / ms_f,
             "taped_forward_ms": ms_ft, "taped_adjoint_ms": ms_at,
             "ratio_taped": ms_at / ms_f, "tape_bytes": sim.tape_bytes,
+            "rounds_ms": rounds,
             "workspace_bytes": adj.ws_bytes,
             "note": "ratio: self-contained adjoint (recomputes the step's fluxes) / forward "
                     "step; ratio_taped: adjoint from the tape of a taped forward step "
