@@ -1,6 +1,7 @@
 // flop_count.cpp -- counts the FP64 arithmetic of the device physics per call
-// (PLMC reconstruction, PPMC reconstruction, HLLD solve) by compiling the same
-// source on the host with a counting scalar.  Convention: one FLOP per add,
+// (PLMC reconstruction, PPMC reconstruction, HLLD solve, and their reverse
+// derivatives used by the adjoint) by compiling the same source on the host
+// with a counting scalar.  Convention: one FLOP per add,
 // subtract, multiply, divide or square root; comparisons, min, max, abs and
 // copysign count zero.  Branch-dependent paths are averaged over random
 // turbulence-like states (rho ~ 1, |v| ~ 1, P ~ 0.6, B ~ (1.1, 0, 0) + 0.2 noise).
@@ -37,15 +38,17 @@ inline Counted fmax(Counted a, Counted b) { return Counted(std::fmax(a.v, b.v));
 inline Counted fmin(Counted a, double b) { return Counted(std::fmin(a.v, b)); }
 inline Counted fmax(Counted a, double b) { return Counted(std::fmax(a.v, b)); }
 inline Counted copysign(Counted a, Counted b) { return Counted(std::copysign(a.v, b.v)); }
+inline Counted copysign(double a, Counted b) { return Counted(std::copysign(a, b.v)); }
 
 #define VLCT_HOST_COUNT
 #define double Counted
 #include "mhd_physics.hpp"
+#include "mhd_adjoint.hpp"
 #undef double
 
 int main()
 {
-    std::mt19937_64 rng(2402);
+    std::mt19937_64 rng(2402), rng_cot(5240);
     std::normal_distribution<double> nrm(0.0, 1.0);
     std::uniform_real_distribution<double> uni(0.8, 1.2);
     const double gam = 5.0 / 3.0, gm1i = 1.0 / (gam - 1.0);
@@ -55,6 +58,7 @@ int main()
     };
     const int N = 20000;
     long long plmc_f = 0, ppmc_f = 0, plmp_f = 0, ppmp_f = 0, hlld_f = 0;
+    long long hlld_r = 0, plmc_r = 0, plmp_r = 0;
     for (int q = 0; q < N; ++q) {
         vlct::W7 a = state(), b = state(), c = state(), d = state(), e = state();
         // smooth-ish stencils: neighbours close to the centre
@@ -83,6 +87,24 @@ int main()
         f0 = g_flops;
         vlct::hlld(m1, c, Counted(bn), Counted(gam), Counted(gm1i), f, upw);
         hlld_f += g_flops - f0;
+        // reverse derivatives (the adjoint's per-face and per-cell maps)
+        Counted af[7], afm[7], afp[7];
+        for (int k = 0; k < 7; ++k) {
+            af[k] = Counted(nrm(rng_cot));
+            afm[k] = Counted(nrm(rng_cot));
+            afp[k] = Counted(nrm(rng_cot));
+        }
+        vlct::W7 aL{0, 0, 0, 0, 0, 0, 0}, aR{0, 0, 0, 0, 0, 0, 0}, a3{0, 0, 0, 0, 0, 0, 0};
+        Counted abn(0.0);
+        f0 = g_flops;
+        vlct::hlld_rev(m1, c, Counted(bn), Counted(gam), Counted(gm1i), af, aL, aR, abn);
+        hlld_r += g_flops - f0;
+        f0 = g_flops;
+        vlct::plmc_rev<true>(m1, c, p1, Counted(bn), Counted(gam), afm, afp, aL, aR, a3, abn);
+        plmc_r += g_flops - f0;
+        f0 = g_flops;
+        vlct::plmc_rev<false>(m1, c, p1, Counted(bn), Counted(gam), afm, afp, aL, aR, a3, abn);
+        plmp_r += g_flops - f0;
     }
     std::printf("plmc_per_call %.1f\nppmc_per_call %.1f\nhlld_per_call %.1f\n",
                 double(plmc_f) / N, double(ppmc_f) / N, double(hlld_f) / N);
@@ -94,5 +116,12 @@ int main()
                 double(plmc_f + hlld_f) / N, double(ppmc_f + hlld_f) / N);
     std::printf("plmp_hlld_per_face %.1f\nppmp_hlld_per_face %.1f\n",
                 double(plmp_f + hlld_f) / N, double(ppmp_f + hlld_f) / N);
+    // adjoint: a corrector face recomputes both interface states and reverses
+    // HLLD; every cell reverses its reconstruction; a predictor face reverses
+    // HLLD on the cell states
+    std::printf("hlld_rev_per_call %.1f\nplmc_rev_per_call %.1f\nplmp_rev_per_call %.1f\n",
+                double(hlld_r) / N, double(plmc_r) / N, double(plmp_r) / N);
+    std::printf("adj_faces_plmc_per_face %.1f\nadj_faces_pcm_per_face %.1f\n",
+                double(2 * plmc_f + hlld_r) / N, double(hlld_r) / N);
     return 0;
 }
