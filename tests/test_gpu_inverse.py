@@ -13,6 +13,13 @@ from parity_util import FIELDS, gpu_available
 
 pytestmark = pytest.mark.gpu
 
+# The adjoint accumulates with FP64 atomics, whose summation order varies from
+# run to run: two evaluations of the same gradient differ in the last bits of
+# each accumulation, and a rollout compounds that over its steps (~1e-12 of the
+# largest element after 7-9 steps).  Any error in the method moves gradients
+# by many orders of magnitude more.
+ROLLOUT_ORDER_TOL = 1e-10
+
 
 def _need_gpu():
     if not gpu_available():
@@ -150,7 +157,7 @@ def test_checkpointed_rollout_gradient_independent_of_segment():
         for a, b in zip(outs[0], outs[k]):
             assert np.array_equal(a, b)
         for a, b, name in zip(grads[0], grads[k], FIELDS):
-            assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max(), name
+            assert np.abs(a - b).max() <= ROLLOUT_ORDER_TOL * np.abs(a).max(), name
 
 
 def test_taped_step_and_adjoint_equal_untaped():
@@ -182,7 +189,7 @@ def test_taped_step_and_adjoint_equal_untaped():
         lb = sim.adjoint_taped(fields, lam, dt, tape)
         torch.cuda.synchronize()
         for x, y, name in zip(la, lb, FIELDS):
-            assert float((x - y).abs().max()) <= 1e-13 * float(x.abs().max()), (recon, name)
+            assert float((x - y).abs().max()) <= 1e-12 * float(x.abs().max()), (recon, name)
 
 
 def test_rollout_taped_and_untaped_gradients_agree():
@@ -203,7 +210,7 @@ def test_rollout_taped_and_untaped_gradients_agree():
         torch.cuda.synchronize()
         grads.append([f.grad.cpu().numpy() for f in fields])
     for a, b, name in zip(grads[0], grads[1], FIELDS):
-        assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max(), name
+        assert np.abs(a - b).max() <= ROLLOUT_ORDER_TOL * np.abs(a).max(), name
 
 
 def _oracle_loss(g, rho, m, E, A, b0, dts, target):
