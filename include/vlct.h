@@ -137,6 +137,31 @@ int vlct_step_batch(int count, const vlct_grid *grids, const vlct_state *in,
                     const vlct_state *out, const double *dt_dev, double *next_dt_dev,
                     uint32_t *status_dev, void *ws, size_t ws_bytes, void *stream);
 
+/* Per-instance tile plan: vlct_step_batch with plan[i] (HOST array of `count`
+ * bytes, NULL = all zero) choosing instance i's tiles: low nibble the CT
+ * column tile (0: 64 x 8, 1: 32 x 16, 2: 16 x 32), high nibble the corrector
+ * march segment along y and z (0: 32 faces, 1: 16).  Every plan gives the
+ * same results bit for bit (the tiles only regroup the same per-cell and
+ * per-face arithmetic); VLCT_EINVAL for an unknown variant. */
+int vlct_step_batch_plan(int count, const vlct_grid *grids, const vlct_state *in,
+                         const vlct_state *out, const double *dt_dev, double *next_dt_dev,
+                         uint32_t *status_dev, const uint8_t *plan, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/* Autotuner for a batch: writes into plan[count] (host) the tiles that make
+ * the batched step fastest, found by timing it on this batch: instances are
+ * grouped by nx (<= 24, <= 48, <= 96, larger) and each group's CT tile, then
+ * its march segment, is changed while the rest of the batch keeps its current
+ * choice, keeping a change that makes the whole step at least 1% faster.
+ * Each trial times `reps` (1..100) batched steps after one untimed step.  The
+ * trial steps read `in` and overwrite `out` (every instance must be out of
+ * place, else VLCT_EINVAL; next dt and status are not written).  Unlike the
+ * step calls, this call synchronises with the host (it creates and destroys
+ * two HIP events) and must not be captured into a graph. */
+int vlct_batch_tune(int count, const vlct_grid *grids, const vlct_state *in,
+                    const vlct_state *out, const double *dt_dev, void *ws, size_t ws_bytes,
+                    void *stream, int reps, uint8_t *plan);
+
 /* --- adjoint of one step --------------------------------------------------
  * Reverse derivative of the VL+CT step of Sec. 2.2 (Steps 2-9) at the state
  * `in`, for the step size *dt_dev held fixed:

@@ -28,6 +28,15 @@ constexpr int kMarch = 32;
 constexpr int kTx = 64, kTy = 8, kTz = 16;
 constexpr int kCt = kTx * kTy;  // threads of a CT block: one per column of the tile
 
+// tile variants a batched step can give each instance (its plan byte: CT
+// variant in the low nibble, march variant in the high nibble); variant 0 is
+// the single-instance kernels' shape
+constexpr int kCtVariants = 3;     // CT column tiles 64 x 8, 32 x 16, 16 x 32 (kCt threads)
+constexpr int kMarchVariants = 2;  // march segments of 32 and 16 faces
+__host__ __device__ constexpr int ct_tx(int v) { return v == 0 ? 64 : (v == 1 ? 32 : 16); }
+__host__ __device__ constexpr int ct_ty(int v) { return kCt / ct_tx(v); }
+__host__ __device__ constexpr int march_len(int v) { return v == 0 ? 32 : 16; }
+
 __host__ __device__ __forceinline__ idx_t nblk_prims(const Geom &g)
 {
     return ((idx_t)g.p[0] * g.p[1] * g.p[2] + kBlock - 1) / kBlock;
@@ -45,16 +54,16 @@ __host__ __device__ __forceinline__ idx_t nblk_row(const Geom &g)
     const idx_t items = (idx_t)(g.n[0] + 2) * (g.n[1] + 2) * (g.n[2] + 2);
     return (items - 1 + kRowFaces - 1) / kRowFaces;
 }
-__host__ __device__ __forceinline__ idx_t nblk_march(const Geom &g, int d)
+__host__ __device__ __forceinline__ idx_t nblk_march(const Geom &g, int d, int m = kMarch)
 {
     const int t = d == 1 ? 2 : 1;
     const idx_t cols = (idx_t)(g.n[0] + 2) * (g.n[t] + 2);
-    return ((cols + kBlock - 1) / kBlock) * ((g.n[d] + 1 + kMarch - 1) / kMarch);
+    return ((cols + kBlock - 1) / kBlock) * ((g.n[d] + 1 + m - 1) / m);
 }
-__host__ __device__ __forceinline__ idx_t nblk_ct(const Geom &g)
+__host__ __device__ __forceinline__ idx_t nblk_ct(const Geom &g, int tx = kTx, int ty = kTy)
 {
-    const int ntx = (g.n[0] + (g.bc[0] == VLCT_BC_OUTFLOW) + kTx - 1) / kTx;
-    const int nty = (g.n[1] + (g.bc[1] == VLCT_BC_OUTFLOW) + kTy - 1) / kTy;
+    const int ntx = (g.n[0] + (g.bc[0] == VLCT_BC_OUTFLOW) + tx - 1) / tx;
+    const int nty = (g.n[1] + (g.bc[1] == VLCT_BC_OUTFLOW) + ty - 1) / ty;
     const int ntz = (g.n[2] + kTz - 1) / kTz;
     return (idx_t)ntx * nty * ntz;
 }
@@ -242,9 +251,9 @@ __device__ __forceinline__ void recon_x_body(const Geom &g, const StateP &s, con
 
 // y and z axes: one thread per transverse column (columns flattened with x
 // fastest, so loads and stores are coalesced); each thread marches along the
-// axis through a segment of kMarch faces, keeping the stencil and the previous
+// axis through a segment of M faces, keeping the stencil and the previous
 // cell's high-face state in registers (one extra reconstruction per segment).
-template <int D, int RECON>
+template <int D, int RECON, int M = kMarch>
 __device__ __forceinline__ void march_body(const Geom &g, const StateP &s, const Prims &P,
                                            const Flux &F, uint32_t *status, idx_t b)
 {
@@ -255,14 +264,14 @@ __device__ __forceinline__ void march_body(const Geom &g, const StateP &s, const
     // columns (i, it), i in [-1, nx], it in [-1, n_T], flattened with i fastest
     const idx_t cols = (idx_t)(g.n[0] + 2) * (g.n[T] + 2);
     const idx_t ncb = (cols + kBlock - 1) / kBlock;
-    const int nseg = (nD + 1 + kMarch - 1) / kMarch;
+    const int nseg = (nD + 1 + M - 1) / M;
     const int seg = (int)(b / ncb);
     const idx_t col = (b % ncb) * kBlock + threadIdx.x;
     if (seg >= nseg || col >= cols) return;
     const int i = (int)(col % (g.n[0] + 2)) - 1;
     const int it = (int)(col / (g.n[0] + 2)) - 1;
-    const int s0 = seg * kMarch;
-    const int s1 = min(s0 + kMarch, nD + 1);  // faces [s0, s1)
+    const int s0 = seg * M;
+    const int s1 = min(s0 + M, nD + 1);  // faces [s0, s1)
     int x[3];
     x[0] = i;
     x[T] = it;
@@ -368,37 +377,37 @@ __device__ __forceinline__ double edge_emf(const Geom &g, const Flux &F, int i, 
 // k_update, without the round trip of the edge arrays through HBM.
 // ---------------------------------------------------------------------------
 
-template <bool FULL>
+template <bool FULL, int TX = kTx, int TY = kTy>
 __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flux &F,
                                         const StateP &base, const StateW &out,
                                         const double *dt_dev, uint32_t *status, idx_t b)
 {
-    __shared__ double sez[kTy + 1][kTx + 1];
-    __shared__ double sex[2][kTy + 1][kTx];
-    __shared__ double sey[2][kTy][kTx + 1];
+    __shared__ double sez[TY + 1][TX + 1];
+    __shared__ double sex[2][TY + 1][TX];
+    __shared__ double sey[2][TY][TX + 1];
     // cell-centred -(v x B) of the tile plus a one-cell halo below in x and y,
     // two planes in flight: plane kk lives in slot (kk - k0 + 1) & 1
-    __shared__ double sref[2][3][kTy + 2][kTx + 2];
+    __shared__ double sref[2][3][TY + 2][TX + 2];
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     // positions owned by threads: cells/faces i in [0, ex), j in [0, ey)
     const int ex = nx + (g.bc[0] == VLCT_BC_OUTFLOW), ey = ny + (g.bc[1] == VLCT_BC_OUTFLOW);
-    const int ntx = (ex + kTx - 1) / kTx, nty = (ey + kTy - 1) / kTy, ntz = (nz + kTz - 1) / kTz;
+    const int ntx = (ex + TX - 1) / TX, nty = (ey + TY - 1) / TY, ntz = (nz + kTz - 1) / kTz;
     if (b >= (idx_t)ntx * nty * ntz) return;
     const int bx = (int)(b % ntx), by = (int)((b / ntx) % nty), bz = (int)(b / ((idx_t)ntx * nty));
-    const int i0 = bx * kTx, j0 = by * kTy, k0 = bz * kTz, k1 = min(k0 + kTz, nz);
-    const int tx = threadIdx.x % kTx, ty = threadIdx.x / kTx;
+    const int i0 = bx * TX, j0 = by * TY, k0 = bz * kTz, k1 = min(k0 + kTz, nz);
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int i = i0 + tx, j = j0 + ty;
     const double dt = FULL ? dt_dev[0] : 0.5 * dt_dev[0];
     const double cx = dt / g.dl[0], cy = dt / g.dl[1], cz = dt / g.dl[2];
-    constexpr int NEZ = (kTy + 1) * (kTx + 1), NEX = (kTy + 1) * kTx, NEY = kTy * (kTx + 1);
+    constexpr int NEZ = (TY + 1) * (TX + 1), NEX = (TY + 1) * TX, NEY = TY * (TX + 1);
 
-    constexpr int NREF = (kTy + 2) * (kTx + 2);
+    constexpr int NREF = (TY + 2) * (TX + 2);
     auto slot = [&](int kk) { return (kk - k0 + 1) & 1; };
     // reference EMFs of plane kk (cells up to n: the highest edges are at n - 1/2)
     auto stage_ref = [&](int kk) {
         const int sl = slot(kk);
-        for (int q = threadIdx.x; q < NREF; q += kCt) {
-            const int a = q % (kTx + 2), c = q / (kTx + 2), ii = i0 - 1 + a, jj = j0 - 1 + c;
+        for (int q = threadIdx.x; q < NREF; q += (TX * TY)) {
+            const int a = q % (TX + 2), c = q / (TX + 2), ii = i0 - 1 + a, jj = j0 - 1 + c;
             if (ii <= nx && jj <= ny) {
                 const idx_t o = pidx(g, ii, jj, kk);
                 const double vx = P.w[1][o], vy = P.w[2][o], vz = P.w[3][o];
@@ -413,16 +422,16 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
     // edges of the plane kk - 1/2 (E_x, E_y at edge index kk) into slot h
     auto horizontal_edges = [&](int kk, int h) {
         const int up = slot(kk), dn = slot(kk - 1);
-        for (int q = threadIdx.x; q < NEX; q += kCt) {
-            const int a = q % kTx, c = q / kTx, ii = i0 + a, jj = j0 + c;
+        for (int q = threadIdx.x; q < NEX; q += (TX * TY)) {
+            const int a = q % TX, c = q / TX, ii = i0 + a, jj = j0 + c;
             // E_x at (ii, jj - 1/2, kk - 1/2): B = y, C = z
             if (ii < nx && jj <= ny)
                 sex[h][c][a] = edge_emf<0>(g, F, ii, jj, kk, sref[up][0][c + 1][a + 1],
                                            sref[up][0][c][a + 1], sref[dn][0][c + 1][a + 1],
                                            sref[dn][0][c][a + 1]);
         }
-        for (int q = threadIdx.x; q < NEY; q += kCt) {
-            const int a = q % (kTx + 1), c = q / (kTx + 1), ii = i0 + a, jj = j0 + c;
+        for (int q = threadIdx.x; q < NEY; q += (TX * TY)) {
+            const int a = q % (TX + 1), c = q / (TX + 1), ii = i0 + a, jj = j0 + c;
             // E_y at (ii - 1/2, jj, kk - 1/2): B = z, C = x
             if (ii <= nx && jj < ny)
                 sey[h][c][a] = edge_emf<1>(g, F, ii, jj, kk, sref[up][1][c + 1][a + 1],
@@ -441,8 +450,8 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
         stage_ref(k + 1);  // into the slot of plane k - 1, no longer read
         __syncthreads();
         const int sk = slot(k);
-        for (int q = threadIdx.x; q < NEZ; q += kCt) {
-            const int a = q % (kTx + 1), c = q / (kTx + 1), ii = i0 + a, jj = j0 + c;
+        for (int q = threadIdx.x; q < NEZ; q += (TX * TY)) {
+            const int a = q % (TX + 1), c = q / (TX + 1), ii = i0 + a, jj = j0 + c;
             // E_z at (ii - 1/2, jj - 1/2, k): B = x, C = y
             if (ii <= nx && jj <= ny)
                 sez[c][a] = edge_emf<2>(g, F, ii, jj, k, sref[sk][2][c + 1][a + 1],
@@ -651,8 +660,20 @@ __global__ void __launch_bounds__(kBlock) k_dt_partial(Geom g, StateP s, double 
 // body as the single-instance kernel, so an instance's result equals its
 // single-instance step bit for bit.
 // ---------------------------------------------------------------------------
-enum Slot { kSlotPrims, kSlotFlux0, kSlotFlux1, kSlotFlux2, kSlotRow, kSlotMarch1, kSlotMarch2,
-            kSlotCt, kSlotDt, kSlots };
+// launches of a batched step; the march and CT launches come once per tile
+// variant (an instance has blocks only in the slot of its own variant)
+enum Slot {
+    kSlotPrims,
+    kSlotFlux0,
+    kSlotFlux1,
+    kSlotFlux2,
+    kSlotRow,
+    kSlotMarch1,
+    kSlotMarch2 = kSlotMarch1 + kMarchVariants,
+    kSlotCt = kSlotMarch2 + kMarchVariants,
+    kSlotDt = kSlotCt + kCtVariants,
+    kSlots
+};
 
 struct Inst {
     Geom g;
@@ -747,33 +768,33 @@ __global__ void __launch_bounds__(kBlock) kb_recon_x(const Inst *tab, int count,
     recon_x_body<RECON>(g, st, P, F, I.status, lb);
 }
 
-template <int D, int RECON>
+template <int D, int RECON, int V>
 __global__ void __launch_bounds__(kBlock) kb_march(const Inst *tab, int count, idx_t total)
 {
     const idx_t gb = xcd_block(total);
     if (gb >= total) return;
     idx_t lb;
-    const Inst &I = find_inst(tab, count, D == 1 ? kSlotMarch1 : kSlotMarch2, gb, lb);
+    const Inst &I = find_inst(tab, count, (D == 1 ? kSlotMarch1 : kSlotMarch2) + V, gb, lb);
     const Geom g = I.g;
     const StateP st = const_view(I.half);
     const Prims P = I.P;
     const Flux F = I.F;
-    march_body<D, RECON>(g, st, P, F, I.status, lb);
+    march_body<D, RECON, march_len(V)>(g, st, P, F, I.status, lb);
 }
 
-template <bool FULL>
+template <bool FULL, int V>
 __global__ void __launch_bounds__(kCt) kb_ct(const Inst *tab, int count, idx_t total)
 {
     const idx_t gb = xcd_block(total);
     if (gb >= total) return;
     idx_t lb;
-    const Inst &I = find_inst(tab, count, kSlotCt, gb, lb);
+    const Inst &I = find_inst(tab, count, kSlotCt + V, gb, lb);
     const Geom g = I.g;
     const Prims P = I.P;
     const Flux F = I.F;
     const StateP base = I.in;
     const StateW out = FULL ? I.out : I.half;
-    ct_body<FULL>(g, P, F, base, out, I.dt, I.status, lb);
+    ct_body<FULL, ct_tx(V), ct_ty(V)>(g, P, F, base, out, I.dt, I.status, lb);
 }
 
 __global__ void __launch_bounds__(kBlock) kb_dt_partial(const Inst *tab, int count, idx_t total)
@@ -978,8 +999,8 @@ static size_t batch_table_bytes(int count) { return align_up((size_t)count * siz
 // returns the per-slot block totals through `total`
 static void batch_records(int count, const vlct_grid *grids, const vlct_state *in,
                           const vlct_state *out, const double *dt_dev, double *next_dt_dev,
-                          uint32_t *status_dev, void *ws, std::vector<Inst> &rec,
-                          idx_t total[kSlots])
+                          uint32_t *status_dev, const uint8_t *plan, void *ws,
+                          std::vector<Inst> &rec, idx_t total[kSlots])
 {
     rec.resize(count);
     size_t off = batch_table_bytes(count);
@@ -1000,9 +1021,15 @@ static void batch_records(int count, const vlct_grid *grids, const vlct_state *i
         r.dt = dt_dev + i;
         r.next_dt = next_dt_dev ? next_dt_dev + i : nullptr;
         r.status = status_dev ? status_dev + i : nullptr;
-        const idx_t nb[kSlots] = {nblk_prims(g), nblk_flux(g, 0), nblk_flux(g, 1), nblk_flux(g, 2),
-                                  nblk_row(g), nblk_march(g, 1), nblk_march(g, 2), nblk_ct(g),
-                                  nblk_dt(g)};
+        const int cv = plan ? (plan[i] & 15) : 0, mv = plan ? (plan[i] >> 4) : 0;
+        idx_t nb[kSlots] = {};
+        nb[kSlotPrims] = nblk_prims(g);
+        for (int d = 0; d < 3; ++d) nb[kSlotFlux0 + d] = nblk_flux(g, d);
+        nb[kSlotRow] = nblk_row(g);
+        nb[kSlotMarch1 + mv] = nblk_march(g, 1, march_len(mv));
+        nb[kSlotMarch2 + mv] = nblk_march(g, 2, march_len(mv));
+        nb[kSlotCt + cv] = nblk_ct(g, ct_tx(cv), ct_ty(cv));
+        nb[kSlotDt] = nblk_dt(g);
         for (int s = 0; s < kSlots; ++s) {
             r.start[s] = total[s];
             total[s] += nb[s];
@@ -1185,18 +1212,38 @@ int vlct_step_batch(int count, const vlct_grid *grids, const vlct_state *in,
                     const vlct_state *out, const double *dt_dev, double *next_dt_dev,
                     uint32_t *status_dev, void *ws, size_t ws_bytes, void *stream)
 {
+    return vlct_step_batch_plan(count, grids, in, out, dt_dev, next_dt_dev, status_dev, nullptr,
+                                ws, ws_bytes, stream);
+}
+
+static int batch_args(int count, const vlct_grid *grids, const vlct_state *in,
+                      const vlct_state *out, const double *dt_dev, const uint8_t *plan)
+{
     if (count < 1 || count > kMaxBatch || !grids || !in || !out || !dt_dev) return VLCT_EINVAL;
     for (int i = 0; i < count; ++i)
         if (!grid_ok(&grids[i]) || !state_ok(&in[i]) || !state_ok(&out[i])) return VLCT_EINVAL;
+    if (plan)
+        for (int i = 0; i < count; ++i)
+            if ((plan[i] & 15) >= kCtVariants || (plan[i] >> 4) >= kMarchVariants) return VLCT_EINVAL;
     for (int i = 1; i < count; ++i)
         if (grids[i].recon != grids[0].recon) return VLCT_EUNSUPPORTED;
     if (!batch_aliasing_ok(count, in, out)) return VLCT_EINVAL;
+    return VLCT_OK;
+}
+
+int vlct_step_batch_plan(int count, const vlct_grid *grids, const vlct_state *in,
+                         const vlct_state *out, const double *dt_dev, double *next_dt_dev,
+                         uint32_t *status_dev, const uint8_t *plan, void *ws, size_t ws_bytes,
+                         void *stream)
+{
+    const int arc = batch_args(count, grids, in, out, dt_dev, plan);
+    if (arc) return arc;
     const size_t need = vlct_batch_workspace_bytes(grids, count);
     if (!ws || ws_bytes < need) return VLCT_EWORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<Inst> rec;
     idx_t tot[kSlots];
-    batch_records(count, grids, in, out, dt_dev, next_dt_dev, status_dev, ws, rec, tot);
+    batch_records(count, grids, in, out, dt_dev, next_dt_dev, status_dev, plan, ws, rec, tot);
     Inst *tab = static_cast<Inst *>(ws);
     for (int first = 0; first < count; first += kPackChunk) {
         PackArgs a;
@@ -1224,23 +1271,28 @@ int vlct_step_batch(int count, const vlct_grid *grids, const vlct_state *in,
         Observe o(VLCT_KERNEL_FLUX_PCM, s);
         kb_flux_pcm<2><<<xcd_grid(tot[kSlotFlux2]), kBlock, 0, s>>>(tab, count, tot[kSlotFlux2], 0);
     }
-    {
-        Observe o(VLCT_KERNEL_UPDATE_HALF, s);
-        kb_ct<false><<<xcd_grid(tot[kSlotCt]), kCt, 0, s>>>(tab, count, tot[kSlotCt]);
+#define VLCT_BCT(FULL, V)                                                                 \
+    if (tot[kSlotCt + V]) {                                                                   \
+        Observe o(FULL ? VLCT_KERNEL_UPDATE_FULL : VLCT_KERNEL_UPDATE_HALF, s);                \
+        kb_ct<FULL, V><<<xcd_grid(tot[kSlotCt + V]), kCt, 0, s>>>(tab, count, tot[kSlotCt + V]); \
     }
+    VLCT_BCT(false, 0) VLCT_BCT(false, 1) VLCT_BCT(false, 2)
     // corrector (Steps 6-9)
     {
         Observe o(VLCT_KERNEL_PRIMS, s);
         kb_prims<<<xcd_grid(tot[kSlotPrims]), kBlock, 0, s>>>(tab, count, tot[kSlotPrims], 1);
     }
+#define VLCT_BMARCH(D, R, V)                                                                  \
+    if (tot[(D == 1 ? kSlotMarch1 : kSlotMarch2) + V]) {                                      \
+        const idx_t n = tot[(D == 1 ? kSlotMarch1 : kSlotMarch2) + V];                        \
+        Observe o(VLCT_KERNEL_FLUX_RECON, s);                                                 \
+        kb_march<D, R, V><<<xcd_grid(n), kBlock, 0, s>>>(tab, count, n);                      \
+    }
 #define VLCT_BRECON(R)                                                                        \
     {                                                                                         \
         { Observe o(VLCT_KERNEL_FLUX_RECON, s);                                                \
           kb_recon_x<R><<<xcd_grid(tot[kSlotRow]), kBlock, 0, s>>>(tab, count, tot[kSlotRow]); } \
-        { Observe o(VLCT_KERNEL_FLUX_RECON, s);                                                \
-          kb_march<1, R><<<xcd_grid(tot[kSlotMarch1]), kBlock, 0, s>>>(tab, count, tot[kSlotMarch1]); } \
-        { Observe o(VLCT_KERNEL_FLUX_RECON, s);                                                \
-          kb_march<2, R><<<xcd_grid(tot[kSlotMarch2]), kBlock, 0, s>>>(tab, count, tot[kSlotMarch2]); } \
+        VLCT_BMARCH(1, R, 0) VLCT_BMARCH(1, R, 1) VLCT_BMARCH(2, R, 0) VLCT_BMARCH(2, R, 1)    \
     }
     switch (recon) {
     case VLCT_RECON_PCM:
@@ -1258,16 +1310,94 @@ int vlct_step_batch(int count, const vlct_grid *grids, const vlct_state *in,
     default: VLCT_BRECON(VLCT_RECON_PPMP) break;
     }
 #undef VLCT_BRECON
-    {
-        Observe o(VLCT_KERNEL_UPDATE_FULL, s);
-        kb_ct<true><<<xcd_grid(tot[kSlotCt]), kCt, 0, s>>>(tab, count, tot[kSlotCt]);
-    }
+#undef VLCT_BMARCH
+    VLCT_BCT(true, 0) VLCT_BCT(true, 1) VLCT_BCT(true, 2)
+#undef VLCT_BCT
     if (next_dt_dev) {
         Observe o(VLCT_KERNEL_DT, s);
         kb_dt_partial<<<(unsigned)tot[kSlotDt], kBlock, 0, s>>>(tab, count, tot[kSlotDt]);
         kb_dt_final<<<count, 1024, 0, s>>>(tab);
     }
     return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
+}
+
+int vlct_batch_tune(int count, const vlct_grid *grids, const vlct_state *in,
+                    const vlct_state *out, const double *dt_dev, void *ws, size_t ws_bytes,
+                    void *stream, int reps, uint8_t *plan)
+{
+    const int arc = batch_args(count, grids, in, out, dt_dev, nullptr);
+    if (arc) return arc;
+    if (!plan || reps < 1 || reps > 100) return VLCT_EINVAL;
+    // the trial steps write `out` and leave `in` unchanged
+    for (int i = 0; i < count; ++i)
+        if (in[i].rho == out[i].rho) return VLCT_EINVAL;
+    if (!ws || ws_bytes < vlct_batch_workspace_bytes(grids, count)) return VLCT_EWORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return VLCT_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return VLCT_EHIP;
+    }
+    // mean time of one batched step under plan p (one untimed step first)
+    auto time_plan = [&](const std::vector<uint8_t> &p, float &ms) -> int {
+        int rc = vlct_step_batch_plan(count, grids, in, out, dt_dev, nullptr, nullptr, p.data(),
+                                      ws, ws_bytes, stream);
+        if (rc) return rc;
+        if (hipEventRecord(e0, s) != hipSuccess) return VLCT_EHIP;
+        for (int r = 0; r < reps && !rc; ++r)
+            rc = vlct_step_batch_plan(count, grids, in, out, dt_dev, nullptr, nullptr, p.data(),
+                                      ws, ws_bytes, stream);
+        if (rc) return rc;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return VLCT_EHIP;
+        ms /= (float)reps;
+        return VLCT_OK;
+    };
+    // size classes by the x extent (the CT tile's long side): <= 24, <= 48, <= 96, larger;
+    // each class's CT tile, then its march segment, is changed while the rest
+    // of the batch keeps its current choice, and kept if the whole batched step
+    // gets at least 1% faster
+    std::vector<int> cls(count);
+    for (int i = 0; i < count; ++i) {
+        const int nx = grids[i].nx;
+        cls[i] = nx <= 24 ? 0 : (nx <= 48 ? 1 : (nx <= 96 ? 2 : 3));
+    }
+    std::vector<uint8_t> cur(count, 0);
+    float best = 0.0f;
+    int rc = time_plan(cur, best);
+    for (int c = 0; c < 4 && !rc; ++c) {
+        bool present = false;
+        for (int i = 0; i < count; ++i) present |= cls[i] == c;
+        if (!present) continue;
+        for (int field = 0; field < 2 && !rc; ++field) {
+            const int nv = field == 0 ? kCtVariants : kMarchVariants;
+            for (int v = 0; v < nv && !rc; ++v) {
+                std::vector<uint8_t> trial = cur;
+                bool changed = false;
+                for (int i = 0; i < count; ++i) {
+                    if (cls[i] != c) continue;
+                    const uint8_t b = field == 0 ? (uint8_t)((trial[i] & 0xF0) | v)
+                                                 : (uint8_t)((trial[i] & 0x0F) | (v << 4));
+                    changed |= b != trial[i];
+                    trial[i] = b;
+                }
+                if (!changed) continue;
+                float ms = 0.0f;
+                rc = time_plan(trial, ms);
+                if (!rc && ms < 0.99f * best) {
+                    best = ms;
+                    cur = trial;
+                }
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    for (int i = 0; i < count; ++i) plan[i] = cur[i];
+    return VLCT_OK;
 }
 
 const char *vlct_kernel_name(int kernel)

@@ -97,8 +97,9 @@ class BatchStepper:
     per kernel for all of them); per-instance dt, next dt and status live in
     device arrays of len(grids) elements."""
 
-    def __init__(self, grids, device: str = "cuda:0", inplace: bool = False):
+    def __init__(self, grids, device: str = "cuda:0", inplace: bool = False, plan=None):
         torch = _torch()
+        self.plan = list(plan) if plan is not None else None
         self.grids = list(grids)
         n = len(self.grids)
         self.device = device
@@ -139,14 +140,28 @@ class BatchStepper:
 
     def step(self) -> None:
         """One step of every instance; afterwards self.dt holds the next CFL steps."""
-        rc = vlct.vlct_step_batch(self.cgs, [d.c_state() for d in self.cur],
-                                  [d.c_state() for d in self.nxt], self.dt.data_ptr(),
-                                  self.next_dt.data_ptr(), self.status.data_ptr(),
-                                  self.ws.data_ptr(), self.ws_bytes, self.stream())
+        rc = vlct.vlct_step_batch_plan(self.cgs, [d.c_state() for d in self.cur],
+                                       [d.c_state() for d in self.nxt], self.dt.data_ptr(),
+                                       self.next_dt.data_ptr(), self.status.data_ptr(),
+                                       self.plan, self.ws.data_ptr(), self.ws_bytes, self.stream())
         if rc:
-            raise vlct.VlctError(rc, "vlct_step_batch")
+            raise vlct.VlctError(rc, "vlct_step_batch_plan")
         self.cur, self.nxt = self.nxt, self.cur
         self.dt, self.next_dt = self.next_dt, self.dt
+
+    def tune(self, reps: int = 3):
+        """Per-instance tiles from the library's autotuner (vlct_batch_tune),
+        timed on the current states with the current dt; needs out-of-place
+        stepping (the trial steps overwrite the other buffer)."""
+        if self.nxt is self.cur:
+            raise ValueError("tuning needs out-of-place stepping")
+        rc, plan = vlct.vlct_batch_tune(self.cgs, [d.c_state() for d in self.cur],
+                                        [d.c_state() for d in self.nxt], self.dt.data_ptr(),
+                                        self.ws.data_ptr(), self.ws_bytes, self.stream(), reps)
+        if rc:
+            raise vlct.VlctError(rc, "vlct_batch_tune")
+        self.plan = plan
+        return plan
 
     def status_bits(self):
         return [int(x) for x in self.status.cpu()]

@@ -33,7 +33,7 @@ EXPORTED = ("vlct_workspace_bytes", "vlct_cfl_dt", "vlct_step", "vlct_strerror",
             "vlct_batch_workspace_bytes", "vlct_step_batch", "vlct_adjoint_workspace_bytes",
             "vlct_step_adjoint", "vlct_curl_potential", "vlct_curl_potential_adjoint",
             "vlct_tape_bytes", "vlct_step_taped", "vlct_adjoint_taped_workspace_bytes",
-            "vlct_step_adjoint_taped")
+            "vlct_step_adjoint_taped", "vlct_step_batch_plan", "vlct_batch_tune")
 
 VLCT_KERNEL_PRIMS = 0
 VLCT_KERNEL_FLUX_PCM = 1
@@ -94,6 +94,17 @@ def load(path: str = LIB_PATH):
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         lib.vlct_step_batch.restype = ctypes.c_int
+        lib.vlct_step_batch_plan.argtypes = [ctypes.c_int, ctypes.POINTER(vlct_grid),
+                                             ctypes.POINTER(vlct_state), ctypes.POINTER(vlct_state),
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                             ctypes.c_void_p]
+        lib.vlct_step_batch_plan.restype = ctypes.c_int
+        lib.vlct_batch_tune.argtypes = [ctypes.c_int, ctypes.POINTER(vlct_grid),
+                                        ctypes.POINTER(vlct_state), ctypes.POINTER(vlct_state),
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+        lib.vlct_batch_tune.restype = ctypes.c_int
         lib.vlct_adjoint_workspace_bytes.argtypes = [ctypes.POINTER(vlct_grid)]
         lib.vlct_adjoint_workspace_bytes.restype = ctypes.c_size_t
         lib.vlct_step_adjoint.argtypes = [ctypes.POINTER(vlct_grid), ctypes.POINTER(vlct_state),
@@ -229,6 +240,32 @@ def vlct_curl_potential_adjoint(grid: vlct_grid, lbx: int, lby: int, lbz: int, l
                                 lay: int, laz: int, stream: int) -> int:
     return int(load().vlct_curl_potential_adjoint(ctypes.byref(grid), lbx, lby, lbz, lax, lay,
                                                   laz, stream))
+
+
+def vlct_step_batch_plan(grids, states_in, states_out, dt_dev: int, next_dt_dev: int,
+                         status_dev: int, plan, ws: int, ws_bytes: int, stream: int) -> int:
+    """vlct_step_batch with a per-instance tile plan (sequence of ints or None)."""
+    n = len(grids)
+    g = (vlct_grid * n)(*grids)
+    a = (vlct_state * n)(*states_in)
+    b = (vlct_state * n)(*states_out)
+    p = (ctypes.c_uint8 * n)(*plan) if plan is not None else None
+    return int(load().vlct_step_batch_plan(n, g, a, b, dt_dev, next_dt_dev, status_dev,
+                                           ctypes.cast(p, ctypes.c_void_p) if p is not None else None,
+                                           ws, ws_bytes, stream))
+
+
+def vlct_batch_tune(grids, states_in, states_out, dt_dev: int, ws: int, ws_bytes: int,
+                    stream: int, reps: int = 3):
+    """Returns (code, plan list) from the library's batch autotuner."""
+    n = len(grids)
+    g = (vlct_grid * n)(*grids)
+    a = (vlct_state * n)(*states_in)
+    b = (vlct_state * n)(*states_out)
+    p = (ctypes.c_uint8 * n)()
+    rc = int(load().vlct_batch_tune(n, g, a, b, dt_dev, ws, ws_bytes, stream, int(reps),
+                                    ctypes.cast(p, ctypes.c_void_p)))
+    return rc, [int(x) for x in p]
 
 
 def vlct_strerror(code: int) -> str:

@@ -109,6 +109,28 @@ def test_batch_validation():
                                 0) == vlct.VLCT_EWORKSPACE
 
 
+def test_batch_plan_and_tune_validation():
+    """Unknown tile variants and in-place tuning are rejected on the host."""
+    _lib()
+    g1, g2 = _grid(), _grid(nx=12, ny=5, nz=7)
+    two = vlct.vlct_batch_workspace_bytes([g1, g2])
+
+    def st(base):
+        return vlct.make_state([base + 4096 * f for f in range(8)])
+    a, b, c, d = st(1 << 20), st(2 << 20), st(3 << 20), st(4 << 20)
+    ws = 1 << 30
+    for bad in ([3, 0], [0, 0x20], [0, 0xF3]):
+        assert vlct.vlct_step_batch_plan([g1, g2], [a, b], [c, d], 64, 0, 0, bad, ws, two,
+                                         0) == vlct.VLCT_EINVAL
+    # tuning steps write `out`: an in-place instance is refused
+    rc, _ = vlct.vlct_batch_tune([g1, g2], [a, b], [a, d], 64, ws, two, 0)
+    assert rc == vlct.VLCT_EINVAL
+    rc, _ = vlct.vlct_batch_tune([g1, g2], [a, b], [c, d], 64, ws, two, 0, reps=0)
+    assert rc == vlct.VLCT_EINVAL
+    rc, _ = vlct.vlct_batch_tune([g1, g2], [a, b], [c, d], 64, ws, two - 1, 0)
+    assert rc == vlct.VLCT_EWORKSPACE
+
+
 def test_adjoint_validation():
     """vlct_step_adjoint rejects bad calls on the host, before any launch."""
     _lib()

@@ -142,3 +142,62 @@ def test_batch_steps_replayed_from_hip_graph():
             for f in FIELDS:
                 assert np.array_equal(a[q][f], b[q][f]), (rep, q, f)
         assert torch.equal(graphed.dt, eager.dt)
+
+
+def _run_plan(inst, dts, plan, nsteps=2):
+    from paper_2402_05240_amd.device import BatchStepper
+    import torch
+    bs = BatchStepper([g for g, _ in inst], plan=plan).upload([s for _, s in inst])
+    bs.set_dt(dts)
+    nexts = []
+    for _ in range(nsteps):
+        bs.step()
+        nexts.append(bs.dt.cpu().numpy().copy())
+    torch.cuda.synchronize()
+    return bs.download(), nexts
+
+
+def test_batch_tile_plans_are_bit_identical():
+    """Every per-instance tile plan (CT tiles 64x8, 32x16, 16x32; march
+    segments 32, 16) gives exactly the default plan's results: the tiles only
+    regroup the same per-cell and per-face arithmetic."""
+    _need_gpu()
+    inst = _instances(2)
+    dts = [ref.cfl_dt(g, s) for g, s in inst]
+    base, base_dt = _run_plan(inst, dts, None)
+    rng = np.random.default_rng(3)
+    plans = [[0x11] * len(inst), [0x02] * len(inst),
+             [int(rng.integers(0, 3)) | (int(rng.integers(0, 2)) << 4) for _ in inst]]
+    for plan in plans:
+        _say("plan %s" % [hex(p) for p in plan])
+        outs, nexts = _run_plan(inst, dts, plan)
+        for q in range(len(inst)):
+            for f in FIELDS:
+                assert np.array_equal(outs[q][f], base[q][f]), (plan, q, f)
+        for a, b in zip(nexts, base_dt):
+            assert np.array_equal(a, b)
+
+
+def test_batch_autotuner_plan_is_valid_and_exact():
+    _need_gpu()
+    from paper_2402_05240_amd.device import BatchStepper
+    import torch
+    ens = I.ensemble(12, seed=7, nmin=16, nmax=64)
+    inst = [(g, s) for g, s, _ in ens]
+    dts = [ref.cfl_dt(g, s) for g, s in inst]
+    tuner = BatchStepper([g for g, _ in inst]).upload([s for _, s in inst])
+    tuner.set_dt(dts)
+    plan = tuner.tune(reps=2)
+    torch.cuda.synchronize()
+    _say("tuned plan %s" % [hex(p) for p in plan])
+    assert len(plan) == len(inst)
+    assert all((p & 15) < 3 and (p >> 4) < 2 for p in plan)
+    # the tuner leaves the input states untouched
+    for d, (g, s) in zip(tuner.download(), inst):
+        for f in FIELDS:
+            assert np.array_equal(d[f], s[f])
+    base, _ = _run_plan(inst, dts, None, nsteps=1)
+    tuned, _ = _run_plan(inst, dts, plan, nsteps=1)
+    for q in range(len(inst)):
+        for f in FIELDS:
+            assert np.array_equal(tuned[q][f], base[q][f]), (q, f)
