@@ -205,3 +205,46 @@ def test_adjoint_is_linear_in_the_cotangent():
         ref_v = 2.0 * a[f] - 3.0 * b[f]
         scale = float(np.abs(2.0 * a[f]).max() + np.abs(3.0 * b[f]).max())
         assert float(np.abs(c[f] - ref_v).max()) <= 1e-13 * scale, f
+
+
+@pytest.fixture(scope="module")
+def cso(tmp_path_factory):
+    from complex_step import cs
+    return cs.build(tmp_path_factory.mktemp("cs_oracle"))
+
+
+@pytest.mark.parametrize("recon", RECONS)
+def test_adjoint_against_complex_step_of_the_oracle(cso, recon):
+    """<lam_in, delta> against <lam_out, J delta> with J delta from the
+    complex-step build of the oracle (exact to rounding, every branch at the
+    unperturbed state like the adjoint's), for full random directions over
+    every coordinate of a 16^3 grid, and lam_in element by element for
+    sampled coordinates (J e_j): within 1e-10."""
+    _need_gpu()
+    g, s = _state((16, 16, 16), recon, 41)
+    dt = ref.cfl_dt(g, s)
+    lam = _random_cotangent(g, 42)
+    lin = _gpu_vjp(g, s, lam, dt)
+    rng = np.random.default_rng(43)
+    worst = 0.0
+    for rep in range(3):
+        delta = {f: rng.standard_normal(g.field_shape(f)) for f in FIELDS}
+        I._periodic_face_copy(g, delta)
+        _, jv, st = cso.jvp(g, s, delta, [dt])
+        assert st == 0
+        want = sum(float(np.sum(lam[f] * jv[f])) for f in FIELDS)
+        scale = sum(float(np.sum(np.abs(lam[f] * jv[f]))) for f in FIELDS)
+        got = sum(float(np.sum(lin[f] * delta[f])) for f in FIELDS)
+        worst = max(worst, abs(got - want) / scale)
+    for f in FIELDS:
+        shape = list(g.field_shape(f))
+        for _ in range(3):
+            idx = tuple(int(rng.integers(0, m - (1 if (f, a) in (("bx", 2), ("by", 1), ("bz", 0)) else 0)))
+                        for a, m in enumerate(shape))
+            e = _unit(g, f, idx)
+            _, jv, _ = cso.jvp(g, s, e, [dt])
+            want = sum(float(np.sum(lam[q] * jv[q])) for q in FIELDS)
+            scale = sum(float(np.sum(np.abs(lam[q] * jv[q]))) for q in FIELDS)
+            worst = max(worst, abs(float(lin[f][idx]) - want) / scale)
+    _say("recon %d: worst rel err against complex step %.2e" % (recon, worst))
+    assert worst <= 1e-10

@@ -287,3 +287,46 @@ def test_inverse_problem_gradient_matches_oracle_differences():
             assert err <= 1e-6, (which, idx, float(gr[idx]), f1)
     _say("checked %d, skipped %d (branch point), worst rel err %.2e" % (checked, skipped, worst))
     assert skipped <= 0.1 * (checked + skipped)
+
+
+def test_inverse_problem_gradient_matches_oracle_complex_step(tmp_path):
+    """The 16^3, 6-step inverse problem's gradient along full random
+    directions of all parameters (rho, m, E and the vector potential) against
+    the complex-step derivative of the oracle's loss: within 1e-10."""
+    _need_gpu()
+    import torch
+    from complex_step import cs
+    from paper_2402_05240_amd import autograd as AG
+    cso = cs.build(tmp_path)
+    g = _grid((16, 16, 16))
+    rho, v, p, A = _params(g, 7)
+    b0 = (0.8, 0.0, 0.0)
+    s0 = _state_from(g, rho, v, p, A, b0)
+    rng = np.random.default_rng(8)
+    target = s0["rho"] * (1.0 + 0.05 * _smooth(g, rng))
+    sim = AG.Simulator(g)
+    names = ("rho", "mx", "my", "mz", "E")
+    cons = [torch.from_numpy(s0[f]).cuda().requires_grad_(True) for f in names]
+    pot = [torch.from_numpy(a).cuda().requires_grad_(True) for a in A]
+    bfaces = AG.curl(sim, *pot)
+    out, dts = AG.rollout(sim, cons + [b + c for b, c in zip(bfaces, b0)], nsteps=6)
+    loss = ((out[0] - torch.from_numpy(target).cuda()) ** 2).mean()
+    loss.backward()
+    torch.cuda.synchronize()
+    dts = [float(x.item()) for x in dts]
+    grads = [c.grad.cpu().numpy() for c in cons] + [a.grad.cpu().numpy() for a in pot]
+    worst = 0.0
+    for rep in range(3):
+        dc = [rng.standard_normal(s0[f].shape) for f in names]
+        da = [rng.standard_normal(a.shape) for a in A]
+        # the state direction: conserved part as drawn, faces through the curl
+        dbx, dby, dbz = I.curl_edge_potential(g, *da)
+        ds = dict(zip(names, dc))
+        ds.update({"bx": dbx, "by": dby, "bz": dbz})
+        fin, jv, st = cso.jvp(g, s0, ds, dts)
+        assert st == 0
+        want = float(np.mean(2.0 * (fin["rho"] - target) * jv["rho"]))
+        got = sum(float(np.sum(gr * d)) for gr, d in zip(grads, dc + da))
+        worst = max(worst, abs(got - want) / abs(want))
+    _say("inverse problem: worst rel err against complex step %.2e" % worst)
+    assert worst <= 1e-10
