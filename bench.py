@@ -398,7 +398,7 @@ def ensemble_bench(count, steps, warmup):
     ms_tuned = timed(tbs.step, steps)
     hist = {}
     for p in plan:
-        key = "ct%dx%d_march%d" % ((64, 32, 16)[p & 15], (8, 16, 32)[p & 15], (32, 16)[p >> 4])
+        key = "ct%dx%d_march%d" % ((64, 32, 16)[p & 15], (8, 16, 32)[p & 15], (16, 32, 8)[p >> 4])
         hist[key] = hist.get(key, 0) + 1
     outs = bs.download()
     same = all(np.array_equal(o[f], st.download()[f]) for o, st in zip(outs, singles)

@@ -24,7 +24,7 @@ namespace vlct {
 // logical block counts of the kernels (host launches and batch offsets)
 // ---------------------------------------------------------------------------
 constexpr int kRowFaces = kBlock - 1;
-constexpr int kMarch = 32;
+constexpr int kMarch = 16;
 constexpr int kTx = 64, kTy = 8, kTz = 16;
 constexpr int kCt = kTx * kTy;  // threads of a CT block: one per column of the tile
 
@@ -32,10 +32,10 @@ constexpr int kCt = kTx * kTy;  // threads of a CT block: one per column of the 
 // variant in the low nibble, march variant in the high nibble); variant 0 is
 // the single-instance kernels' shape
 constexpr int kCtVariants = 3;     // CT column tiles 64 x 8, 32 x 16, 16 x 32 (kCt threads)
-constexpr int kMarchVariants = 2;  // march segments of 32 and 16 faces
+constexpr int kMarchVariants = 3;  // march segments of 16, 32 and 8 faces
 __host__ __device__ constexpr int ct_tx(int v) { return v == 0 ? 64 : (v == 1 ? 32 : 16); }
 __host__ __device__ constexpr int ct_ty(int v) { return kCt / ct_tx(v); }
-__host__ __device__ constexpr int march_len(int v) { return v == 0 ? 32 : 16; }
+__host__ __device__ constexpr int march_len(int v) { return v == 0 ? 16 : (v == 1 ? 32 : 8); }
 
 __host__ __device__ __forceinline__ idx_t nblk_prims(const Geom &g)
 {
@@ -1292,7 +1292,8 @@ int vlct_step_batch_plan(int count, const vlct_grid *grids, const vlct_state *in
     {                                                                                         \
         { Observe o(VLCT_KERNEL_FLUX_RECON, s);                                                \
           kb_recon_x<R><<<xcd_grid(tot[kSlotRow]), kBlock, 0, s>>>(tab, count, tot[kSlotRow]); } \
-        VLCT_BMARCH(1, R, 0) VLCT_BMARCH(1, R, 1) VLCT_BMARCH(2, R, 0) VLCT_BMARCH(2, R, 1)    \
+        VLCT_BMARCH(1, R, 0) VLCT_BMARCH(1, R, 1) VLCT_BMARCH(1, R, 2)                        \
+        VLCT_BMARCH(2, R, 0) VLCT_BMARCH(2, R, 1) VLCT_BMARCH(2, R, 2)                        \
     }
     switch (recon) {
     case VLCT_RECON_PCM:

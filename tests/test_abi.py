@@ -119,7 +119,7 @@ def test_batch_plan_and_tune_validation():
         return vlct.make_state([base + 4096 * f for f in range(8)])
     a, b, c, d = st(1 << 20), st(2 << 20), st(3 << 20), st(4 << 20)
     ws = 1 << 30
-    for bad in ([3, 0], [0, 0x20], [0, 0xF3]):
+    for bad in ([3, 0], [0, 0x30], [0, 0xF3]):
         assert vlct.vlct_step_batch_plan([g1, g2], [a, b], [c, d], 64, 0, 0, bad, ws, two,
                                          0) == vlct.VLCT_EINVAL
     # tuning steps write `out`: an in-place instance is refused
