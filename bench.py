@@ -418,15 +418,19 @@ def ensemble_bench(count, steps, warmup):
             "bitwise_equal": bool(same)}
 
 
-def adjoint_bench(n, steps, warmup):
+RECON_NAMES = {1: "PCM", 2: "PLMC", 3: "PPMC", 4: "PLMP", 5: "PPMP"}
+
+
+def adjoint_bench(n, steps, warmup, recon=2):
     """Cost of the adjoint of one step against one forward step on decaying
-    turbulence at n^3 (PLMC): the forward step is vlct_step with the next-dt
-    reduction, the adjoint is vlct_step_adjoint (which recomputes the forward
-    intermediates it needs); both timed with events on the current stream."""
+    turbulence at n^3 (PLMC unless `recon` says otherwise): the forward step
+    is vlct_step with the next-dt reduction, the adjoint is vlct_step_adjoint
+    (which recomputes the forward intermediates it needs); both timed with
+    events on the current stream."""
     import torch
     from paper_2402_05240_amd import inputs as I
     from paper_2402_05240_amd.device import Adjoint, Stepper
-    g, s = I.turbulence((n, n, n))
+    g, s = I.turbulence((n, n, n), recon=recon)
     fwd = Stepper(g).upload(s)
     fwd.compute_dt()
     dt = float(fwd.dt.item())
@@ -475,7 +479,8 @@ def adjoint_bench(n, steps, warmup):
         rounds["taped_adjoint"].append(timed(ataped, steps))
     ms_f, ms_a = min(rounds["forward"]), min(rounds["adjoint"])
     ms_ft, ms_at = min(rounds["taped_forward"]), min(rounds["taped_adjoint"])
-    return {"workload": "turbulence_plmc_%d" % n, "grid": [n, n, n], "recon": "PLMC",
+    name = RECON_NAMES[recon]
+    return {"workload": "turbulence_%s_%d" % (name.lower(), n), "grid": [n, n, n], "recon": name,
             "steps": steps, "forward_ms": ms_f, "adjoint_ms": ms_a, "ratio": ms_a / ms_f,
             "taped_forward_ms": ms_ft, "taped_adjoint_ms": ms_at,
             "ratio_taped": ms_at / ms_f, "tape_bytes": sim.tape_bytes,
@@ -553,6 +558,9 @@ def main():
                     help="skip the differentiable inverse-problem measurement")
     ap.add_argument("--inverse-n", type=int, default=128)
     ap.add_argument("--inverse-steps", type=int, default=200)
+    ap.add_argument("--adjoint-recon", default="plmc",
+                    choices=["pcm", "plmc", "ppmc", "plmp", "ppmp"],
+                    help="corrector reconstruction of the adjoint cost measurement")
     ap.add_argument("--cpu-planes", type=int, default=256)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--cpu-threads", type=int, default=0)
@@ -632,7 +640,7 @@ def main():
     value = ncell * args.steps / (ms_total * 1e-3)
     rl = rooflines(g, kern, args.steps, args.workload)
     dom = max(rl, key=lambda k: rl[k]["ms_per_step"])
-    recon_name = {1: "PCM", 2: "PLMC", 3: "PPMC", 4: "PLMP", 5: "PPMP"}[g.recon]
+    recon_name = RECON_NAMES[g.recon]
     design_bytes = sum(r["bytes_per_step"] for r in rl.values() if "bytes_per_step" in r) / ncell
     out = {
         "metric": BASELINE_METRIC,
@@ -669,7 +677,8 @@ def main():
     del st
     torch.cuda.empty_cache()
     if not args.no_adjoint:
-        costs = [adjoint_bench(n, args.adjoint_steps, 2) for n in args.adjoint_n]
+        recon = {v.lower(): k for k, v in RECON_NAMES.items()}[args.adjoint_recon]
+        costs = [adjoint_bench(n, args.adjoint_steps, 2, recon) for n in args.adjoint_n]
         out["adjoint_forward_cost"] = costs[0] if len(costs) == 1 else costs
         torch.cuda.empty_cache()
     if not args.no_inverse:

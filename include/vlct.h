@@ -184,8 +184,8 @@ size_t vlct_adjoint_workspace_bytes(const vlct_grid *g);
 
 /* Writes lam_in (device arrays, none shared with `in` or `lam_out`, else
  * VLCT_EINVAL).  in, lam_out: device, read only.  dt_dev: device pointer to
- * the step size.  Periodic boundaries on every axis and the PCM, PLMC and
- * PLMP correctors only (else VLCT_EUNSUPPORTED).  VLCT_EWORKSPACE if
+ * the step size.  Periodic boundaries on every axis only (else
+ * VLCT_EUNSUPPORTED); every corrector reconstruction.  VLCT_EWORKSPACE if
  * ws_bytes < vlct_adjoint_workspace_bytes(g).  Stream-ordered; no
  * allocation and no host synchronisation. */
 int vlct_step_adjoint(const vlct_grid *g, const vlct_state *in, const vlct_state *lam_out,

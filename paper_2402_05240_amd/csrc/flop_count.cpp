@@ -58,7 +58,7 @@ int main()
     };
     const int N = 20000;
     long long plmc_f = 0, ppmc_f = 0, plmp_f = 0, ppmp_f = 0, hlld_f = 0;
-    long long hlld_r = 0, plmc_r = 0, plmp_r = 0;
+    long long hlld_r = 0, plmc_r = 0, plmp_r = 0, ppmc_r = 0, ppmp_r = 0;
     for (int q = 0; q < N; ++q) {
         vlct::W7 a = state(), b = state(), c = state(), d = state(), e = state();
         // smooth-ish stencils: neighbours close to the centre
@@ -105,6 +105,15 @@ int main()
         f0 = g_flops;
         vlct::plmc_rev<false>(m1, c, p1, Counted(bn), Counted(gam), afm, afp, aL, aR, a3, abn);
         plmp_r += g_flops - f0;
+        vlct::W7 a4{0, 0, 0, 0, 0, 0, 0}, a5{0, 0, 0, 0, 0, 0, 0};
+        f0 = g_flops;
+        vlct::ppmc_rev<true>(m2, m1, c, p1, p2, Counted(bn), Counted(gam), afm, afp, aL, aR, a3,
+                             a4, a5, abn);
+        ppmc_r += g_flops - f0;
+        f0 = g_flops;
+        vlct::ppmc_rev<false>(m2, m1, c, p1, p2, Counted(bn), Counted(gam), afm, afp, aL, aR, a3,
+                              a4, a5, abn);
+        ppmp_r += g_flops - f0;
     }
     std::printf("plmc_per_call %.1f\nppmc_per_call %.1f\nhlld_per_call %.1f\n",
                 double(plmc_f) / N, double(ppmc_f) / N, double(hlld_f) / N);
@@ -123,5 +132,8 @@ int main()
                 double(hlld_r) / N, double(plmc_r) / N, double(plmp_r) / N);
     std::printf("adj_faces_plmc_per_face %.1f\nadj_faces_pcm_per_face %.1f\n",
                 double(2 * plmc_f + hlld_r) / N, double(hlld_r) / N);
+    std::printf("ppmc_rev_per_call %.1f\nppmp_rev_per_call %.1f\n", double(ppmc_r) / N,
+                double(ppmp_r) / N);
+    std::printf("adj_faces_ppmc_per_face %.1f\n", double(2 * ppmc_f + hlld_r) / N);
     return 0;
 }

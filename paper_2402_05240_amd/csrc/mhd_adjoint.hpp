@@ -769,4 +769,330 @@ VLCT_DEV void plmc_rev(const W7 &wm, const W7 &w0, const W7 &wp, double bn, doub
     a_wp.bz = a_wp.bz + ap_[6];
 }
 
+// ---------------------------------------------------------------------------
+// PPMC / PPMP reverse
+// ---------------------------------------------------------------------------
+// ppm_face(am, a0, ap, app) reversed: adds the cotangents of its four inputs
+// given that of its output
+VLCT_DEV void ppm_face_rev(double am, double a0, double ap, double app, double af, double &a_am,
+                           double &a_a0, double &a_ap, double &a_app)
+{
+    const double f0 = (7.0 / 12.0) * (a0 + ap) - (1.0 / 12.0) * (am + app);
+    double a_f0 = 0.0;
+    if ((f0 - a0) * (ap - f0) < 0.0) {
+        // f = (a0 + ap) / 2 - lim / 3
+        const double d2 = 3.0 * (a0 - 2.0 * f0 + ap);
+        const double d2l = am - 2.0 * a0 + ap;
+        const double d2r = a0 - 2.0 * ap + app;
+        a_a0 = a_a0 + 0.5 * af;
+        a_ap = a_ap + 0.5 * af;
+        const double a_lim = -af / 3.0;
+        if (d2 * d2l > 0.0 && d2 * d2r > 0.0) {
+            // lim = sign(d2) min(C |d2l|, C |d2r|, |d2|): all three share d2's sign
+            const double A = kPpmC * fabs(d2l), Bv = kPpmC * fabs(d2r), Cv = fabs(d2);
+            const bool ab_b = takes_second_min(A, Bv);
+            const double mab = ab_b ? Bv : A;
+            const bool pick_c = takes_second_min(mab, Cv);
+            if (pick_c) {
+                const double a_d2 = a_lim;  // lim = d2
+                a_a0 = a_a0 + 3.0 * a_d2;
+                a_ap = a_ap + 3.0 * a_d2;
+                a_f0 = a_f0 - 6.0 * a_d2;
+            } else if (ab_b) {
+                const double a_d2r = kPpmC * a_lim;  // lim = C d2r
+                a_a0 = a_a0 + a_d2r;
+                a_ap = a_ap - 2.0 * a_d2r;
+                a_app = a_app + a_d2r;
+            } else {
+                const double a_d2l = kPpmC * a_lim;  // lim = C d2l
+                a_am = a_am + a_d2l;
+                a_a0 = a_a0 - 2.0 * a_d2l;
+                a_ap = a_ap + a_d2l;
+            }
+        }
+    } else {
+        a_f0 = af;
+    }
+    a_a0 = a_a0 + (7.0 / 12.0) * a_f0;
+    a_ap = a_ap + (7.0 / 12.0) * a_f0;
+    a_am = a_am - (1.0 / 12.0) * a_f0;
+    a_app = a_app - (1.0 / 12.0) * a_f0;
+}
+
+// the clamp fmax(fmin(lo_a, lo_b), fmin(v, fmax(hi_a, hi_b))) as ppmc writes it
+// (bounds from the pair (0 or x0, neighbour)): returns which argument it
+// passes through -- 0: v, 1: the first bound argument (0 / x0), 2: the
+// neighbour
+VLCT_DEV int clamp_pick(double x0, double nb, double v)
+{
+    const bool lo_nb = takes_second_min(x0, nb);
+    const double lo = lo_nb ? nb : x0;
+    const bool hi_nb = takes_second_max(x0, nb);
+    const double hi = hi_nb ? nb : x0;
+    const bool inner_hi = takes_second_min(v, hi);
+    const double inner = inner_hi ? hi : v;
+    const bool outer_inner = takes_second_max(lo, inner);
+    if (outer_inner) return inner_hi ? (hi_nb ? 2 : 1) : 0;
+    return lo_nb ? 2 : 1;
+}
+
+template <bool CHAR>
+VLCT_DEV void ppmc_rev(const W7 &wmm, const W7 &wm, const W7 &w0, const W7 &wp, const W7 &wpp,
+                       double bn, double gam, const double a_fm[7], const double a_fp[7],
+                       W7 &a_wmm, W7 &a_wm, W7 &a_w0, W7 &a_wp, W7 &a_wpp, double &a_bn)
+{
+    // ---- forward (the steps of ppmc, the quantities the reverse needs kept)
+    Eigen E;
+    double fv, fb;
+    if (CHAR) {
+        eigen_setup(w0, bn, gam, E);
+        fv = E.cf;
+        fb = E.sqd * E.cf;
+    } else {
+        fv = fast_speed(w0.d, w0.p, bn, w0.by, w0.bz, gam);
+        fb = sqrt(w0.d) * fv;
+    }
+    const double floor_c[7] = {0.0, fv, fv, fv, 0.0, fb, fb};
+    double x0[7], xn[4][7], xs[4][7];
+    to_arr(w0, x0);
+    to_arr(wmm, xn[0]);
+    to_arr(wm, xn[1]);
+    to_arr(wp, xn[2]);
+    to_arr(wpp, xn[3]);
+    bool tie[4][7];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            const double d = xn[q][c] - x0[c];
+            tie[q][c] = fabs(d) <= kPpmTie * (fabs(xn[q][c]) + fabs(x0[c]) + floor_c[c]);
+            xs[q][c] = tie[q][c] ? 0.0 : d;
+        }
+    double a[4][7];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (CHAR) {
+            project(E, xs[q], a[q]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 7; ++c) a[q][c] = xs[q][c];
+        }
+    }
+    double dplus[7], dminus[7];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+        const double a_2 = a[0][m], a_1 = a[1][m], a1 = a[2][m], a2 = a[3][m];
+        const double fl = ppm_face(a_2, a_1, 0.0, a1);
+        const double fr = ppm_face(a_1, 0.0, a1, a2);
+        double dp = fr, dm = -fl;
+        if (dp * dm <= 0.0 || a1 * (-a_1) <= 0.0) {
+            const double d2 = 6.0 * (fl + fr);
+            const double d2c = a_1 + a1, d2l = a_2 - 2.0 * a_1, d2r = -2.0 * a1 + a2;
+            double lim = 0.0;
+            if (d2 * d2c > 0.0 && d2 * d2l > 0.0 && d2 * d2r > 0.0)
+                lim = copysign(fmin(fmin(kPpmC * fabs(d2l), kPpmC * fabs(d2r)),
+                                    fmin(kPpmC * fabs(d2c), fabs(d2))), d2);
+            const double ratio = d2 != 0.0 ? lim / d2 : 0.0;
+            dp = dp * ratio;
+            dm = dm * ratio;
+        } else {
+            if (fabs(dp) >= 2.0 * fabs(dm)) dp = 2.0 * dm;
+            if (fabs(dm) >= 2.0 * fabs(dp)) dm = 2.0 * dp;
+        }
+        dplus[m] = fmax(fmin(0.0, a1), fmin(dp, fmax(0.0, a1)));
+        dminus[m] = fmax(fmin(0.0, a_1), fmin(-dm, fmax(0.0, a_1)));
+    }
+    double wpl[7], wmi[7];
+    if (CHAR) {
+        unproject(E, dplus, wpl);
+        unproject(E, dminus, wmi);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            wpl[c] = dplus[c];
+            wmi[c] = dminus[c];
+        }
+    }
+
+    // ---- reverse
+    double a_x0[7] = {0, 0, 0, 0, 0, 0, 0}, a_xn[4][7];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 7; ++c) a_xn[q][c] = 0.0;
+    double a_wpl[7], a_wmi[7];
+    // primitive bounds and the CW84 constraints
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+        const double xl = xn[1][c], xr = xn[2][c];
+        const double up = x0[c] + wpl[c], um = x0[c] + wmi[c];
+        const double vp = fmax(fmin(x0[c], xr), fmin(up, fmax(x0[c], xr)));
+        const double vm = fmax(fmin(x0[c], xl), fmin(um, fmax(x0[c], xl)));
+        const double tol = kPpmTie * (fabs(x0[c]) + fabs(xl) + fabs(xr) + floor_c[c]);
+        double a_vp = a_fp[c], a_vm = a_fm[c];
+        if (fabs(vp - up) > tol || fabs(vm - um) > tol) {
+            const double dpp = vp - x0[c], dmm = x0[c] - vm;
+            if (dpp * dmm <= 0.0) {
+                // vp = vm = x0
+                a_x0[c] = a_x0[c] + a_vp + a_vm;
+                a_vp = 0.0;
+                a_vm = 0.0;
+            } else {
+                double a_dpp = 0.0, a_dmm = 0.0;
+                if (fabs(dpp) >= 2.0 * fabs(dmm)) {  // vp = x0 + 2 dmm
+                    a_x0[c] = a_x0[c] + a_vp;
+                    a_dmm = a_dmm + 2.0 * a_vp;
+                    a_vp = 0.0;
+                }
+                if (fabs(dmm) >= 2.0 * fabs(dpp)) {  // vm = x0 - 2 dpp
+                    a_x0[c] = a_x0[c] + a_vm;
+                    a_dpp = a_dpp - 2.0 * a_vm;
+                    a_vm = 0.0;
+                }
+                // dpp = vp - x0, dmm = x0 - vm (of the bounded values)
+                a_vp = a_vp + a_dpp;
+                a_x0[c] = a_x0[c] - a_dpp + a_dmm;
+                a_vm = a_vm - a_dmm;
+            }
+        }
+        // the bounds: each passes up / um, x0 or the neighbour through
+        double a_up = 0.0, a_um = 0.0;
+        const int pp = clamp_pick(x0[c], xr, up), pm = clamp_pick(x0[c], xl, um);
+        if (pp == 0) a_up = a_vp; else if (pp == 1) a_x0[c] = a_x0[c] + a_vp; else a_xn[2][c] = a_xn[2][c] + a_vp;
+        if (pm == 0) a_um = a_vm; else if (pm == 1) a_x0[c] = a_x0[c] + a_vm; else a_xn[1][c] = a_xn[1][c] + a_vm;
+        a_x0[c] = a_x0[c] + a_up + a_um;
+        a_wpl[c] = a_up;
+        a_wmi[c] = a_um;
+    }
+    // back-projection
+    double a_dplus[7] = {0, 0, 0, 0, 0, 0, 0}, a_dminus[7] = {0, 0, 0, 0, 0, 0, 0};
+    EigenA EA;
+    if (CHAR) {
+        eigen_zero(EA);
+        unproject_rev(E, dplus, a_wpl, a_dplus, EA);
+        unproject_rev(E, dminus, a_wmi, a_dminus, EA);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            a_dplus[c] = a_wpl[c];
+            a_dminus[c] = a_wmi[c];
+        }
+    }
+    // per wave: the characteristic limiter chain
+    double a_a[4][7];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+        const double a_2 = a[0][m], a_1 = a[1][m], a1 = a[2][m], a2 = a[3][m];
+        const double fl = ppm_face(a_2, a_1, 0.0, a1);
+        const double fr = ppm_face(a_1, 0.0, a1, a2);
+        const double dp0 = fr, dm0 = -fl;
+        double aa_2 = 0.0, aa_1 = 0.0, aa1 = 0.0, aa2 = 0.0;
+        // recompute the limited dp, dm with their branch
+        const bool ext = dp0 * dm0 <= 0.0 || a1 * (-a_1) <= 0.0;
+        double dp = dp0, dm = dm0, ratio = 0.0, d2 = 0.0, lim = 0.0;
+        int lim_pick = -1;  // 0: C d2l, 1: C d2r, 2: C d2c, 3: d2, -1: zero
+        bool o1 = false, o2 = false;
+        if (ext) {
+            d2 = 6.0 * (fl + fr);
+            const double d2c = a_1 + a1, d2l = a_2 - 2.0 * a_1, d2r = -2.0 * a1 + a2;
+            if (d2 * d2c > 0.0 && d2 * d2l > 0.0 && d2 * d2r > 0.0) {
+                const double L = kPpmC * fabs(d2l), R = kPpmC * fabs(d2r);
+                const double Cc = kPpmC * fabs(d2c), Dd = fabs(d2);
+                const bool lr = takes_second_min(L, R);
+                const double mlr = lr ? R : L;
+                const bool cd = takes_second_min(Cc, Dd);
+                const double mcd = cd ? Dd : Cc;
+                const bool pick2 = takes_second_min(mlr, mcd);
+                lim_pick = pick2 ? (cd ? 3 : 2) : (lr ? 1 : 0);
+                lim = copysign(pick2 ? mcd : mlr, d2);
+            }
+            ratio = d2 != 0.0 ? lim / d2 : 0.0;
+            dp = dp0 * ratio;
+            dm = dm0 * ratio;
+        } else {
+            o1 = fabs(dp0) >= 2.0 * fabs(dm0);
+            if (o1) dp = 2.0 * dm0;
+            o2 = fabs(dm0) >= 2.0 * fabs(dp);
+            if (o2) dm = 2.0 * dp;
+        }
+        // dplus = clamp of dp to the pair (0, a1); dminus = clamp of -dm to (0, a_1)
+        double a_dp = 0.0, a_dm = 0.0;
+        {
+            const int pk = clamp_pick(0.0, a1, dp);
+            if (pk == 0) a_dp = a_dplus[m]; else if (pk == 2) aa1 = aa1 + a_dplus[m];
+            const int mk = clamp_pick(0.0, a_1, -dm);
+            if (mk == 0) a_dm = -a_dminus[m]; else if (mk == 2) aa_1 = aa_1 + a_dminus[m];
+        }
+        double a_fl = 0.0, a_fr = 0.0;
+        if (ext) {
+            const double a_dp0 = ratio * a_dp, a_dm0 = ratio * a_dm;
+            const double a_ratio = dp0 * a_dp + dm0 * a_dm;
+            double a_d2 = 0.0, a_lim = 0.0;
+            if (d2 != 0.0) {
+                a_lim = a_ratio / d2;
+                a_d2 = -a_ratio * ratio / d2;
+            }
+            // lim = sign(d2) min(...): all candidates share d2's sign
+            double a_d2l = 0.0, a_d2r = 0.0, a_d2c = 0.0;
+            if (lim_pick == 0) a_d2l = kPpmC * a_lim;
+            else if (lim_pick == 1) a_d2r = kPpmC * a_lim;
+            else if (lim_pick == 2) a_d2c = kPpmC * a_lim;
+            else if (lim_pick == 3) a_d2 = a_d2 + a_lim;
+            a_fl = a_fl + 6.0 * a_d2 - a_dm0;
+            a_fr = a_fr + 6.0 * a_d2 + a_dp0;
+            aa_1 = aa_1 + a_d2c - 2.0 * a_d2l;
+            aa1 = aa1 + a_d2c - 2.0 * a_d2r;
+            aa_2 = aa_2 + a_d2l;
+            aa2 = aa2 + a_d2r;
+        } else {
+            double a_dp1 = a_dp, a_dm0 = 0.0, a_dp0 = 0.0;
+            if (o2) a_dp1 = a_dp1 + 2.0 * a_dm; else a_dm0 = a_dm0 + a_dm;
+            if (o1) a_dm0 = a_dm0 + 2.0 * a_dp1; else a_dp0 = a_dp0 + a_dp1;
+            a_fr = a_fr + a_dp0;
+            a_fl = a_fl - a_dm0;
+        }
+        // fl = ppm_face(a_2, a_1, 0, a1), fr = ppm_face(a_1, 0, a1, a2)
+        double dummy = 0.0;
+        ppm_face_rev(a_2, a_1, 0.0, a1, a_fl, aa_2, aa_1, dummy, aa1);
+        ppm_face_rev(a_1, 0.0, a1, a2, a_fr, aa_1, dummy, aa1, aa2);
+        a_a[0][m] = aa_2;
+        a_a[1][m] = aa_1;
+        a_a[2][m] = aa1;
+        a_a[3][m] = aa2;
+    }
+    // projections of the stencil differences, then the tie snapping
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        double a_xs[7] = {0, 0, 0, 0, 0, 0, 0};
+        if (CHAR) {
+            project_rev(E, xs[q], a_a[q], a_xs, EA);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 7; ++c) a_xs[c] = a_a[q][c];
+        }
+#pragma unroll
+        for (int c = 0; c < 7; ++c)
+            if (!tie[q][c]) {
+                a_xn[q][c] = a_xn[q][c] + a_xs[c];
+                a_x0[c] = a_x0[c] - a_xs[c];
+            }
+    }
+    W7 ae0{a_x0[0], a_x0[1], a_x0[2], a_x0[3], a_x0[4], a_x0[5], a_x0[6]};
+    if (CHAR) eigen_rev(w0, bn, gam, EA, ae0, a_bn);
+    W7 *outs[5] = {&a_wmm, &a_wm, &a_w0, &a_wp, &a_wpp};
+    const double *src[5] = {a_xn[0], a_xn[1], nullptr, a_xn[2], a_xn[3]};
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        W7 &o = *outs[q];
+        if (q == 2) {
+            o.d = o.d + ae0.d; o.u = o.u + ae0.u; o.v = o.v + ae0.v; o.w = o.w + ae0.w;
+            o.p = o.p + ae0.p; o.by = o.by + ae0.by; o.bz = o.bz + ae0.bz;
+        } else {
+            const double *v = src[q];
+            o.d = o.d + v[0]; o.u = o.u + v[1]; o.v = o.v + v[2]; o.w = o.w + v[3];
+            o.p = o.p + v[4]; o.by = o.by + v[5]; o.bz = o.bz + v[6];
+        }
+    }
+}
+
 }  // namespace vlct

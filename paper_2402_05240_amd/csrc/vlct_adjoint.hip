@@ -15,7 +15,7 @@
 //   faces   : flux cotangents (flux differences transposed; B_t1/B_t2 fluxes
 //             gathered from the two edges that use each, with the upwind
 //             weights of the forward fluxes), then HLLD reversed
-//   recon   : PLMC/PLMP reversed per cell and axis (corrector only)
+//   recon   : PLMC/PLMP/PPMC/PPMP reversed per cell and axis (corrector only)
 //   prims   : reference fields -(v x B) gathered from the 12 edges around the
 //             cell and reversed, then primitive recovery reversed
 // The forward intermediates (primitives, fluxes with their upwind indicators,
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_ad_faces(Geom g, Prims P, StateP st,
     if (RECON == VLCT_RECON_PCM) {
         wl = w7_at(P, D, at(-1));
         wr = w7_at(P, D, at(0));
-    } else {
+    } else if (RECON == VLCT_RECON_PLMC || RECON == VLCT_RECON_PLMP) {
         constexpr bool kChar = RECON == VLCT_RECON_PLMC;
         W7 tmp;
         plmc<kChar>(w7_at(P, D, at(-2)), w7_at(P, D, at(-1)), w7_at(P, D, at(0)),
@@ -261,6 +261,15 @@ __global__ __launch_bounds__(kBlock) void k_ad_faces(Geom g, Prims P, StateP st,
         fl = floor_state(wl);
         plmc<kChar>(w7_at(P, D, at(-1)), w7_at(P, D, at(0)), w7_at(P, D, at(1)),
                     P.w[5 + D][at(0)], g.gamma, wr, tmp);
+        fr = floor_state(wr);
+    } else {
+        constexpr bool kChar = RECON == VLCT_RECON_PPMC;
+        const W7 s0 = w7_at(P, D, at(-2)), s1 = w7_at(P, D, at(-1)), s2 = w7_at(P, D, at(0)),
+                 s3 = w7_at(P, D, at(1));
+        W7 tmp;
+        ppmc<kChar>(w7_at(P, D, at(-3)), s0, s1, s2, s3, P.w[5 + D][at(-1)], g.gamma, tmp, wl);
+        fl = floor_state(wl);
+        ppmc<kChar>(s0, s1, s2, s3, w7_at(P, D, at(2)), P.w[5 + D][at(0)], g.gamma, wr, tmp);
         fr = floor_state(wr);
     }
     const idx_t fo = face_store(g, D, x[0], x[1], x[2]);
@@ -286,41 +295,51 @@ __global__ __launch_bounds__(kBlock) void k_ad_faces(Geom g, Prims P, StateP st,
     }
 }
 
-// reconstruction of each cell along D reversed: cotangents of the three
-// stencil states and of the cell's B_cc,D
+// reconstruction of each cell along D reversed: cotangents of the stencil
+// states (three cells for PLM, five for PPM) and of the cell's B_cc,D
 template <int D, int RECON>
 __global__ __launch_bounds__(kBlock) void k_ad_recon(Geom g, Prims P, AdStage S)
 {
+    constexpr bool kPpm = RECON == VLCT_RECON_PPMC || RECON == VLCT_RECON_PPMP;
+    constexpr bool kChar = RECON == VLCT_RECON_PLMC || RECON == VLCT_RECON_PPMC;
+    constexpr int kR = kPpm ? 2 : 1;  // stencil radius
     const idx_t N = (idx_t)g.n[0] * g.n[1] * g.n[2];
     const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N) return;
     int x[3];
     cell_coords(g, t, x);
-    constexpr bool kChar = RECON == VLCT_RECON_PLMC;
     double afm[7], afp[7];
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
         afm[c] = S.lrec[D][c][t];
         afp[c] = S.lrec[D][7 + c][t];
     }
-    idx_t po[3];
+    idx_t po[2 * kR + 1];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q <= 2 * kR; ++q) {
         int e[3] = {x[0], x[1], x[2]};
-        e[D] += q - 1;
+        e[D] += q - kR;
         po[q] = pidx(g, e[0], e[1], e[2]);
     }
-    W7 am{0, 0, 0, 0, 0, 0, 0}, a0{0, 0, 0, 0, 0, 0, 0}, ap{0, 0, 0, 0, 0, 0, 0};
-    double abn = 0.0;
-    plmc_rev<kChar>(w7_at(P, D, po[0]), w7_at(P, D, po[1]), w7_at(P, D, po[2]), P.w[5 + D][po[1]],
-                    g.gamma, afm, afp, am, a0, ap, abn);
-    const W7 *outs[3] = {&am, &a0, &ap};
+    W7 ad[2 * kR + 1];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q <= 2 * kR; ++q) ad[q] = W7{0, 0, 0, 0, 0, 0, 0};
+    double abn = 0.0;
+    if (kPpm) {
+        ppmc_rev<kChar>(w7_at(P, D, po[0]), w7_at(P, D, po[1]), w7_at(P, D, po[kR]),
+                        w7_at(P, D, po[2 * kR - 1]), w7_at(P, D, po[2 * kR]),
+                        P.w[5 + D][po[kR]], g.gamma, afm, afp, ad[0], ad[1], ad[kR],
+                        ad[2 * kR - 1], ad[2 * kR], abn);
+    } else {
+        plmc_rev<kChar>(w7_at(P, D, po[0]), w7_at(P, D, po[1]), w7_at(P, D, po[2]),
+                        P.w[5 + D][po[1]], g.gamma, afm, afp, ad[0], ad[1], ad[2], abn);
+    }
+#pragma unroll
+    for (int q = 0; q <= 2 * kR; ++q) {
         int e[3] = {x[0], x[1], x[2]};
-        e[D] += q - 1;
+        e[D] += q - kR;
         const idx_t c = cell_of(g, e);
-        const W7 &v = *outs[q];
+        const W7 &v = ad[q];
         const double a[7] = {v.d, v.u, v.v, v.w, v.p, v.by, v.bz};
 #pragma unroll
         for (int s = 0; s < 7; ++s) atomicAdd(&S.lw[lab_slot(D, s)][c], a[s]);
@@ -454,9 +473,15 @@ static void stage_adjoint(const Geom &g, double factor, const StateP &lout, cons
     } else if (recon == VLCT_RECON_PLMC) {
         VLCT_AD_FACES(VLCT_RECON_PLMC)
         VLCT_AD_RECON(VLCT_RECON_PLMC)
-    } else {
+    } else if (recon == VLCT_RECON_PLMP) {
         VLCT_AD_FACES(VLCT_RECON_PLMP)
         VLCT_AD_RECON(VLCT_RECON_PLMP)
+    } else if (recon == VLCT_RECON_PPMC) {
+        VLCT_AD_FACES(VLCT_RECON_PPMC)
+        VLCT_AD_RECON(VLCT_RECON_PPMC)
+    } else {
+        VLCT_AD_FACES(VLCT_RECON_PPMP)
+        VLCT_AD_RECON(VLCT_RECON_PPMP)
     }
 #undef VLCT_AD_FACES
 #undef VLCT_AD_RECON
@@ -534,8 +559,6 @@ static int adjoint_args(const vlct_grid *vg, const vlct_state *in, const vlct_st
         return VLCT_EINVAL;
     for (int d = 0; d < 3; ++d)
         if (vg->bc[d] != VLCT_BC_PERIODIC) return VLCT_EUNSUPPORTED;
-    if (vg->recon != VLCT_RECON_PCM && vg->recon != VLCT_RECON_PLMC && vg->recon != VLCT_RECON_PLMP)
-        return VLCT_EUNSUPPORTED;
     // no array of lam_in may overlap an array of `in` or `lam_out`, nor another of lam_in
     const int n[3] = {vg->nx, vg->ny, vg->nz};
     const vlct_state *sts[3] = {lam_in, in, lam_out};

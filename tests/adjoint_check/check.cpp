@@ -122,5 +122,64 @@ int main(int argc, char **argv) {
         }
         printf("PLM%s: worst rel err %.3e, bad %d\n", chr ? "C" : "P", worst, nbad);
     }
+
+    // PPMC / PPMP over five-cell stencils: random ones (extremum and
+    // overshoot branches, the bounds), smooth ones (the unlimited parabola),
+    // stencils with repeated cells (the tie snapping) and B_n = 0
+    for (int chr = 0; chr < 2; ++chr) {
+        worst = 0; nbad = 0;
+        for (int trial = 0; trial < trials; ++trial) {
+            W7 w0 = rand_w(2.0);
+            W7 st[5];
+            const int kind = trial % 4;
+            if (kind == 1) {
+                // smooth profile: w0 + k g + k^2 h with small g, h
+                double gx[7], hx[7];
+                for (int c = 0; c < 7; ++c) { gx[c] = U(-0.05, 0.05); hx[c] = U(-0.01, 0.01); }
+                for (int k = -2; k <= 2; ++k) {
+                    double x[7]; w_arr(w0, x);
+                    for (int c = 0; c < 7; ++c) x[c] += k * gx[c] + k * k * hx[c];
+                    st[k + 2] = W7{x[0], x[1], x[2], x[3], x[4], x[5], x[6]};
+                }
+            } else {
+                const double s = kind == 2 ? 0.02 : 0.3;
+                for (int k = 0; k < 5; ++k) {
+                    W7 w = w0;
+                    w.d *= 1 + U(-s, s); w.u += U(-s, s); w.v += U(-s, s); w.w += U(-s, s);
+                    w.p *= 1 + U(-s, s); w.by += U(-s, s); w.bz += U(-s, s);
+                    st[k] = w;
+                }
+                st[2] = w0;
+                if (kind == 3) { st[0] = st[1]; st[4] = w0; }  // repeated cells
+            }
+            double bn = trial % 9 == 0 ? 0.0 : U(-2, 2);
+            if (trial % 13 == 0) { for (auto &w : st) { w.by = 0; w.bz = 0; } }
+            double afm[7], afp[7]; for (auto &v : afm) v = U(-1, 1); for (auto &v : afp) v = U(-1, 1);
+            W7 a[5]; for (auto &w : a) w = W7{0,0,0,0,0,0,0}; double abn = 0;
+            if (chr) vlct::ppmc_rev<true>(st[0], st[1], st[2], st[3], st[4], bn, gam, afm, afp, a[0], a[1], a[2], a[3], a[4], abn);
+            else vlct::ppmc_rev<false>(st[0], st[1], st[2], st[3], st[4], bn, gam, afm, afp, a[0], a[1], a[2], a[3], a[4], abn);
+            double x[36]; for (int k = 0; k < 5; ++k) w_arr(st[k], x + 7 * k); x[35] = bn;
+            double g[40];
+            for (int pass = 0; pass < 5; ++pass) {
+                D8 in[36];
+                for (int q = 0; q < 36; ++q) { in[q] = D8(x[q]); int kk = q - pass * 8; if (kk >= 0 && kk < 8) in[q].d[kk] = 1.0; }
+                P::W7 w[5];
+                for (int k = 0; k < 5; ++k) w[k] = P::W7{in[7*k],in[7*k+1],in[7*k+2],in[7*k+3],in[7*k+4],in[7*k+5],in[7*k+6]};
+                P::W7 fm, fp;
+                if (chr) P::ppmc<true>(w[0], w[1], w[2], w[3], w[4], in[35], D8(gam), fm, fp);
+                else P::ppmc<false>(w[0], w[1], w[2], w[3], w[4], in[35], D8(gam), fm, fp);
+                const D8 *o[14] = {&fm.d,&fm.u,&fm.v,&fm.w,&fm.p,&fm.by,&fm.bz,&fp.d,&fp.u,&fp.v,&fp.w,&fp.p,&fp.by,&fp.bz};
+                for (int kk = 0; kk < 8; ++kk) { double s2 = 0; for (int c2 = 0; c2 < 7; ++c2) s2 += afm[c2] * o[c2]->d[kk] + afp[c2] * o[7+c2]->d[kk]; if (pass*8+kk < 40) g[pass*8+kk] = s2; }
+            }
+            double got[36]; for (int k = 0; k < 5; ++k) w_arr(a[k], got + 7 * k); got[35] = abn;
+            double sc = 0; for (int q = 0; q < 36; ++q) sc = std::max(sc, std::fabs(g[q]));
+            for (int q = 0; q < 36; ++q) {
+                double e = std::fabs(got[q] - g[q]) / (sc + 1e-300);
+                if (e > worst) worst = e;
+                if (e > 1e-10) { if (nbad < 10) printf("ppmc%d trial %d input %d: rev %.15g dual %.15g\n", chr, trial, q, got[q], g[q]); nbad++; }
+            }
+        }
+        printf("PPM%s: worst rel err %.3e, bad %d\n", chr ? "C" : "P", worst, nbad);
+    }
     return 0;
 }

@@ -145,12 +145,9 @@ def test_adjoint_validation():
     ws = 1 << 30
     assert vlct.vlct_step_adjoint(g, a, b, c, 0, ws, need, 0) == vlct.VLCT_EINVAL
     assert vlct.vlct_step_adjoint(_grid(dx=0.0), a, b, c, 64, ws, need, 0) == vlct.VLCT_EINVAL
-    # outflow boundaries and the parabolic reconstructions are not differentiated
+    # outflow boundaries are not differentiated
     assert vlct.vlct_step_adjoint(_grid(bc=(0, 1, 0)), a, b, c, 64, ws, need,
                                   0) == vlct.VLCT_EUNSUPPORTED
-    for recon in (3, 5):
-        assert vlct.vlct_step_adjoint(_grid(recon=recon), a, b, c, 64, ws, need,
-                                      0) == vlct.VLCT_EUNSUPPORTED
     # lam_in overlapping the state, lam_out or itself
     assert vlct.vlct_step_adjoint(g, a, b, a, 64, ws, need, 0) == vlct.VLCT_EINVAL
     assert vlct.vlct_step_adjoint(g, a, b, st((2 << 20) + 8), 64, ws, need, 0) == vlct.VLCT_EINVAL

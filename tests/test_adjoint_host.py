@@ -1,5 +1,5 @@
 """The reverse derivatives of HLLD, the characteristic eigen-system and the
-PLMC / PLMP reconstructions (paper_2402_05240_amd/csrc/mhd_adjoint.hpp),
+PLMC / PLMP / PPMC / PPMP reconstructions (paper_2402_05240_amd/csrc/mhd_adjoint.hpp),
 compiled for the host, against forward-mode dual numbers pushed through the
 device physics header itself (tests/adjoint_check/check.cpp): J^T a from
 the hand-written reverse code must equal the dual-number Jacobian contracted
@@ -32,7 +32,7 @@ def test_reverse_derivatives_match_dual_numbers(tmp_path):
                    check=True, cwd=tmp_path)
     out = subprocess.run([str(exe), "20000"], check=True, capture_output=True, text=True).stdout
     print(out)
-    found = re.findall(r"(HLLD|PLMP|PLMC): worst rel err ([0-9.e+-]+), bad (\d+)", out)
-    assert {name for name, _, _ in found} == {"HLLD", "PLMP", "PLMC"}, out
+    found = re.findall(r"(HLLD|PLMP|PLMC|PPMP|PPMC): worst rel err ([0-9.e+-]+), bad (\d+)", out)
+    assert {name for name, _, _ in found} == {"HLLD", "PLMP", "PLMC", "PPMP", "PPMC"}, out
     for name, worst, bad in found:
         assert int(bad) == 0 and float(worst) <= 1e-12, (name, worst, bad)

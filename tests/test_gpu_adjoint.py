@@ -19,7 +19,7 @@ from parity_util import FIELDS, gpu_available
 
 pytestmark = pytest.mark.gpu
 
-RECONS = [I.RECON_PCM, I.RECON_PLMC, I.RECON_PLMP]
+RECONS = [I.RECON_PCM, I.RECON_PLMC, I.RECON_PLMP, I.RECON_PPMC, I.RECON_PPMP]
 # tolerances relative to sum |lam_out * d out|, the size of the compared
 # products: the central differences carry ~1e-16 / H rounding per output
 # element (a few 1e-9 for single coordinates, ~1e-11 along full directions)

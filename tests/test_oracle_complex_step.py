@@ -35,7 +35,7 @@ def test_complex_step_real_part_is_the_oracle(cso, recon):
         assert np.array_equal(out[f], r2[f]), f
 
 
-@pytest.mark.parametrize("recon", [I.RECON_PLMC, I.RECON_PCM])
+@pytest.mark.parametrize("recon", [I.RECON_PLMC, I.RECON_PCM, I.RECON_PPMC])
 def test_complex_step_matches_central_differences(cso, recon):
     g, s = I.turbulence((9, 10, 9), recon=recon)
     dt = ref.cfl_dt(g, s)
