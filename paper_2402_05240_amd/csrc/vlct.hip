@@ -419,18 +419,19 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
         }
     };
     // LDS coordinates of cell (ii, jj): [jj - j0 + 1][ii - i0 + 1]
-    // edges of the plane kk - 1/2 (E_x, E_y at edge index kk) into slot h
-    auto horizontal_edges = [&](int kk, int h) {
+    // edge q of the plane kk - 1/2 (E_x for q < NEX, else E_y, at edge index
+    // kk) into slot h
+    auto horizontal_edge = [&](int q, int kk, int h) {
         const int up = slot(kk), dn = slot(kk - 1);
-        for (int q = threadIdx.x; q < NEX; q += (TX * TY)) {
+        if (q < NEX) {
             const int a = q % TX, c = q / TX, ii = i0 + a, jj = j0 + c;
             // E_x at (ii, jj - 1/2, kk - 1/2): B = y, C = z
             if (ii < nx && jj <= ny)
                 sex[h][c][a] = edge_emf<0>(g, F, ii, jj, kk, sref[up][0][c + 1][a + 1],
                                            sref[up][0][c][a + 1], sref[dn][0][c + 1][a + 1],
                                            sref[dn][0][c][a + 1]);
-        }
-        for (int q = threadIdx.x; q < NEY; q += (TX * TY)) {
+        } else {
+            q -= NEX;
             const int a = q % (TX + 1), c = q / (TX + 1), ii = i0 + a, jj = j0 + c;
             // E_y at (ii - 1/2, jj, kk - 1/2): B = z, C = x
             if (ii <= nx && jj < ny)
@@ -439,26 +440,33 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
                                            sref[dn][1][c + 1][a]);
         }
     };
+    // two barriers per plane: (1) E_z of plane k and E_x / E_y of plane
+    // k + 1/2 as one flat loop (reads the reference EMFs of planes k, k + 1);
+    // (2) the update of plane k, then the reference EMFs of plane k + 2 into
+    // the slot of plane k, which (1) no longer reads
     int lo = 0;
     stage_ref(k0 - 1);
     stage_ref(k0);
     __syncthreads();
-    horizontal_edges(k0, lo);
+    for (int q = threadIdx.x; q < NEX + NEY; q += (TX * TY)) horizontal_edge(q, k0, lo);
+    __syncthreads();
+    stage_ref(k0 + 1);  // into the slot of plane k0 - 1, no longer read
     __syncthreads();
     bool bad = false;
     for (int k = k0; k < k1; ++k) {
-        stage_ref(k + 1);  // into the slot of plane k - 1, no longer read
-        __syncthreads();
         const int sk = slot(k);
-        for (int q = threadIdx.x; q < NEZ; q += (TX * TY)) {
-            const int a = q % (TX + 1), c = q / (TX + 1), ii = i0 + a, jj = j0 + c;
-            // E_z at (ii - 1/2, jj - 1/2, k): B = x, C = y
-            if (ii <= nx && jj <= ny)
-                sez[c][a] = edge_emf<2>(g, F, ii, jj, k, sref[sk][2][c + 1][a + 1],
-                                        sref[sk][2][c + 1][a], sref[sk][2][c][a + 1],
-                                        sref[sk][2][c][a]);
+        for (int q = threadIdx.x; q < NEZ + NEX + NEY; q += (TX * TY)) {
+            if (q < NEZ) {
+                const int a = q % (TX + 1), c = q / (TX + 1), ii = i0 + a, jj = j0 + c;
+                // E_z at (ii - 1/2, jj - 1/2, k): B = x, C = y
+                if (ii <= nx && jj <= ny)
+                    sez[c][a] = edge_emf<2>(g, F, ii, jj, k, sref[sk][2][c + 1][a + 1],
+                                            sref[sk][2][c + 1][a], sref[sk][2][c][a + 1],
+                                            sref[sk][2][c][a]);
+            } else {
+                horizontal_edge(q - NEZ, k + 1, 1 - lo);
+            }
         }
-        horizontal_edges(k + 1, 1 - lo);
         __syncthreads();
         const int hi = 1 - lo;
         if (i < ex && j < ey) {
@@ -520,6 +528,7 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
                 if (FULL) bad |= !isfinite(v);
             }
         }
+        if (k + 2 <= k1) stage_ref(k + 2);
         __syncthreads();
         lo = hi;
     }
