@@ -42,11 +42,12 @@ BYTES_PER_UNIT = {"prims": 16 * F64, "ct_update": 46 * F64, "dt": 8 * F64}
 STEP_MIN_BYTES_PER_CELL = 16 * F64
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "hbm_counters_turbulence_plmc_256.json")
 SOURCES = ("paper_2402_05240_amd/csrc/vlct.hip", "paper_2402_05240_amd/csrc/vlct_common.hpp",
-           "paper_2402_05240_amd/csrc/mhd_physics.hpp")
+           "paper_2402_05240_amd/csrc/mhd_physics.hpp", "paper_2402_05240_amd/build.py")
 
 
 def source_hash():
-    """sha256 over the kernel sources: counter figures are valid only for them."""
+    """sha256 over the kernel sources and their compiler flags: counter
+    figures are valid only for them."""
     import hashlib
     h = hashlib.sha256()
     for rel in SOURCES:

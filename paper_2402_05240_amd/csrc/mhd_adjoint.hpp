@@ -33,7 +33,7 @@ VLCT_DEV FastSq fast_sq_fwd(double d, double p, double bn, double bt1, double bt
     q.bp2 = bt1 * bt1 + bt2 * bt2;
     q.b2 = bn * bn + q.bp2;
     q.t = q.gp - q.b2;
-    q.disc = sqrt(q.t * q.t + 4.0 * q.gp * q.bp2);
+    q.disc = msqrt(q.t * q.t + 4.0 * q.gp * q.bp2);
     q.cf2 = (q.gp + q.b2 + q.disc) / (2.0 * d);
     return q;
 }
@@ -81,7 +81,7 @@ VLCT_DEV void hlld_rev(const W7 &L, const W7 &R, double bn, double gam, double g
     const double eR = R.p * gm1i + 0.5 * R.d * u2R + pbR;
     const FastSq qfL = fast_sq_fwd(L.d, L.p, bn, L.by, L.bz, gam);
     const FastSq qfR = fast_sq_fwd(R.d, R.p, bn, R.by, R.bz, gam);
-    const double cfL = sqrt(qfL.cf2), cfR = sqrt(qfR.cf2);
+    const double cfL = msqrt(qfL.cf2), cfR = msqrt(qfR.cf2);
     const bool cmaxR = takes_second_max(cfL, cfR);
     const double cmax = cmaxR ? cfR : cfL;
     const bool uminR = takes_second_min(L.u, R.u);
@@ -124,7 +124,7 @@ VLCT_DEV void hlld_rev(const W7 &L, const W7 &R, double bn, double gam, double g
         es[a] = num_e[a] * issm[a];
     }
     const double sg = bn >= 0.0 ? 1.0 : -1.0;
-    const double rL = sqrt(ds[0]), rR = sqrt(ds[1]);
+    const double rL = msqrt(ds[0]), rR = msqrt(ds[1]);
     const double isum = 1.0 / (rL + rR);
     const double nv = rL * vs[0] + rR * vs[1] + sg * (bys[1] - bys[0]);
     const double nw = rL * ws[0] + rR * ws[1] + sg * (bzs[1] - bzs[0]);
@@ -449,7 +449,7 @@ VLCT_DEV void eigen_rev(const W7 &c, double bn_in, double gam, const EigenA &A, 
                         double &a_bn_in)
 {
     // forward
-    const double bscale = sqrt(gam * c.p + bn_in * bn_in + c.by * c.by + c.bz * c.bz);
+    const double bscale = msqrt(gam * c.p + bn_in * bn_in + c.by * c.by + c.bz * c.bz);
     const bool snap_n = fabs(bn_in) <= kBperpTiny * bscale;
     const bool snap_1 = fabs(c.by) <= kBperpTiny * bscale;
     const bool snap_2 = fabs(c.bz) <= kBperpTiny * bscale;
@@ -458,15 +458,15 @@ VLCT_DEV void eigen_rev(const W7 &c, double bn_in, double gam, const EigenA &A, 
     const double bt2 = snap_2 ? 0.0 : c.bz;
     const double id = 1.0 / c.d;
     const double gp = gam * c.p;
-    const double sqd = sqrt(c.d);
+    const double sqd = msqrt(c.d);
     const double asq = gp * id;
-    const double a = sqrt(asq);
+    const double a = msqrt(asq);
     const double ia2 = c.d / gp;
     const FastSq q = fast_sq_fwd(c.d, c.p, bn, bt1, bt2, gam);
     const double cf2 = q.cf2, disc = q.disc;
     const double cs2 = asq * bn * bn * id / cf2;
-    const double cf = sqrt(cf2), cs = sqrt(cs2);
-    const double bp = sqrt(bt1 * bt1 + bt2 * bt2);
+    const double cf = msqrt(cf2), cs = msqrt(cs2);
+    const double bp = msqrt(bt1 * bt1 + bt2 * bt2);
     const bool haveperp = bp > kBperpTiny * bscale;
     const double ibp = 1.0 / bp;
     const double tdiff = gam * c.p - (bn * bn + bt1 * bt1 + bt2 * bt2);
@@ -475,8 +475,8 @@ VLCT_DEV void eigen_rev(const W7 &c, double bn_in, double gam, const EigenA &A, 
     const double qfv = (disc + tdiff) * idisc, qsv = (disc - tdiff) * idisc;
     const double af2 = fmin(fmax(qfv, 0.0), 1.0);
     const double as2 = fmin(fmax(qsv, 0.0), 1.0);
-    const double af = split ? sqrt(af2) : 1.0;
-    const double as = split ? sqrt(as2) : 0.0;
+    const double af = split ? msqrt(af2) : 1.0;
+    const double as = split ? msqrt(as2) : 0.0;
     const double s = bn >= 0.0 ? 1.0 : -1.0;
     const double isqd = 1.0 / sqd;
     const double iasq = isqd / a;
@@ -850,7 +850,7 @@ VLCT_DEV void ppmc_rev(const W7 &wmm, const W7 &wm, const W7 &w0, const W7 &wp, 
         fb = E.sqd * E.cf;
     } else {
         fv = fast_speed(w0.d, w0.p, bn, w0.by, w0.bz, gam);
-        fb = sqrt(w0.d) * fv;
+        fb = msqrt(w0.d) * fv;
     }
     const double floor_c[7] = {0.0, fv, fv, fv, 0.0, fb, fb};
     double x0[7], xn[4][7], xs[4][7];

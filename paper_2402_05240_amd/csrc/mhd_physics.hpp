@@ -17,6 +17,31 @@
 
 namespace vlct {
 
+#ifndef VLCT_HOST_COUNT
+// Square root of a finite argument >= 0 in the normal range (every use here:
+// densities, pressures, squared speeds and field magnitudes, never subnormal
+// or near overflow): the hardware reciprocal square root refined by one
+// Goldschmidt step and two Newton corrections (Markstein's iteration), within
+// an ulp of the correctly rounded root; zero maps to itself.  The library's
+// sqrt differs only by the range scaling around the same iteration, which
+// these arguments never need.
+VLCT_DEV double msqrt(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    g = fma(d, h, g);
+    return x == 0.0 ? x : g;  // rsq(0) is infinite
+}
+#else
+VLCT_DEV double msqrt(double x) { return sqrt(x); }
+#endif
+
 // Floors on derived and reconstructed rho, P (the conserved state is never changed).
 constexpr double kFloorRho = 1.0e-20;
 constexpr double kFloorP = 1.0e-20;
@@ -54,7 +79,7 @@ VLCT_DEV double fast_sq(double d, double p, double bn, double bt1, double bt2,
     const double bp2 = bt1 * bt1 + bt2 * bt2;
     const double b2 = bn * bn + bp2;
     const double t = gp - b2;
-    disc = sqrt(t * t + 4.0 * gp * bp2);
+    disc = msqrt(t * t + 4.0 * gp * bp2);
     return (gp + b2 + disc) / (2.0 * d);
 }
 
@@ -62,7 +87,7 @@ VLCT_DEV double fast_speed(double d, double p, double bn, double bt1,
                                              double bt2, double gam)
 {
     double disc;
-    return sqrt(fast_sq(d, p, bn, bt1, bt2, gam, disc));
+    return msqrt(fast_sq(d, p, bn, bt1, bt2, gam, disc));
 }
 
 // ---------------------------------------------------------------------------
@@ -81,8 +106,8 @@ VLCT_DEV void hlld(const W7 &L, const W7 &R, double bn, double gam, double gm1i,
     const double eL = L.p * gm1i + 0.5 * L.d * (L.u * L.u + L.v * L.v + L.w * L.w) + pbL;
     const double eR = R.p * gm1i + 0.5 * R.d * (R.u * R.u + R.v * R.v + R.w * R.w) + pbR;
     double discL, discR;
-    const double cfL = sqrt(fast_sq(L.d, L.p, bn, L.by, L.bz, gam, discL));
-    const double cfR = sqrt(fast_sq(R.d, R.p, bn, R.by, R.bz, gam, discR));
+    const double cfL = msqrt(fast_sq(L.d, L.p, bn, L.by, L.bz, gam, discL));
+    const double cfR = msqrt(fast_sq(R.d, R.p, bn, R.by, R.bz, gam, discR));
     const double cmax = fmax(cfL, cfR);
     const double sL = fmin(L.u, R.u) - cmax;
     const double sR = fmax(L.u, R.u) + cmax;
@@ -120,7 +145,7 @@ VLCT_DEV void hlld(const W7 &L, const W7 &R, double bn, double gam, double gm1i,
     }
     // double-star states (shared by both sides)
     const double sg = bn >= 0.0 ? 1.0 : -1.0;
-    const double rL = sqrt(ds[0]), rR = sqrt(ds[1]);
+    const double rL = msqrt(ds[0]), rR = msqrt(ds[1]);
     const double isum = 1.0 / (rL + rR);
     const double vss = (rL * vs[0] + rR * vs[1] + sg * (bys[1] - bys[0])) * isum;
     const double wss = (rL * ws[0] + rR * ws[1] + sg * (bzs[1] - bzs[0])) * isum;
@@ -198,23 +223,23 @@ VLCT_DEV void eigen_setup(const W7 &c, double bn_in, double gam, Eigen &E)
 {
     // field components below kBperpTiny of the magnetosonic scale are rounding
     // noise and are zero here, so noise cannot turn the B_perp direction
-    const double bscale = sqrt(gam * c.p + bn_in * bn_in + c.by * c.by + c.bz * c.bz);
+    const double bscale = msqrt(gam * c.p + bn_in * bn_in + c.by * c.by + c.bz * c.bz);
     const double bn = fabs(bn_in) <= kBperpTiny * bscale ? 0.0 : bn_in;
     const double bt1 = fabs(c.by) <= kBperpTiny * bscale ? 0.0 : c.by;
     const double bt2 = fabs(c.bz) <= kBperpTiny * bscale ? 0.0 : c.bz;
     const double id = 1.0 / c.d;
     const double gp = gam * c.p;
     E.d = c.d;
-    E.sqd = sqrt(c.d);
+    E.sqd = msqrt(c.d);
     E.asq = gp * id;
-    E.a = sqrt(E.asq);
+    E.a = msqrt(E.asq);
     E.ia2 = c.d / gp;
     double disc;
     const double cf2 = fast_sq(c.d, c.p, bn, bt1, bt2, gam, disc);
     const double cs2 = E.asq * bn * bn * id / cf2;
-    E.cf = sqrt(cf2);
-    E.cs = sqrt(cs2);
-    const double bp = sqrt(bt1 * bt1 + bt2 * bt2);
+    E.cf = msqrt(cf2);
+    E.cs = msqrt(cs2);
+    const double bp = msqrt(bt1 * bt1 + bt2 * bt2);
     const bool haveperp = bp > kBperpTiny * bscale;
     const double ibp = 1.0 / bp;
     E.by = haveperp ? bt1 * ibp : 0.70710678118654752440;
@@ -224,8 +249,8 @@ VLCT_DEV void eigen_setup(const W7 &c, double bn_in, double gam, Eigen &E)
     const double idisc = 0.5 / disc;
     const double af2 = fmin(fmax((disc + tdiff) * idisc, 0.0), 1.0);
     const double as2 = fmin(fmax((disc - tdiff) * idisc, 0.0), 1.0);
-    E.af = split ? sqrt(af2) : 1.0;
-    E.as = split ? sqrt(as2) : 0.0;
+    E.af = split ? msqrt(af2) : 1.0;
+    E.as = split ? msqrt(as2) : 0.0;
     E.s = bn >= 0.0 ? 1.0 : -1.0;
     const double ia2 = E.ia2;
     E.nf = 0.5 * E.af * E.cf * ia2;
@@ -401,7 +426,7 @@ VLCT_DEV void ppmc(const W7 &wmm, const W7 &wm, const W7 &w0, const W7 &wp,
         fb = E.sqd * E.cf;
     } else {
         fv = fast_speed(w0.d, w0.p, bn, w0.by, w0.bz, gam);
-        fb = sqrt(w0.d) * fv;
+        fb = msqrt(w0.d) * fv;
     }
     // magnitude floors of the tie test: c_f for velocities, sqrt(rho) c_f for B
     const double floor_c[7] = {0.0, fv, fv, fv, 0.0, fb, fb};
