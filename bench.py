@@ -35,8 +35,11 @@ F64 = 8
 # cells for the primitive kernel):
 #   prims      reads 5 cell + 3 face fields, writes 8 primitives
 #   ct_update  reads 5 cell + 3 face fields, 3 axes x 8 flux components and
-#              6 primitives (v, B_cc for -v x B), writes 5 + 3 fields
-#   dt         reads 5 cell + 3 face fields
+#              6 primitives (v, B_cc for -v x B), writes 5 + 3 fields; the
+#              full update also evaluates the CFL condition of the new state
+#              from values it already holds (no further bytes)
+#   dt         reads 5 cell + 3 face fields (the CFL kernel of vlct_cfl_dt and
+#              of in-place steps)
 BYTES_PER_UNIT = {"prims": 16 * F64, "ct_update": 46 * F64, "dt": 8 * F64}
 # a fully fused step would move the state in and out once
 STEP_MIN_BYTES_PER_CELL = 16 * F64
@@ -209,6 +212,14 @@ def rooflines(g, kern, steps, workload=None):
         avg_ms = f["total_ms"] / f["launches"]
         r = {"kernel": key, "launches_per_step": f["launches"] / steps,
              "ms_per_step": f["total_ms"] / steps, "avg_launch_ms": avg_ms}
+        if key == "dt_final":
+            # one block reducing the CT blocks' CFL maxima: launch latency
+            r.update({"bound": "latency", "achieved": None, "peak": None, "unit": None,
+                      "frac": None, "per_unit": "the maxima of the full update's blocks"})
+            r["bytes_per_step"] = 0.0
+            r["traffic"] = None
+            out[key] = r
+            continue
         if key in ("flux_recon_hlld", "flux_pcm_hlld"):
             recon = g.recon if key == "flux_recon_hlld" else 1
             # one axis' faces per launch (n faces per row of a periodic axis)

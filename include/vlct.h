@@ -252,8 +252,10 @@ int vlct_curl_potential_adjoint(const vlct_grid *g, const double *lbx, const dou
 #define VLCT_KERNEL_EDGES 3        /* reserved (edge fields are computed inside the updates) */
 #define VLCT_KERNEL_UPDATE_HALF 4  /* CT edge fields + half-step cell and face update */
 #define VLCT_KERNEL_UPDATE_FULL 5  /* CT edge fields + full-step cell and face update */
-#define VLCT_KERNEL_DT 6           /* CFL reduction (two launches) */
-#define VLCT_KERNEL_COUNT 7
+#define VLCT_KERNEL_DT 6           /* CFL reduction over a state (two launches: vlct_cfl_dt, in-place steps) */
+#define VLCT_KERNEL_DT_FINAL 7     /* last launch of a step's CFL reduction whose per-block
+                                      maxima the full update computed */
+#define VLCT_KERNEL_COUNT 8
 typedef void (*vlct_launch_observer)(void *user, int kernel, int phase, void *stream);
 int vlct_set_launch_observer(vlct_launch_observer cb, void *user);
 

@@ -332,6 +332,37 @@ __device__ __forceinline__ void march_body(const Geom &g, const StateP &s, const
 }
 
 // ---------------------------------------------------------------------------
+// CFL condition of one cell (Step 1, Eq. dt): max_l (|v_l| + c_f,l) / d_l from
+// its conserved variables and cell-centred field (face averages); floored
+// rho / P as in the primitive recovery, the floors reported in `st`
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double cell_cfl(const Geom &g, double d, double mx, double my,
+                                           double mz, double e, const double b[3], uint32_t &st)
+{
+    if (!(d >= kFloorRho)) { d = kFloorRho; st |= kStatusDensityFloor; }
+    const double id = 1.0 / d;
+    const double v[3] = {mx * id, my * id, mz * id};
+    const double ke = 0.5 * d * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    const double me = 0.5 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    double p = (g.gamma - 1.0) * (e - ke - me);
+    if (!(p >= kFloorP)) { p = kFloorP; st |= kStatusPressureFloor; }
+    double m = 0.0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const double cf = fast_speed(d, p, b[l], b[(l + 1) % 3], b[(l + 2) % 3], g.gamma);
+        m = fmax(m, (fabs(v[l]) + cf) / g.dl[l]);
+    }
+    return m;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
 // CT edge EMFs (Step 4 / Step 8; Eqs. emf-edge, emf-upwind-slope, emf-slope)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double upwind(double s, double lo, double hi)
@@ -377,11 +408,17 @@ __device__ __forceinline__ double edge_emf(const Geom &g, const Flux &F, int i, 
 // k_update, without the round trip of the edge arrays through HBM.
 // ---------------------------------------------------------------------------
 
-template <bool FULL, int TX = kTx, int TY = kTy>
+// DT (full step only): the CFL condition of the updated cells is reduced on
+// the way, one maximum per block into partial[b]; the cell-centred field
+// takes the cell's high faces recomputed from the same edge fields as the
+// threads (or blocks) that own them.
+template <bool FULL, int TX = kTx, int TY = kTy, bool DT = false>
 __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flux &F,
                                         const StateP &base, const StateW &out,
-                                        const double *dt_dev, uint32_t *status, idx_t b)
+                                        const double *dt_dev, uint32_t *status, idx_t b,
+                                        double *partial = nullptr)
 {
+    static_assert(FULL || !DT, "the CFL reduction belongs to the full step");
     __shared__ double sez[TY + 1][TX + 1];
     __shared__ double sex[2][TY + 1][TX];
     __shared__ double sey[2][TY][TX + 1];
@@ -453,6 +490,8 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
     stage_ref(k0 + 1);  // into the slot of plane k0 - 1, no longer read
     __syncthreads();
     bool bad = false;
+    double mcfl = 0.0;
+    uint32_t stcfl = 0;
     for (int k = k0; k < k1; ++k) {
         const int sk = slot(k);
         for (int q = threadIdx.x; q < NEZ + NEX + NEY; q += (TX * TY)) {
@@ -502,6 +541,30 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
                 out.u[4][c] = u4;
                 if (FULL) bad |= !isfinite(u0) || !isfinite(u1) || !isfinite(u2) || !isfinite(u3) ||
                                  !isfinite(u4);
+                if (DT) {
+                    // faces (i, j, k) low and high of the updated cell (a periodic
+                    // high face through the face map, as its owner computes it)
+                    const double bx0 = base.b[0][face_store(g, 0, i, j, k)]
+                                       - cy * (sez[ty + 1][tx] - sez[ty][tx])
+                                       + cz * (sey[hi][ty][tx] - sey[lo][ty][tx]);
+                    const double bx1 = base.b[0][face_store(g, 0, map_face(i + 1, nx, g.bc[0]), j, k)]
+                                       - cy * (sez[ty + 1][tx + 1] - sez[ty][tx + 1])
+                                       + cz * (sey[hi][ty][tx + 1] - sey[lo][ty][tx + 1]);
+                    const double by0 = base.b[1][face_store(g, 1, i, j, k)]
+                                       - cz * (sex[hi][ty][tx] - sex[lo][ty][tx])
+                                       + cx * (sez[ty][tx + 1] - sez[ty][tx]);
+                    const double by1 = base.b[1][face_store(g, 1, i, map_face(j + 1, ny, g.bc[1]), k)]
+                                       - cz * (sex[hi][ty + 1][tx] - sex[lo][ty + 1][tx])
+                                       + cx * (sez[ty + 1][tx + 1] - sez[ty + 1][tx]);
+                    const double bz0 = base.b[2][face_store(g, 2, i, j, k)]
+                                       - cx * (sey[lo][ty][tx + 1] - sey[lo][ty][tx])
+                                       + cy * (sex[lo][ty + 1][tx] - sex[lo][ty][tx]);
+                    const double bz1 = base.b[2][face_store(g, 2, i, j, map_face(k + 1, nz, g.bc[2]))]
+                                       - cx * (sey[hi][ty][tx + 1] - sey[hi][ty][tx])
+                                       + cy * (sex[hi][ty + 1][tx] - sex[hi][ty][tx]);
+                    const double bcc[3] = {0.5 * (bx0 + bx1), 0.5 * (by0 + by1), 0.5 * (bz0 + bz1)};
+                    mcfl = fmax(mcfl, cell_cfl(g, u0, u1, u2, u3, u4, bcc, stcfl));
+                }
             }
             if (j < ny) {  // face x (i-1/2, j, k)
                 const double b0 = base.b[0][face_store(g, 0, i, j, k)];
@@ -541,19 +604,24 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
         if (FULL) bad |= !isfinite(v);
     }
     if (FULL && bad && status) atomicOr(status, kStatusNonfinite);
+    if (DT) {
+        if (stcfl && status) atomicOr(status, stcfl);
+        __shared__ double red[(TX * TY) / 64];
+        const double m = wave_max(mcfl);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double r = red[0];
+            for (int q = 1; q < (TX * TY) / 64; ++q) r = fmax(r, red[q]);
+            partial[b] = r;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
 // CFL reduction (Step 1, Eq. dt): per-block maxima of max_l (|v_l| + c_f,l)/d_l,
 // then one block reduces the partials and writes dt = cfl / max.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
 __device__ __forceinline__ void dt_partial_body(const Geom &g, const StateP &s, double *partial,
                                                 uint32_t *status, idx_t b)
 {
@@ -575,20 +643,8 @@ __device__ __forceinline__ void dt_partial_body(const Geom &g, const StateP &s, 
             0.5 * (s.b[1][face_store(g, 1, i, j, k)] + s.b[1][face_store(g, 1, i, jp, k)]),
             0.5 * (s.b[2][face_store(g, 2, i, j, k)] + s.b[2][face_store(g, 2, i, j, kp)])};
         uint32_t st = 0;
-        double d = s.u[0][t];
-        if (!(d >= kFloorRho)) { d = kFloorRho; st |= kStatusDensityFloor; }
-        const double id = 1.0 / d;
-        const double v[3] = {s.u[1][t] * id, s.u[2][t] * id, s.u[3][t] * id};
-        const double ke = 0.5 * d * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-        const double me = 0.5 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
-        double p = (g.gamma - 1.0) * (s.u[4][t] - ke - me);
-        if (!(p >= kFloorP)) { p = kFloorP; st |= kStatusPressureFloor; }
+        m = cell_cfl(g, s.u[0][t], s.u[1][t], s.u[2][t], s.u[3][t], s.u[4][t], b, st);
         if (st && status) atomicOr(status, st);
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-            const double cf = fast_speed(d, p, b[l], b[(l + 1) % 3], b[(l + 2) % 3], g.gamma);
-            m = fmax(m, (fabs(v[l]) + cf) / g.dl[l]);
-        }
     }
     m = wave_max(m);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -647,12 +703,13 @@ __global__ void __launch_bounds__(kBlock) k_flux_recon_march(Geom g, StateP s, P
     march_body<D, RECON>(g, s, P, F, status, xcd_block(nblk_march(g, D)));
 }
 
-template <bool FULL>
+template <bool FULL, bool DT = false>
 __global__ void __launch_bounds__(kCt) k_ct_update(Geom g, Prims P, Flux F, StateP base,
                                                        StateW out, const double *dt_dev,
-                                                       uint32_t *status)
+                                                       uint32_t *status, double *partial)
 {
-    ct_body<FULL>(g, P, F, base, out, dt_dev, status, xcd_block(nblk_ct(g)));
+    ct_body<FULL, kTx, kTy, DT>(g, P, F, base, out, dt_dev, status, xcd_block(nblk_ct(g)),
+                                partial);
 }
 
 __global__ void __launch_bounds__(kBlock) k_dt_partial(Geom g, StateP s, double *partial,
@@ -865,9 +922,10 @@ static Layout layout(const Geom &g)
         off += 8 * align_up(L.flux_len[d] * sizeof(double));
     }
     const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
-    L.npartial = (N + kBlock - 1) / kBlock;
+    L.npartial = (N + kBlock - 1) / kBlock;  // partials of the CFL kernel
     L.partial = off;
-    off += align_up(L.npartial * sizeof(double));
+    // room also for one partial per CT block (the CFL reduction fused into the full step)
+    off += align_up(std::max<size_t>(L.npartial, (size_t)nblk_ct(g)) * sizeof(double));
     L.total = off;
     return L;
 }
@@ -965,9 +1023,27 @@ int launch_ct(const Geom &g, bool full, const Prims &P, const Flux &F, const Sta
 {
     Observe o(full ? VLCT_KERNEL_UPDATE_FULL : VLCT_KERNEL_UPDATE_HALF, s);
     if (full)
-        k_ct_update<true><<<xcd_grid(nblk_ct(g)), kCt, 0, s>>>(g, P, F, base, out, dt_dev, status);
+        k_ct_update<true><<<xcd_grid(nblk_ct(g)), kCt, 0, s>>>(g, P, F, base, out, dt_dev, status,
+                                                               nullptr);
     else
-        k_ct_update<false><<<xcd_grid(nblk_ct(g)), kCt, 0, s>>>(g, P, F, base, out, dt_dev, status);
+        k_ct_update<false><<<xcd_grid(nblk_ct(g)), kCt, 0, s>>>(g, P, F, base, out, dt_dev,
+                                                                status, nullptr);
+    return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
+}
+
+// the full step's CT update with the CFL reduction of the new state fused in
+// (one partial per CT block), then the final reduction into dt_out
+static int launch_ct_dt(const Geom &g, const Prims &P, const Flux &F, const StateP &base,
+                        const StateW &out, const double *dt_dev, uint32_t *status,
+                        double *partial, double *dt_out, hipStream_t s)
+{
+    {
+        Observe o(VLCT_KERNEL_UPDATE_FULL, s);
+        k_ct_update<true, true><<<xcd_grid(nblk_ct(g)), kCt, 0, s>>>(g, P, F, base, out, dt_dev,
+                                                                     status, partial);
+    }
+    Observe o(VLCT_KERNEL_DT_FINAL, s);
+    k_dt_final<<<1, 1024, 0, s>>>(partial, (int)nblk_ct(g), g.cfl, dt_out);
     return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
 }
 
@@ -1100,11 +1176,11 @@ int vlct_step(const vlct_grid *vg, const vlct_state *in, const vlct_state *out,
               size_t ws_bytes, void *stream)
 {
     if (!grid_ok(vg) || !state_ok(in) || !state_ok(out) || !dt_dev) return VLCT_EINVAL;
+    // out must equal in or be disjoint from it field by field
+    bool all_same = true;
     {
-        // out must equal in or be disjoint from it field by field
         const double *pi[8] = {in->rho, in->mx, in->my, in->mz, in->E, in->bx, in->by, in->bz};
         const double *po[8] = {out->rho, out->mx, out->my, out->mz, out->E, out->bx, out->by, out->bz};
-        bool all_same = true;
         for (int f = 0; f < 8; ++f) all_same &= (pi[f] == po[f]);
         if (!all_same)
             for (int f = 0; f < 8; ++f)
@@ -1125,7 +1201,13 @@ int vlct_step(const vlct_grid *vg, const vlct_state *in, const vlct_state *out,
     const StateP half = as_const(B.half);
     if (!rc) rc = launch_prims(g, half, B.P, status_dev, s);
     if (!rc) rc = launch_fluxes(g, half, B.P, B.F, vg->recon, status_dev, s);
-    if (!rc) rc = launch_ct(g, true, B.P, B.F, sin, as_mut(out), dt_dev, status_dev, s);
+    if (rc) return rc;
+    // the CFL reduction rides on the full update unless the step is in place
+    // (it reads the base field on faces that other threads update)
+    if (next_dt_dev && !all_same)
+        return launch_ct_dt(g, B.P, B.F, sin, as_mut(out), dt_dev, status_dev, B.partial,
+                            next_dt_dev, s);
+    rc = launch_ct(g, true, B.P, B.F, sin, as_mut(out), dt_dev, status_dev, s);
     if (rc) return rc;
     if (next_dt_dev) return launch_dt(g, as_const(out), B, L, next_dt_dev, status_dev, s);
     return VLCT_OK;
@@ -1143,10 +1225,11 @@ int vlct_step_taped(const vlct_grid *vg, const vlct_state *in, const vlct_state 
                     size_t ws_bytes, void *tape, size_t tape_bytes, void *stream)
 {
     if (!grid_ok(vg) || !state_ok(in) || !state_ok(out) || !dt_dev) return VLCT_EINVAL;
+    // out must equal in or be disjoint from it field by field
+    bool all_same = true;
     {
         const double *pi[8] = {in->rho, in->mx, in->my, in->mz, in->E, in->bx, in->by, in->bz};
         const double *po[8] = {out->rho, out->mx, out->my, out->mz, out->E, out->bx, out->by, out->bz};
-        bool all_same = true;
         for (int f = 0; f < 8; ++f) all_same &= (pi[f] == po[f]);
         if (!all_same)
             for (int f = 0; f < 8; ++f)
@@ -1179,7 +1262,13 @@ int vlct_step_taped(const vlct_grid *vg, const vlct_state *in, const vlct_state 
     if (!rc) rc = launch_prims(g, hc, B.P, status_dev, s);
     if (!rc) rc = launch_fluxes(g, hc, B.P, B.F, vg->recon, status_dev, s);
     if (!rc) rc = launch_pack_sides(g, B.F, side[1], s);
-    if (!rc) rc = launch_ct(g, true, B.P, B.F, sin, as_mut(out), dt_dev, status_dev, s);
+    if (rc) return rc;
+    // the CFL reduction rides on the full update unless the step is in place
+    // (it reads the base field on faces that other threads update)
+    if (next_dt_dev && !all_same)
+        return launch_ct_dt(g, B.P, B.F, sin, as_mut(out), dt_dev, status_dev, B.partial,
+                            next_dt_dev, s);
+    rc = launch_ct(g, true, B.P, B.F, sin, as_mut(out), dt_dev, status_dev, s);
     if (rc) return rc;
     if (next_dt_dev) return launch_dt(g, as_const(out), B, L, next_dt_dev, status_dev, s);
     return VLCT_OK;
@@ -1412,8 +1501,10 @@ int vlct_batch_tune(int count, const vlct_grid *grids, const vlct_state *in,
 
 const char *vlct_kernel_name(int kernel)
 {
-    static const char *names[VLCT_KERNEL_COUNT] = {"prims", "flux_pcm_hlld", "flux_recon_hlld",
-                                                   "edges", "update_half", "update_full", "dt"};
+    static const char *names[VLCT_KERNEL_COUNT] = {"prims",       "flux_pcm_hlld",
+                                                   "flux_recon_hlld", "edges",
+                                                   "update_half", "update_full",
+                                                   "dt",          "dt_final"};
     return kernel >= 0 && kernel < VLCT_KERNEL_COUNT ? names[kernel] : "?";
 }
 

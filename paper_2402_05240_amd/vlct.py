@@ -42,7 +42,8 @@ VLCT_KERNEL_EDGES = 3
 VLCT_KERNEL_UPDATE_HALF = 4
 VLCT_KERNEL_UPDATE_FULL = 5
 VLCT_KERNEL_DT = 6
-VLCT_KERNEL_COUNT = 7
+VLCT_KERNEL_DT_FINAL = 7
+VLCT_KERNEL_COUNT = 8
 
 vlct_launch_observer = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_void_p)

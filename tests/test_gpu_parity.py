@@ -239,6 +239,48 @@ def test_single_step_tight():
     _check(g, s0, gpu, orc, rel=1e-14, elem=1e-13)
 
 
+@pytest.mark.parametrize("case", ["turbulence_ragged", "blast_outflow", "riemann_y", "thin_z"])
+def test_step_next_dt_equals_the_cfl_kernel(case):
+    """An out-of-place step reduces the next dt inside its full CT update; an
+    in-place step and vlct_cfl_dt run the separate CFL kernels over the new
+    state.  All three must agree bit for bit (periodic and outflow axes, tiles
+    cut by the grid edges, an axis thinner than a tile)."""
+    _need_gpu()
+    from paper_2402_05240_amd.device import Stepper
+    import torch
+    if case == "turbulence_ragged":
+        g, s0 = I.turbulence((70, 13, 35))
+    elif case == "blast_outflow":
+        g, s0 = I.blast((37, 29, 18), b0=1.0, recon=I.RECON_PLMC)
+    elif case == "riemann_y":
+        g, s0 = I.riemann((1.0, 1.0, 0.0, 0.0, 0.0, 1.0, 0.0), (0.125, 0.1, 0.0, 0.0, 0.0, -1.0, 0.0),
+                          0.75, 2.0, n=40, axis=1, transverse=5)
+    else:
+        g, s0 = I.orszag_tang((40, 36, 3))
+    dt = ref.cfl_dt(g, s0)
+    nexts = []
+    outs = []
+    for inplace in (False, True):
+        st = Stepper(g, inplace=inplace).upload(s0)
+        st.set_dt(dt)
+        st.step()
+        torch.cuda.synchronize()
+        nexts.append(float(st.dt.item()))
+        outs.append(st.download())
+        assert st.status_bits() == 0
+    for f in FIELDS:
+        assert np.array_equal(outs[0][f], outs[1][f]), f
+    st = Stepper(g).upload(outs[0])
+    st.compute_dt()
+    torch.cuda.synchronize()
+    nexts.append(float(st.dt.item()))
+    _say("%s: next dt fused %.17g, in place %.17g, cfl kernel %.17g" % (case, *nexts))
+    assert nexts[0] == nexts[1] == nexts[2]
+    # and the oracle's CFL of the oracle's step
+    orc, next_ref, _ = ref.step(g, s0, dt)
+    assert abs(nexts[0] - next_ref) <= 1e-13 * next_ref
+
+
 def test_inplace_equals_out_of_place_and_is_deterministic():
     _need_gpu()
     g, s0 = I.turbulence((24, 24, 24))
