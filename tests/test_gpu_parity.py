@@ -281,6 +281,46 @@ def test_step_next_dt_equals_the_cfl_kernel(case):
     assert abs(nexts[0] - next_ref) <= 1e-13 * next_ref
 
 
+@pytest.mark.parametrize("case", ["turbulence_ragged_ppmc", "blast_outflow", "riemann_y"])
+def test_taped_step_writes_what_the_step_writes(case):
+    """vlct_step_taped (which also fills a tape) and vlct_step agree bit for
+    bit in state, next dt and status on grids the adjoint tests do not cover:
+    outflow axes, tiles cut by the grid edges, PPMC."""
+    _need_gpu()
+    import torch
+    from paper_2402_05240_amd import vlct
+    from paper_2402_05240_amd.device import DeviceState
+    if case == "turbulence_ragged_ppmc":
+        g, s0 = I.turbulence((70, 13, 35), recon=I.RECON_PPMC)
+    elif case == "blast_outflow":
+        g, s0 = I.blast((37, 29, 18), b0=1.0, recon=I.RECON_PLMC)
+    else:
+        g, s0 = I.riemann((1.0, 1.0, 0.0, 0.0, 0.0, 1.0, 0.0), (0.125, 0.1, 0.0, 0.0, 0.0, -1.0, 0.0),
+                          0.75, 2.0, n=40, axis=1, transverse=5)
+    cg = vlct.make_grid(g)
+    dt = torch.full((1,), ref.cfl_dt(g, s0), dtype=torch.float64, device="cuda:0")
+    nd = torch.zeros(2, dtype=torch.float64, device="cuda:0")
+    status = torch.zeros(2, dtype=torch.int32, device="cuda:0")
+    src = DeviceState(g).upload(s0)
+    outs = [DeviceState(g), DeviceState(g)]
+    ws = torch.empty(vlct.vlct_workspace_bytes(cg), dtype=torch.uint8, device="cuda:0")
+    tb = vlct.vlct_tape_bytes(cg)
+    tape = torch.empty(tb, dtype=torch.uint8, device="cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    rc = vlct.vlct_step(cg, src.c_state(), outs[0].c_state(), dt.data_ptr(), nd.data_ptr(),
+                        status.data_ptr(), ws.data_ptr(), ws.numel(), stream)
+    assert rc == 0
+    rc = vlct.vlct_step_taped(cg, src.c_state(), outs[1].c_state(), dt.data_ptr(),
+                              nd.data_ptr() + 8, status.data_ptr() + 4, ws.data_ptr(), ws.numel(),
+                              tape.data_ptr(), tb, stream)
+    assert rc == 0
+    torch.cuda.synchronize()
+    a, b = outs[0].download(), outs[1].download()
+    for f in FIELDS:
+        assert np.array_equal(a[f], b[f]), (case, f)
+    assert float(nd[0]) == float(nd[1]) and int(status[0]) == int(status[1]) == 0
+
+
 def test_inplace_equals_out_of_place_and_is_deterministic():
     _need_gpu()
     g, s0 = I.turbulence((24, 24, 24))
