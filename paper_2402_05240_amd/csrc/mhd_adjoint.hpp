@@ -680,8 +680,10 @@ VLCT_DEV void plmc_rev(const W7 &wm, const W7 &w0, const W7 &wp, double bn, doub
             av[c] = dv[c];
         }
     }
-    // limiter (the fmin order of plmc) with the slope of the value chosen
-    double kl[7], kr[7], kc[7], kv[7];
+    // limiter (the fmin order of plmc): which difference the limited slope
+    // took (0: left, 1: right, 2: centred, 3: van Leer) and its slope there
+    int pick[7];
+    double coef[7];
 #pragma unroll
     for (int m = 0; m < 7; ++m) {
         const double A2l = 2.0 * fabs(al[m]), A2r = 2.0 * fabs(ar[m]);
@@ -696,10 +698,9 @@ VLCT_DEV void plmc_rev(const W7 &wm, const W7 &w0, const W7 &wp, double bn, doub
         const double sgn = copysign(1.0, ac[m]);  // the sign copysign gives lim
         am[m] = on ? sgn * lim : 0.0;
         const double g = on ? sgn : 0.0;
-        kl[m] = (!pick_cv && !lr_r) ? g * 2.0 * abs_slope(al[m]) : 0.0;
-        kr[m] = (!pick_cv && lr_r) ? g * 2.0 * abs_slope(ar[m]) : 0.0;
-        kc[m] = (pick_cv && !cv_v) ? g * abs_slope(ac[m]) : 0.0;
-        kv[m] = (pick_cv && cv_v) ? g * abs_slope(av[m]) : 0.0;
+        pick[m] = pick_cv ? (cv_v ? 3 : 2) : (lr_r ? 1 : 0);
+        const double x = pick_cv ? (cv_v ? av[m] : ac[m]) : (lr_r ? ar[m] : al[m]);
+        coef[m] = g * (pick_cv ? 1.0 : 2.0) * abs_slope(x);
     }
     // fp = x0 + dw / 2, fm = x0 - dw / 2
     double adw[7], ax0[7];
@@ -720,10 +721,11 @@ VLCT_DEV void plmc_rev(const W7 &wm, const W7 &w0, const W7 &wp, double bn, doub
     double aal[7], aar[7], aac[7], aav[7];
 #pragma unroll
     for (int m = 0; m < 7; ++m) {
-        aal[m] = kl[m] * aam[m];
-        aar[m] = kr[m] * aam[m];
-        aac[m] = kc[m] * aam[m];
-        aav[m] = kv[m] * aam[m];
+        const double v = coef[m] * aam[m];
+        aal[m] = pick[m] == 0 ? v : 0.0;
+        aar[m] = pick[m] == 1 ? v : 0.0;
+        aac[m] = pick[m] == 2 ? v : 0.0;
+        aav[m] = pick[m] == 3 ? v : 0.0;
     }
     double adl[7] = {0, 0, 0, 0, 0, 0, 0}, adr[7] = {0, 0, 0, 0, 0, 0, 0};
     double adc[7] = {0, 0, 0, 0, 0, 0, 0}, adv[7] = {0, 0, 0, 0, 0, 0, 0};
