@@ -4,7 +4,10 @@
 // Step structure (all kernels on the caller's stream, state resident in HBM):
 //   stage(U^n, PCM)        : prims -> 3 x (HLLD fluxes) -> CT edge EMFs + half update
 //   stage(U^{n+1/2}, PLMC) : prims -> 3 x (reconstruction + HLLD)
-//                            -> CT edge EMFs + full update from U^n -> next-dt reduction
+//                            -> CT edge EMFs + full update from U^n, with the
+//                               per-block CFL maxima of the new state -> final
+//                               next-dt reduction (an in-place step reduces the
+//                               CFL condition in a kernel of its own)
 // Boundary conditions enter only through the primitive kernel, which fills a
 // ghost-padded primitive array by index mapping (wrap / clamp), and through
 // face-index mapping when the stored normal field is read.

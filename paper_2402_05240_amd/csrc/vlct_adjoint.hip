@@ -14,7 +14,9 @@
 //   edges   : edge-field cotangents from the face cotangents (curl transposed)
 //   faces   : flux cotangents (flux differences transposed; B_t1/B_t2 fluxes
 //             gathered from the two edges that use each, with the upwind
-//             weights of the forward fluxes), then HLLD reversed
+//             weights of the forward fluxes), then HLLD reversed (the y and
+//             z faces of a reconstructing stage by column marches that
+//             reconstruct each cell once)
 //   recon   : PLMC/PLMP/PPMC/PPMP reversed per cell and axis (corrector only)
 //   prims   : reference fields -(v x B) gathered from the 12 edges around the
 //             cell and reversed, then primitive recovery reversed
@@ -295,6 +297,108 @@ __global__ __launch_bounds__(kBlock) void k_ad_faces(Geom g, Prims P, StateP st,
     }
 }
 
+// faces of axis D = y or z with a reconstructing corrector, one thread per
+// column (i, j or k) and segment of kAdMarch cells along D: each cell is
+// reconstructed once and its high-face state carried to the next face, where
+// the cell-parallel kernel reconstructs both cells of every face.  Per face
+// the same work as k_ad_faces.
+constexpr int kAdMarch = 16;
+
+__host__ __device__ __forceinline__ idx_t ad_march_blocks(const Geom &g, int D)
+{
+    const int T = D == 1 ? 2 : 1;
+    const idx_t cols = (idx_t)g.n[0] * g.n[T];
+    return ((cols + kBlock - 1) / kBlock) * ((g.n[D] + kAdMarch - 1) / kAdMarch);
+}
+
+template <int D, int RECON>
+__global__ __launch_bounds__(kBlock) void k_ad_faces_march(Geom g, Prims P, StateP st,
+                                                           StateP lout, AdStage S,
+                                                           StateW lacc, const double *dt_dev,
+                                                           double factor)
+{
+    static_assert(D == 1 || D == 2, "columns march along y or z");
+    constexpr int T = D == 1 ? 2 : 1;
+    constexpr bool kPpm = RECON == VLCT_RECON_PPMC || RECON == VLCT_RECON_PPMP;
+    constexpr bool kChar = RECON == VLCT_RECON_PLMC || RECON == VLCT_RECON_PPMC;
+    constexpr int R = kPpm ? 2 : 1;
+    const int nD = g.n[D];
+    const idx_t cols = (idx_t)g.n[0] * g.n[T];
+    const idx_t ncb = (cols + kBlock - 1) / kBlock;
+    const idx_t b = blockIdx.x;
+    const int seg = (int)(b / ncb);
+    const idx_t col = (b - (idx_t)seg * ncb) * kBlock + threadIdx.x;
+    if (col >= cols) return;
+    int x[3];
+    x[0] = (int)(col % g.n[0]);
+    x[T] = (int)(col / g.n[0]);
+    const int s0 = seg * kAdMarch, s1 = min(s0 + kAdMarch, nD);  // cells [s0, s1)
+    const double c = factor * dt_dev[0] / g.dl[D];
+    auto pid = [&](int along) {
+        int q[3] = {x[0], x[1], x[2]};
+        q[D] = along;
+        return pidx(g, q[0], q[1], q[2]);
+    };
+    // stencil window of cells a - R .. a + R for a = s0 - 1
+    W7 win[2 * R + 1];
+    double bnc[2 * R + 1];
+#pragma unroll
+    for (int q = 0; q < 2 * R + 1; ++q) {
+        const idx_t o = pid(s0 - 1 - R + q);
+        win[q] = w7_at(P, D, o);
+        bnc[q] = P.w[5 + D][o];
+    }
+    W7 prev{};
+    uint32_t fprev = 0;
+    for (int a = s0 - 1; a < s1; ++a) {
+        W7 fm, fp;
+        if constexpr (kPpm)
+            ppmc<kChar>(win[0], win[1], win[2], win[3], win[4], bnc[2], g.gamma, fm, fp);
+        else
+            plmc<kChar>(win[0], win[1], win[2], bnc[1], g.gamma, fm, fp);
+        const uint32_t flo = floor_state(fm), fhi = floor_state(fp);
+        if (a >= s0) {
+            // the face a - 1/2 between the carried high state and this low state
+            x[D] = a;
+            const idx_t t = cell_of(g, x);
+            double lf[7];
+            flux_cotangent<D>(g, lout, S, x, t, c, lf);
+            const idx_t fo = face_store(g, D, x[0], x[1], x[2]);
+            W7 aL{0, 0, 0, 0, 0, 0, 0}, aR{0, 0, 0, 0, 0, 0, 0};
+            double abn = 0.0;
+            hlld_rev(prev, fm, st.b[D][fo], g.gamma, g.gm1i, lf, aL, aR, abn);
+            lacc.b[D][fo] += abn;
+            int l[3] = {x[0], x[1], x[2]};
+            l[D] -= 1;
+            const idx_t cl = cell_of(g, l);
+            const double vl[7] = {aL.d, aL.u, aL.v, aL.w, aL.p, aL.by, aL.bz};
+            const double vr[7] = {aR.d, aR.u, aR.v, aR.w, aR.p, aR.by, aR.bz};
+#pragma unroll
+            for (int q = 0; q < 7; ++q) {
+                double u = vl[q], v = vr[q];
+                if (q == 0 && (fprev & kStatusDensityFloor)) u = 0.0;
+                if (q == 4 && (fprev & kStatusPressureFloor)) u = 0.0;
+                if (q == 0 && (flo & kStatusDensityFloor)) v = 0.0;
+                if (q == 4 && (flo & kStatusPressureFloor)) v = 0.0;
+                S.lrec[D][7 + q][cl] = u;  // high face of the cell below
+                S.lrec[D][q][t] = v;       // low face of this cell
+            }
+        }
+        prev = fp;
+        fprev = fhi;
+        if (a + 1 < s1) {
+#pragma unroll
+            for (int q = 0; q < 2 * R; ++q) {
+                win[q] = win[q + 1];
+                bnc[q] = bnc[q + 1];
+            }
+            const idx_t o = pid(a + 1 + R);
+            win[2 * R] = w7_at(P, D, o);
+            bnc[2 * R] = P.w[5 + D][o];
+        }
+    }
+}
+
 // reconstruction of each cell along D reversed: cotangents of the stencil
 // states (three cells for PLM, five for PPM) and of the cell's B_cc,D
 template <int D, int RECON>
@@ -464,6 +568,12 @@ static void stage_adjoint(const Geom &g, double factor, const StateP &lout, cons
     k_ad_faces<0, R><<<gc, kBlock, 0, s>>>(g, P, st, lout, S, lacc, dt, factor);           \
     k_ad_faces<1, R><<<gc, kBlock, 0, s>>>(g, P, st, lout, S, lacc, dt, factor);           \
     k_ad_faces<2, R><<<gc, kBlock, 0, s>>>(g, P, st, lout, S, lacc, dt, factor);
+#define VLCT_AD_FACES_MARCH(R)                                                             \
+    k_ad_faces<0, R><<<gc, kBlock, 0, s>>>(g, P, st, lout, S, lacc, dt, factor);           \
+    k_ad_faces_march<1, R><<<(unsigned)ad_march_blocks(g, 1), kBlock, 0, s>>>(             \
+        g, P, st, lout, S, lacc, dt, factor);                                              \
+    k_ad_faces_march<2, R><<<(unsigned)ad_march_blocks(g, 2), kBlock, 0, s>>>(             \
+        g, P, st, lout, S, lacc, dt, factor);
 #define VLCT_AD_RECON(R)                                                                   \
     k_ad_recon<0, R><<<gc, kBlock, 0, s>>>(g, P, S);                                       \
     k_ad_recon<1, R><<<gc, kBlock, 0, s>>>(g, P, S);                                       \
@@ -471,19 +581,20 @@ static void stage_adjoint(const Geom &g, double factor, const StateP &lout, cons
     if (recon == VLCT_RECON_PCM) {
         VLCT_AD_FACES(VLCT_RECON_PCM)
     } else if (recon == VLCT_RECON_PLMC) {
-        VLCT_AD_FACES(VLCT_RECON_PLMC)
+        VLCT_AD_FACES_MARCH(VLCT_RECON_PLMC)
         VLCT_AD_RECON(VLCT_RECON_PLMC)
     } else if (recon == VLCT_RECON_PLMP) {
-        VLCT_AD_FACES(VLCT_RECON_PLMP)
+        VLCT_AD_FACES_MARCH(VLCT_RECON_PLMP)
         VLCT_AD_RECON(VLCT_RECON_PLMP)
     } else if (recon == VLCT_RECON_PPMC) {
-        VLCT_AD_FACES(VLCT_RECON_PPMC)
+        VLCT_AD_FACES_MARCH(VLCT_RECON_PPMC)
         VLCT_AD_RECON(VLCT_RECON_PPMC)
     } else {
-        VLCT_AD_FACES(VLCT_RECON_PPMP)
+        VLCT_AD_FACES_MARCH(VLCT_RECON_PPMP)
         VLCT_AD_RECON(VLCT_RECON_PPMP)
     }
 #undef VLCT_AD_FACES
+#undef VLCT_AD_FACES_MARCH
 #undef VLCT_AD_RECON
     if (recon == VLCT_RECON_PCM)
         k_ad_prims<true><<<gc, kBlock, 0, s>>>(g, st, P, S, lacc);
