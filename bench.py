@@ -256,8 +256,9 @@ def kernel_family(name):
                          ("k_pack_sides", "tape_sides"), ("k_curl", "curl")):
             if key in name:
                 if fam == "adj_faces":
-                    targs = name[name.index("<") + 1:name.index(">")].replace(" ", "").split(",")
-                    return "adj_faces_pcm" if targs[-1] == "1" else "adj_faces_recon"
+                    # k_ad_faces<D>: PCM stage; k_ad_faces_row / _march: reconstructing stage
+                    return "adj_faces_recon" if ("_row" in name or "_march" in name) \
+                        else "adj_faces_pcm"
                 return fam
         return "adj_other"
     if "k_prims" in name:

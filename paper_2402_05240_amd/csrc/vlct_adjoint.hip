@@ -228,12 +228,12 @@ __device__ __forceinline__ void flux_cotangent(const Geom &g, const StateP &lout
     }
 }
 
-// faces of axis D: flux cotangents, then HLLD reversed at the forward states.
-// PCM: the states are the cell primitives; otherwise they are the (floored)
-// reconstruction outputs of the two cells.  Either way the cotangents of the
-// face's two states are stored per cell and axis (as the high state of the
-// left cell and the low state of the right cell) for the next transpose.
-template <int D, int RECON>
+// faces of axis D of the PCM stage: flux cotangents, then HLLD reversed at
+// the forward states (the cell primitives).  The cotangents of the face's two
+// states are stored per cell and axis (as the high state of the left cell and
+// the low state of the right cell) for the next transpose.  A reconstructing
+// stage takes k_ad_faces_row (x) and k_ad_faces_march (y, z).
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_ad_faces(Geom g, Prims P, StateP st, StateP lout,
                                                      AdStage S, StateW lacc,
                                                      const double *dt_dev, double factor)
@@ -250,30 +250,8 @@ __global__ __launch_bounds__(kBlock) void k_ad_faces(Geom g, Prims P, StateP st,
         q[D] += off;
         return pidx(g, q[0], q[1], q[2]);
     };
-    W7 wl, wr;
-    uint32_t fl = 0, fr = 0;
-    if (RECON == VLCT_RECON_PCM) {
-        wl = w7_at(P, D, at(-1));
-        wr = w7_at(P, D, at(0));
-    } else if (RECON == VLCT_RECON_PLMC || RECON == VLCT_RECON_PLMP) {
-        constexpr bool kChar = RECON == VLCT_RECON_PLMC;
-        W7 tmp;
-        plmc<kChar>(w7_at(P, D, at(-2)), w7_at(P, D, at(-1)), w7_at(P, D, at(0)),
-                    P.w[5 + D][at(-1)], g.gamma, tmp, wl);
-        fl = floor_state(wl);
-        plmc<kChar>(w7_at(P, D, at(-1)), w7_at(P, D, at(0)), w7_at(P, D, at(1)),
-                    P.w[5 + D][at(0)], g.gamma, wr, tmp);
-        fr = floor_state(wr);
-    } else {
-        constexpr bool kChar = RECON == VLCT_RECON_PPMC;
-        const W7 s0 = w7_at(P, D, at(-2)), s1 = w7_at(P, D, at(-1)), s2 = w7_at(P, D, at(0)),
-                 s3 = w7_at(P, D, at(1));
-        W7 tmp;
-        ppmc<kChar>(w7_at(P, D, at(-3)), s0, s1, s2, s3, P.w[5 + D][at(-1)], g.gamma, tmp, wl);
-        fl = floor_state(wl);
-        ppmc<kChar>(s0, s1, s2, s3, w7_at(P, D, at(2)), P.w[5 + D][at(0)], g.gamma, wr, tmp);
-        fr = floor_state(wr);
-    }
+    const W7 wl = w7_at(P, D, at(-1));
+    const W7 wr = w7_at(P, D, at(0));
     const idx_t fo = face_store(g, D, x[0], x[1], x[2]);
     W7 aL{0, 0, 0, 0, 0, 0, 0}, aR{0, 0, 0, 0, 0, 0, 0};
     double abn = 0.0;
@@ -284,24 +262,17 @@ __global__ __launch_bounds__(kBlock) void k_ad_faces(Geom g, Prims P, StateP st,
     const idx_t cl = cell_of(g, l);
     const double vl[7] = {aL.d, aL.u, aL.v, aL.w, aL.p, aL.by, aL.bz};
     const double vr[7] = {aR.d, aR.u, aR.v, aR.w, aR.p, aR.by, aR.bz};
-    // a floored interface component is a constant (no floors on PCM states)
 #pragma unroll
     for (int s = 0; s < 7; ++s) {
-        double a = vl[s], b = vr[s];
-        if (s == 0 && (fl & kStatusDensityFloor)) a = 0.0;
-        if (s == 4 && (fl & kStatusPressureFloor)) a = 0.0;
-        if (s == 0 && (fr & kStatusDensityFloor)) b = 0.0;
-        if (s == 4 && (fr & kStatusPressureFloor)) b = 0.0;
-        S.lrec[D][7 + s][cl] = a;  // high face of the left cell
-        S.lrec[D][s][t] = b;       // low face of the right cell
+        S.lrec[D][7 + s][cl] = vl[s];  // high face of the left cell
+        S.lrec[D][s][t] = vr[s];       // low face of the right cell
     }
 }
 
 // faces of axis D = y or z with a reconstructing corrector, one thread per
 // column (i, j or k) and segment of kAdMarch cells along D: each cell is
-// reconstructed once and its high-face state carried to the next face, where
-// the cell-parallel kernel reconstructs both cells of every face.  Per face
-// the same work as k_ad_faces.
+// reconstructed once and its high-face state carried to the next face.  Per
+// face the same work as k_ad_faces_row.
 constexpr int kAdMarch = 16;
 
 __host__ __device__ __forceinline__ idx_t ad_march_blocks(const Geom &g, int D)
@@ -396,6 +367,84 @@ __global__ __launch_bounds__(kBlock) void k_ad_faces_march(Geom g, Prims P, Stat
             win[2 * R] = w7_at(P, D, o);
             bnc[2 * R] = P.w[5 + D][o];
         }
+    }
+}
+
+// faces of axis x with a reconstructing corrector: items (row, cell) with
+// cells -1 .. nx-1 of every row in one flat sequence; a block reconstructs
+// kBlock consecutive items once each, hands the high-face states to the right
+// neighbour through LDS, and each item with a left neighbour in its block and
+// row takes the face between them (consecutive blocks overlap by one item).
+// Per face: flux cotangents, HLLD reversed, the cotangents of the two floored
+// states stored per cell and axis (a floored component carries none).
+__host__ __device__ __forceinline__ idx_t ad_row_blocks(const Geom &g)
+{
+    const idx_t items = (idx_t)(g.n[0] + 1) * g.n[1] * g.n[2];
+    return (items - 1 + kBlock - 2) / (kBlock - 1);
+}
+
+template <int RECON>
+__global__ __launch_bounds__(kBlock) void k_ad_faces_row(Geom g, Prims P, StateP st,
+                                                         StateP lout, AdStage S, StateW lacc,
+                                                         const double *dt_dev, double factor)
+{
+    constexpr bool kPpm = RECON == VLCT_RECON_PPMC || RECON == VLCT_RECON_PPMP;
+    constexpr bool kChar = RECON == VLCT_RECON_PLMC || RECON == VLCT_RECON_PPMC;
+    __shared__ double lds[7][kBlock];
+    __shared__ uint32_t lfl[kBlock];
+    const int nx = g.n[0];
+    const idx_t per_row = nx + 1;
+    const idx_t items = per_row * g.n[1] * g.n[2];
+    const int t = threadIdx.x;
+    const idx_t q = (idx_t)blockIdx.x * (kBlock - 1) + t;
+    const bool have = q < items;
+    const idx_t row = q / per_row;
+    int x[3];
+    x[0] = (int)(q - row * per_row) - 1;
+    x[1] = (int)(row % g.n[1]);
+    x[2] = (int)(row / g.n[1]);
+    W7 fm{}, fp{};
+    uint32_t flo = 0, fhi = 0;
+    if (have) {
+        auto at = [&](int off) { return pidx(g, x[0] + off, x[1], x[2]); };
+        const double bn = P.w[5][at(0)];
+        if constexpr (kPpm)
+            ppmc<kChar>(w7_at(P, 0, at(-2)), w7_at(P, 0, at(-1)), w7_at(P, 0, at(0)),
+                        w7_at(P, 0, at(1)), w7_at(P, 0, at(2)), bn, g.gamma, fm, fp);
+        else
+            plmc<kChar>(w7_at(P, 0, at(-1)), w7_at(P, 0, at(0)), w7_at(P, 0, at(1)), bn,
+                        g.gamma, fm, fp);
+        flo = floor_state(fm);
+        fhi = floor_state(fp);
+    }
+    lds[0][t] = fp.d; lds[1][t] = fp.u; lds[2][t] = fp.v; lds[3][t] = fp.w;
+    lds[4][t] = fp.p; lds[5][t] = fp.by; lds[6][t] = fp.bz;
+    lfl[t] = fhi;
+    __syncthreads();
+    if (t < 1 || !have || x[0] < 0) return;
+    const W7 wl{lds[0][t - 1], lds[1][t - 1], lds[2][t - 1], lds[3][t - 1],
+                lds[4][t - 1], lds[5][t - 1], lds[6][t - 1]};
+    const uint32_t fl = lfl[t - 1];
+    const idx_t tc = cell_of(g, x);
+    double lf[7];
+    flux_cotangent<0>(g, lout, S, x, tc, factor * dt_dev[0] / g.dl[0], lf);
+    const idx_t fo = face_store(g, 0, x[0], x[1], x[2]);
+    W7 aL{0, 0, 0, 0, 0, 0, 0}, aR{0, 0, 0, 0, 0, 0, 0};
+    double abn = 0.0;
+    hlld_rev(wl, fm, st.b[0][fo], g.gamma, g.gm1i, lf, aL, aR, abn);
+    lacc.b[0][fo] += abn;
+    const idx_t cl = cell_of(g, x[0] - 1, x[1], x[2]);
+    const double vl[7] = {aL.d, aL.u, aL.v, aL.w, aL.p, aL.by, aL.bz};
+    const double vr[7] = {aR.d, aR.u, aR.v, aR.w, aR.p, aR.by, aR.bz};
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+        double u = vl[c], v = vr[c];
+        if (c == 0 && (fl & kStatusDensityFloor)) u = 0.0;
+        if (c == 4 && (fl & kStatusPressureFloor)) u = 0.0;
+        if (c == 0 && (flo & kStatusDensityFloor)) v = 0.0;
+        if (c == 4 && (flo & kStatusPressureFloor)) v = 0.0;
+        S.lrec[0][7 + c][cl] = u;  // high face of the left cell
+        S.lrec[0][c][tc] = v;      // low face of this cell
     }
 }
 
@@ -564,12 +613,9 @@ static void stage_adjoint(const Geom &g, double factor, const StateP &lout, cons
     const unsigned gc = nblocks((size_t)g.n[0] * g.n[1] * g.n[2]);
     if (recon != VLCT_RECON_PCM) fill(S.lw[0], lw_span, s);
     k_ad_edges<<<gc, kBlock, 0, s>>>(g, lout, sd, S, dt, factor);
-#define VLCT_AD_FACES(R)                                                                   \
-    k_ad_faces<0, R><<<gc, kBlock, 0, s>>>(g, P, st, lout, S, lacc, dt, factor);           \
-    k_ad_faces<1, R><<<gc, kBlock, 0, s>>>(g, P, st, lout, S, lacc, dt, factor);           \
-    k_ad_faces<2, R><<<gc, kBlock, 0, s>>>(g, P, st, lout, S, lacc, dt, factor);
-#define VLCT_AD_FACES_MARCH(R)                                                             \
-    k_ad_faces<0, R><<<gc, kBlock, 0, s>>>(g, P, st, lout, S, lacc, dt, factor);           \
+#define VLCT_AD_FACES(R)                                                             \
+    k_ad_faces_row<R><<<(unsigned)ad_row_blocks(g), kBlock, 0, s>>>(g, P, st, lout, S,     \
+                                                                     lacc, dt, factor);    \
     k_ad_faces_march<1, R><<<(unsigned)ad_march_blocks(g, 1), kBlock, 0, s>>>(             \
         g, P, st, lout, S, lacc, dt, factor);                                              \
     k_ad_faces_march<2, R><<<(unsigned)ad_march_blocks(g, 2), kBlock, 0, s>>>(             \
@@ -579,22 +625,23 @@ static void stage_adjoint(const Geom &g, double factor, const StateP &lout, cons
     k_ad_recon<1, R><<<gc, kBlock, 0, s>>>(g, P, S);                                       \
     k_ad_recon<2, R><<<gc, kBlock, 0, s>>>(g, P, S);
     if (recon == VLCT_RECON_PCM) {
-        VLCT_AD_FACES(VLCT_RECON_PCM)
+        k_ad_faces<0><<<gc, kBlock, 0, s>>>(g, P, st, lout, S, lacc, dt, factor);
+        k_ad_faces<1><<<gc, kBlock, 0, s>>>(g, P, st, lout, S, lacc, dt, factor);
+        k_ad_faces<2><<<gc, kBlock, 0, s>>>(g, P, st, lout, S, lacc, dt, factor);
     } else if (recon == VLCT_RECON_PLMC) {
-        VLCT_AD_FACES_MARCH(VLCT_RECON_PLMC)
+        VLCT_AD_FACES(VLCT_RECON_PLMC)
         VLCT_AD_RECON(VLCT_RECON_PLMC)
     } else if (recon == VLCT_RECON_PLMP) {
-        VLCT_AD_FACES_MARCH(VLCT_RECON_PLMP)
+        VLCT_AD_FACES(VLCT_RECON_PLMP)
         VLCT_AD_RECON(VLCT_RECON_PLMP)
     } else if (recon == VLCT_RECON_PPMC) {
-        VLCT_AD_FACES_MARCH(VLCT_RECON_PPMC)
+        VLCT_AD_FACES(VLCT_RECON_PPMC)
         VLCT_AD_RECON(VLCT_RECON_PPMC)
     } else {
-        VLCT_AD_FACES_MARCH(VLCT_RECON_PPMP)
+        VLCT_AD_FACES(VLCT_RECON_PPMP)
         VLCT_AD_RECON(VLCT_RECON_PPMP)
     }
 #undef VLCT_AD_FACES
-#undef VLCT_AD_FACES_MARCH
 #undef VLCT_AD_RECON
     if (recon == VLCT_RECON_PCM)
         k_ad_prims<true><<<gc, kBlock, 0, s>>>(g, st, P, S, lacc);
