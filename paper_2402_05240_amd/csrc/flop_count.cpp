@@ -125,15 +125,18 @@ int main()
                 double(plmc_f + hlld_f) / N, double(ppmc_f + hlld_f) / N);
     std::printf("plmp_hlld_per_face %.1f\nppmp_hlld_per_face %.1f\n",
                 double(plmp_f + hlld_f) / N, double(ppmp_f + hlld_f) / N);
-    // adjoint: a corrector face recomputes both interface states and reverses
-    // HLLD; every cell reverses its reconstruction; a predictor face reverses
-    // HLLD on the cell states
+    // adjoint: a corrector face reverses HLLD at interface states recomputed
+    // by one reconstruction per cell (row and march kernels; the first,
+    // cell-parallel version recomputed two per face); every cell reverses its
+    // reconstruction; a predictor face reverses HLLD on the cell states
     std::printf("hlld_rev_per_call %.1f\nplmc_rev_per_call %.1f\nplmp_rev_per_call %.1f\n",
                 double(hlld_r) / N, double(plmc_r) / N, double(plmp_r) / N);
-    std::printf("adj_faces_plmc_per_face %.1f\nadj_faces_pcm_per_face %.1f\n",
-                double(2 * plmc_f + hlld_r) / N, double(hlld_r) / N);
+    std::printf("adj_faces_plmc_per_face %.1f (cell-parallel: %.1f)\nadj_faces_pcm_per_face %.1f\n",
+                double(plmc_f + hlld_r) / N, double(2 * plmc_f + hlld_r) / N,
+                double(hlld_r) / N);
     std::printf("ppmc_rev_per_call %.1f\nppmp_rev_per_call %.1f\n", double(ppmc_r) / N,
                 double(ppmp_r) / N);
-    std::printf("adj_faces_ppmc_per_face %.1f\n", double(2 * ppmc_f + hlld_r) / N);
+    std::printf("adj_faces_ppmc_per_face %.1f (cell-parallel: %.1f)\n",
+                double(ppmc_f + hlld_r) / N, double(2 * ppmc_f + hlld_r) / N);
     return 0;
 }
