@@ -134,6 +134,8 @@ int main()
     std::printf("adj_faces_plmc_per_face %.1f (cell-parallel: %.1f)\nadj_faces_pcm_per_face %.1f\n",
                 double(plmc_f + hlld_r) / N, double(2 * plmc_f + hlld_r) / N,
                 double(hlld_r) / N);
+    std::printf("adj_march_fused_plmc_per_cell %.1f\n",
+                double(plmc_f + hlld_r + plmc_r) / N);
     std::printf("ppmc_rev_per_call %.1f\nppmp_rev_per_call %.1f\n", double(ppmc_r) / N,
                 double(ppmp_r) / N);
     std::printf("adj_faces_ppmc_per_face %.1f (cell-parallel: %.1f)\n",

@@ -448,6 +448,112 @@ __global__ __launch_bounds__(kBlock) void k_ad_faces_row(Geom g, Prims P, StateP
     }
 }
 
+// y and z faces of a linear-reconstruction stage with the reconstruction
+// transposed in the same march: a segment computes its faces and the one
+// above it (whose cotangent the top cell needs; its normal-field cotangent
+// stays with the segment that owns it), and as soon as a cell has the
+// cotangents of both its interface states it reverses its reconstruction.
+template <int D, int RECON>
+__global__ __launch_bounds__(kBlock) void k_ad_march_fused(Geom g, Prims P, StateP st,
+                                                           StateP lout, AdStage S,
+                                                           StateW lacc, const double *dt_dev,
+                                                           double factor)
+{
+    static_assert(D == 1 || D == 2, "columns march along y or z");
+    static_assert(RECON == VLCT_RECON_PLMC || RECON == VLCT_RECON_PLMP, "linear reconstructions");
+    constexpr int T = D == 1 ? 2 : 1;
+    constexpr bool kChar = RECON == VLCT_RECON_PLMC;
+    const int nD = g.n[D];
+    const idx_t cols = (idx_t)g.n[0] * g.n[T];
+    const idx_t ncb = (cols + kBlock - 1) / kBlock;
+    const idx_t b = blockIdx.x;
+    const int seg = (int)(b / ncb);
+    const idx_t col = (b - (idx_t)seg * ncb) * kBlock + threadIdx.x;
+    if (col >= cols) return;
+    int x[3];
+    x[0] = (int)(col % g.n[0]);
+    x[T] = (int)(col / g.n[0]);
+    const int s0 = seg * kAdMarch, s1 = min(s0 + kAdMarch, nD);  // cells [s0, s1)
+    const double c = factor * dt_dev[0] / g.dl[D];
+    auto pid = [&](int along) {
+        int q[3] = {x[0], x[1], x[2]};
+        q[D] = along;
+        return pidx(g, q[0], q[1], q[2]);
+    };
+    // window of cells a - 2 .. a + 1 for the cell a being reconstructed
+    W7 win[4];
+    double bnc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const idx_t o = pid(s0 - 3 + q);
+        win[q] = w7_at(P, D, o);
+        bnc[q] = P.w[5 + D][o];
+    }
+    W7 prev{};
+    uint32_t fprev = 0;
+    double alow[7];  // cotangent of the low-face state of the cell below the face
+    for (int a = s0 - 1; a <= s1; ++a) {
+        W7 fm, fp;
+        plmc<kChar>(win[1], win[2], win[3], bnc[2], g.gamma, fm, fp);
+        const uint32_t flo = floor_state(fm), fhi = floor_state(fp);
+        if (a >= s0) {
+            // the face a - 1/2
+            x[D] = a;
+            const idx_t t = cell_of(g, x);
+            double lf[7];
+            flux_cotangent<D>(g, lout, S, x, t, c, lf);
+            int m[3] = {x[0], x[1], x[2]};
+            m[D] = wrapc(a, nD);
+            const idx_t fo = face_store(g, D, m[0], m[1], m[2]);
+            W7 aL{0, 0, 0, 0, 0, 0, 0}, aR{0, 0, 0, 0, 0, 0, 0};
+            double abn = 0.0;
+            hlld_rev(prev, fm, st.b[D][fo], g.gamma, g.gm1i, lf, aL, aR, abn);
+            if (a < s1) lacc.b[D][fo] += abn;
+            double ahigh[7] = {aL.d, aL.u, aL.v, aL.w, aL.p, aL.by, aL.bz};
+            if (fprev & kStatusDensityFloor) ahigh[0] = 0.0;
+            if (fprev & kStatusPressureFloor) ahigh[4] = 0.0;
+            if (a - 1 >= s0) {
+                // cell a - 1 has both interface cotangents: reverse its PLM
+                W7 am{0, 0, 0, 0, 0, 0, 0}, a0{0, 0, 0, 0, 0, 0, 0}, ap{0, 0, 0, 0, 0, 0, 0};
+                double abc = 0.0;
+                plmc_rev<kChar>(win[0], win[1], win[2], bnc[1], g.gamma, alow, ahigh, am, a0,
+                                ap, abc);
+                const W7 *outs[3] = {&am, &a0, &ap};
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    int e[3] = {x[0], x[1], x[2]};
+                    e[D] = a - 2 + q;
+                    const idx_t cc = cell_of(g, e);
+                    const W7 &v = *outs[q];
+                    const double av[7] = {v.d, v.u, v.v, v.w, v.p, v.by, v.bz};
+#pragma unroll
+                    for (int k = 0; k < 7; ++k) atomicAdd(&S.lw[lab_slot(D, k)][cc], av[k]);
+                }
+                int e[3] = {x[0], x[1], x[2]};
+                e[D] = a - 1;
+                atomicAdd(&S.lw[5 + D][cell_of(g, e)], abc);
+            }
+            const double lo[7] = {aR.d, aR.u, aR.v, aR.w, aR.p, aR.by, aR.bz};
+#pragma unroll
+            for (int k = 0; k < 7; ++k) alow[k] = lo[k];
+            if (flo & kStatusDensityFloor) alow[0] = 0.0;
+            if (flo & kStatusPressureFloor) alow[4] = 0.0;
+        }
+        prev = fp;
+        fprev = fhi;
+        if (a + 1 <= s1) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                win[q] = win[q + 1];
+                bnc[q] = bnc[q + 1];
+            }
+            const idx_t o = pid(a + 2);
+            win[3] = w7_at(P, D, o);
+            bnc[3] = P.w[5 + D][o];
+        }
+    }
+}
+
 // reconstruction of each cell along D reversed: cotangents of the stencil
 // states (three cells for PLM, five for PPM) and of the cell's B_cc,D
 template <int D, int RECON>
@@ -620,6 +726,14 @@ static void stage_adjoint(const Geom &g, double factor, const StateP &lout, cons
         g, P, st, lout, S, lacc, dt, factor);                                              \
     k_ad_faces_march<2, R><<<(unsigned)ad_march_blocks(g, 2), kBlock, 0, s>>>(             \
         g, P, st, lout, S, lacc, dt, factor);
+#define VLCT_AD_FUSED(R)                                                                   \
+    k_ad_faces_row<R><<<(unsigned)ad_row_blocks(g), kBlock, 0, s>>>(g, P, st, lout, S,     \
+                                                                     lacc, dt, factor);    \
+    k_ad_recon<0, R><<<gc, kBlock, 0, s>>>(g, P, S);                                       \
+    k_ad_march_fused<1, R><<<(unsigned)ad_march_blocks(g, 1), kBlock, 0, s>>>(             \
+        g, P, st, lout, S, lacc, dt, factor);                                              \
+    k_ad_march_fused<2, R><<<(unsigned)ad_march_blocks(g, 2), kBlock, 0, s>>>(             \
+        g, P, st, lout, S, lacc, dt, factor);
 #define VLCT_AD_RECON(R)                                                                   \
     k_ad_recon<0, R><<<gc, kBlock, 0, s>>>(g, P, S);                                       \
     k_ad_recon<1, R><<<gc, kBlock, 0, s>>>(g, P, S);                                       \
@@ -629,11 +743,9 @@ static void stage_adjoint(const Geom &g, double factor, const StateP &lout, cons
         k_ad_faces<1><<<gc, kBlock, 0, s>>>(g, P, st, lout, S, lacc, dt, factor);
         k_ad_faces<2><<<gc, kBlock, 0, s>>>(g, P, st, lout, S, lacc, dt, factor);
     } else if (recon == VLCT_RECON_PLMC) {
-        VLCT_AD_FACES(VLCT_RECON_PLMC)
-        VLCT_AD_RECON(VLCT_RECON_PLMC)
+        VLCT_AD_FUSED(VLCT_RECON_PLMC)
     } else if (recon == VLCT_RECON_PLMP) {
-        VLCT_AD_FACES(VLCT_RECON_PLMP)
-        VLCT_AD_RECON(VLCT_RECON_PLMP)
+        VLCT_AD_FUSED(VLCT_RECON_PLMP)
     } else if (recon == VLCT_RECON_PPMC) {
         VLCT_AD_FACES(VLCT_RECON_PPMC)
         VLCT_AD_RECON(VLCT_RECON_PPMC)
@@ -642,6 +754,7 @@ static void stage_adjoint(const Geom &g, double factor, const StateP &lout, cons
         VLCT_AD_RECON(VLCT_RECON_PPMP)
     }
 #undef VLCT_AD_FACES
+#undef VLCT_AD_FUSED
 #undef VLCT_AD_RECON
     if (recon == VLCT_RECON_PCM)
         k_ad_prims<true><<<gc, kBlock, 0, s>>>(g, st, P, S, lacc);
