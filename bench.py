@@ -252,6 +252,7 @@ def kernel_family(name):
     """Kernel family of a device kernel name as rocprofv3 prints it."""
     if "k_ad_" in name or "k_curl" in name or "k_pack_sides" in name:
         for key, fam in (("k_ad_march_fused", "adj_march_fused"),
+                         ("k_ad_row_fused", "adj_row_fused"),
                          ("k_ad_faces", "adj_faces"), ("k_ad_recon", "adj_recon"),
                          ("k_ad_prims", "adj_prims"), ("k_ad_edges", "adj_edges"),
                          ("k_pack_sides", "tape_sides"), ("k_curl", "curl")):

@@ -554,6 +554,107 @@ __global__ __launch_bounds__(kBlock) void k_ad_march_fused(Geom g, Prims P, Stat
     }
 }
 
+// x faces of a linear-reconstruction stage with the reconstruction transposed
+// in the same kernel: items (row, cell) with cells -1 .. nx of every row in
+// one flat sequence, blocks of kBlock items overlapping by two.  Each item
+// reconstructs its cell and hands the high-face state to the right through
+// LDS; each item with a left neighbour in its block and row takes the face
+// between them and hands the left state's cotangent back; each item whose
+// faces both lie in the block and which is a cell of the grid then reverses
+// its reconstruction.  A face computed twice (the last of a block, the
+// periodic image at the end of a row) leaves its normal-field cotangent to
+// the item that owns it.
+__host__ __device__ __forceinline__ idx_t ad_row_fused_blocks(const Geom &g)
+{
+    const idx_t items = (idx_t)(g.n[0] + 2) * g.n[1] * g.n[2];
+    return (items - 1 + kBlock - 3) / (kBlock - 2);  // items 1 .. items-1 at t in [1, kBlock-2]
+}
+
+template <int RECON>
+__global__ __launch_bounds__(kBlock) void k_ad_row_fused(Geom g, Prims P, StateP st,
+                                                         StateP lout, AdStage S, StateW lacc,
+                                                         const double *dt_dev, double factor)
+{
+    static_assert(RECON == VLCT_RECON_PLMC || RECON == VLCT_RECON_PLMP, "linear reconstructions");
+    constexpr bool kChar = RECON == VLCT_RECON_PLMC;
+    __shared__ double lds[7][kBlock];
+    __shared__ uint32_t lfl[kBlock];
+    const int nx = g.n[0];
+    const idx_t per_row = nx + 2;
+    const idx_t items = per_row * g.n[1] * g.n[2];
+    const int t = threadIdx.x;
+    const idx_t q = (idx_t)blockIdx.x * (kBlock - 2) + t;
+    const bool have = q < items;
+    const idx_t row = q / per_row;
+    int x[3];
+    x[0] = (int)(q - row * per_row) - 1;
+    x[1] = (int)(row % g.n[1]);
+    x[2] = (int)(row / g.n[1]);
+    auto at = [&](int off) { return pidx(g, x[0] + off, x[1], x[2]); };
+    W7 fm{}, fp{};
+    uint32_t flo = 0, fhi = 0;
+    if (have) {
+        plmc<kChar>(w7_at(P, 0, at(-1)), w7_at(P, 0, at(0)), w7_at(P, 0, at(1)),
+                    P.w[5][at(0)], g.gamma, fm, fp);
+        flo = floor_state(fm);
+        fhi = floor_state(fp);
+    }
+    lds[0][t] = fp.d; lds[1][t] = fp.u; lds[2][t] = fp.v; lds[3][t] = fp.w;
+    lds[4][t] = fp.p; lds[5][t] = fp.by; lds[6][t] = fp.bz;
+    lfl[t] = fhi;
+    __syncthreads();
+    // the face x - 1/2 (x in 0 .. nx), between the item on the left and this one
+    const bool face = t >= 1 && have && x[0] >= 0;
+    double alow[7] = {0, 0, 0, 0, 0, 0, 0}, ahigh_left[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (face) {
+        const W7 wl{lds[0][t - 1], lds[1][t - 1], lds[2][t - 1], lds[3][t - 1],
+                    lds[4][t - 1], lds[5][t - 1], lds[6][t - 1]};
+        const uint32_t fl = lfl[t - 1];
+        const idx_t tc = cell_of(g, x);
+        double lf[7];
+        flux_cotangent<0>(g, lout, S, x, tc, factor * dt_dev[0] / g.dl[0], lf);
+        const idx_t fo = face_store(g, 0, wrapc(x[0], nx), x[1], x[2]);
+        W7 aL{0, 0, 0, 0, 0, 0, 0}, aR{0, 0, 0, 0, 0, 0, 0};
+        double abn = 0.0;
+        hlld_rev(wl, fm, st.b[0][fo], g.gamma, g.gm1i, lf, aL, aR, abn);
+        if (t <= kBlock - 2 && x[0] < nx) lacc.b[0][fo] += abn;
+        const double vl[7] = {aL.d, aL.u, aL.v, aL.w, aL.p, aL.by, aL.bz};
+        const double vr[7] = {aR.d, aR.u, aR.v, aR.w, aR.p, aR.by, aR.bz};
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            ahigh_left[c] = vl[c];
+            alow[c] = vr[c];
+        }
+        if (fl & kStatusDensityFloor) ahigh_left[0] = 0.0;
+        if (fl & kStatusPressureFloor) ahigh_left[4] = 0.0;
+        if (flo & kStatusDensityFloor) alow[0] = 0.0;
+        if (flo & kStatusPressureFloor) alow[4] = 0.0;
+    }
+    __syncthreads();
+    // hand the left state's cotangent to the item on the left
+#pragma unroll
+    for (int c = 0; c < 7; ++c) lds[c][t] = ahigh_left[c];
+    __syncthreads();
+    if (!face || t > kBlock - 2 || x[0] >= nx) return;
+    double ahigh[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) ahigh[c] = lds[c][t + 1];
+    W7 am{0, 0, 0, 0, 0, 0, 0}, a0{0, 0, 0, 0, 0, 0, 0}, ap{0, 0, 0, 0, 0, 0, 0};
+    double abc = 0.0;
+    plmc_rev<kChar>(w7_at(P, 0, at(-1)), w7_at(P, 0, at(0)), w7_at(P, 0, at(1)), P.w[5][at(0)],
+                    g.gamma, alow, ahigh, am, a0, ap, abc);
+    const W7 *outs[3] = {&am, &a0, &ap};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const idx_t cc = cell_of(g, x[0] - 1 + k, x[1], x[2]);
+        const W7 &v = *outs[k];
+        const double av[7] = {v.d, v.u, v.v, v.w, v.p, v.by, v.bz};
+#pragma unroll
+        for (int c = 0; c < 7; ++c) atomicAdd(&S.lw[lab_slot(0, c)][cc], av[c]);
+    }
+    atomicAdd(&S.lw[5][cell_of(g, x)], abc);
+}
+
 // reconstruction of each cell along D reversed: cotangents of the stencil
 // states (three cells for PLM, five for PPM) and of the cell's B_cc,D
 template <int D, int RECON>
@@ -727,9 +828,9 @@ static void stage_adjoint(const Geom &g, double factor, const StateP &lout, cons
     k_ad_faces_march<2, R><<<(unsigned)ad_march_blocks(g, 2), kBlock, 0, s>>>(             \
         g, P, st, lout, S, lacc, dt, factor);
 #define VLCT_AD_FUSED(R)                                                                   \
-    k_ad_faces_row<R><<<(unsigned)ad_row_blocks(g), kBlock, 0, s>>>(g, P, st, lout, S,     \
-                                                                     lacc, dt, factor);    \
-    k_ad_recon<0, R><<<gc, kBlock, 0, s>>>(g, P, S);                                       \
+    k_ad_row_fused<R><<<(unsigned)ad_row_fused_blocks(g), kBlock, 0, s>>>(g, P, st, lout,  \
+                                                                           S, lacc, dt,    \
+                                                                           factor);        \
     k_ad_march_fused<1, R><<<(unsigned)ad_march_blocks(g, 1), kBlock, 0, s>>>(             \
         g, P, st, lout, S, lacc, dt, factor);                                              \
     k_ad_march_fused<2, R><<<(unsigned)ad_march_blocks(g, 2), kBlock, 0, s>>>(             \
