@@ -248,3 +248,31 @@ def test_adjoint_against_complex_step_of_the_oracle(cso, recon):
             worst = max(worst, abs(float(lin[f][idx]) - want) / scale)
     _say("recon %d: worst rel err against complex step %.2e" % (recon, worst))
     assert worst <= 1e-10
+
+
+@pytest.mark.parametrize("recon", [I.RECON_PLMC, I.RECON_PLMP, I.RECON_PPMC, I.RECON_PPMP])
+def test_adjoint_complex_step_multi_segment_grid(cso, recon):
+    """A 40 x 36 x 34 grid: rows longer than one block of the x-face kernel
+    and several 16-cell segments per column of the y and z marches (the
+    segment boundaries, the face a segment computes beyond its top cell).
+    <lam_in, delta> against the complex step of the oracle along random
+    directions, within 1e-10."""
+    _need_gpu()
+    g, s = _state((40, 36, 34), recon, 7)
+    dt = ref.cfl_dt(g, s)
+    lam = _random_cotangent(g, 3)
+    lin = _gpu_vjp(g, s, lam, dt)
+    rng = np.random.default_rng(5)
+    worst = 0.0
+    for _ in range(2):
+        delta = {f: rng.standard_normal(g.field_shape(f)) for f in FIELDS}
+        I._periodic_face_copy(g, delta)
+        _, jv, st = cso.jvp(g, s, delta, [dt])
+        assert st == 0
+        want = sum(float(np.sum(lam[f] * jv[f])) for f in FIELDS)
+        scale = sum(float(np.sum(np.abs(lam[f] * jv[f]))) for f in FIELDS)
+        got = sum(float(np.sum(lin[f] * delta[f])) for f in FIELDS)
+        worst = max(worst, abs(got - want) / scale)
+    _say("recon %d, 40x36x34: worst rel err against complex step %.2e" % (recon, worst))
+    assert worst <= 1e-10
+
