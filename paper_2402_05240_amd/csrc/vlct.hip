@@ -28,7 +28,7 @@ namespace vlct {
 // ---------------------------------------------------------------------------
 constexpr int kRowFaces = kBlock - 1;
 constexpr int kMarch = 16;
-constexpr int kTx = 64, kTy = 8, kTz = 16;
+constexpr int kTx = 64, kTy = 8;  // CT column tile (z planes per block: Geom::ct_planes)
 constexpr int kCt = kTx * kTy;  // threads of a CT block: one per column of the tile
 
 // tile variants a batched step can give each instance (its plan byte: CT
@@ -67,7 +67,7 @@ __host__ __device__ __forceinline__ idx_t nblk_ct(const Geom &g, int tx = kTx, i
 {
     const int ntx = (g.n[0] + (g.bc[0] == VLCT_BC_OUTFLOW) + tx - 1) / tx;
     const int nty = (g.n[1] + (g.bc[1] == VLCT_BC_OUTFLOW) + ty - 1) / ty;
-    const int ntz = (g.n[2] + kTz - 1) / kTz;
+    const int ntz = (g.n[2] + g.ct_planes - 1) / g.ct_planes;
     return (idx_t)ntx * nty * ntz;
 }
 __host__ __device__ __forceinline__ idx_t nblk_dt(const Geom &g)
@@ -431,10 +431,11 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     // positions owned by threads: cells/faces i in [0, ex), j in [0, ey)
     const int ex = nx + (g.bc[0] == VLCT_BC_OUTFLOW), ey = ny + (g.bc[1] == VLCT_BC_OUTFLOW);
-    const int ntx = (ex + TX - 1) / TX, nty = (ey + TY - 1) / TY, ntz = (nz + kTz - 1) / kTz;
+    const int tz = g.ct_planes;
+    const int ntx = (ex + TX - 1) / TX, nty = (ey + TY - 1) / TY, ntz = (nz + tz - 1) / tz;
     if (b >= (idx_t)ntx * nty * ntz) return;
     const int bx = (int)(b % ntx), by = (int)((b / ntx) % nty), bz = (int)(b / ((idx_t)ntx * nty));
-    const int i0 = bx * TX, j0 = by * TY, k0 = bz * kTz, k1 = min(k0 + kTz, nz);
+    const int i0 = bx * TX, j0 = by * TY, k0 = bz * tz, k1 = min(k0 + tz, nz);
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int i = i0 + tx, j = j0 + ty;
     const double dt = FULL ? dt_dev[0] : 0.5 * dt_dev[0];

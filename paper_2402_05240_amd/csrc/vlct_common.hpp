@@ -39,6 +39,7 @@ struct Geom {
     double dl[3];
     double gamma, gm1i, cfl;
     int p[3];  // padded primitive dims n + 2G
+    int ct_planes;  // z planes a CT block marches through
 };
 
 __host__ __device__ __forceinline__ int map_cell(int i, int n, int bc)
@@ -137,6 +138,15 @@ inline Geom make_geom(const vlct_grid *vg)
     g.gamma = vg->gamma;
     g.gm1i = 1.0 / (vg->gamma - 1.0);
     g.cfl = vg->cfl;
+    // CT blocks march 16 planes through a column tile of 64 x 8; a grid with
+    // fewer than 1024 such blocks (4 per CU) takes 8, and one with fewer than
+    // 256 blocks of 8 planes takes 4 (measured at 64^3 .. 256^3: 16 planes from
+    // 256^3 up, 8 at 128^3 and 192^3, 4 at 64^3)
+    const long long cols = (long long)((g.n[0] + (g.bc[0] == VLCT_BC_OUTFLOW) + 63) / 64) *
+                           ((g.n[1] + (g.bc[1] == VLCT_BC_OUTFLOW) + 7) / 8);
+    g.ct_planes = 16;
+    if (cols * ((g.n[2] + 15) / 16) < 1024) g.ct_planes = 8;
+    if (g.ct_planes == 8 && cols * ((g.n[2] + 7) / 8) < 256) g.ct_planes = 4;
     return g;
 }
 
