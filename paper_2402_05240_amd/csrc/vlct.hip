@@ -700,11 +700,18 @@ __global__ void __launch_bounds__(kBlock) k_flux_recon_x(Geom g, StateP s, Prims
     recon_x_body<RECON>(g, s, P, F, status, xcd_block(nblk_row(g)));
 }
 
-template <int D, int RECON>
+template <int D, int RECON, int M = kMarch>
 __global__ void __launch_bounds__(kBlock) k_flux_recon_march(Geom g, StateP s, Prims P, Flux F,
                                                               uint32_t *status)
 {
-    march_body<D, RECON>(g, s, P, F, status, xcd_block(nblk_march(g, D)));
+    march_body<D, RECON, M>(g, s, P, F, status, xcd_block(nblk_march(g, D, M)));
+}
+
+// march segment of a single step's corrector: 16 faces, or 8 when the
+// 16-face launch would have fewer than 1024 blocks (4 per CU)
+static int march_segment(const Geom &g, int d)
+{
+    return nblk_march(g, d, kMarch) < 1024 ? 8 : kMarch;
 }
 
 template <bool FULL, bool DT = false>
@@ -1006,8 +1013,16 @@ int launch_fluxes(const Geom &g, const StateP &st, const Prims &P, const Flux &F
 #define VLCT_RECON3(R)                                                                        \
     {                                                                                         \
         { Observe o(kid, s); k_flux_recon_x<R><<<xcd_grid(nblk_row(g)), kBlock, 0, s>>>(g, st, P, F, status); } \
-        { Observe o(kid, s); k_flux_recon_march<1, R><<<xcd_grid(nblk_march(g, 1)), kBlock, 0, s>>>(g, st, P, F, status); } \
-        { Observe o(kid, s); k_flux_recon_march<2, R><<<xcd_grid(nblk_march(g, 2)), kBlock, 0, s>>>(g, st, P, F, status); } \
+        { Observe o(kid, s);                                                                  \
+          if (march_segment(g, 1) == 8)                                                        \
+              k_flux_recon_march<1, R, 8><<<xcd_grid(nblk_march(g, 1, 8)), kBlock, 0, s>>>(g, st, P, F, status); \
+          else                                                                                 \
+              k_flux_recon_march<1, R><<<xcd_grid(nblk_march(g, 1)), kBlock, 0, s>>>(g, st, P, F, status); } \
+        { Observe o(kid, s);                                                                  \
+          if (march_segment(g, 2) == 8)                                                        \
+              k_flux_recon_march<2, R, 8><<<xcd_grid(nblk_march(g, 2, 8)), kBlock, 0, s>>>(g, st, P, F, status); \
+          else                                                                                 \
+              k_flux_recon_march<2, R><<<xcd_grid(nblk_march(g, 2)), kBlock, 0, s>>>(g, st, P, F, status); } \
     }
         switch (recon) {
         case VLCT_RECON_PLMC: VLCT_RECON3(VLCT_RECON_PLMC) break;
