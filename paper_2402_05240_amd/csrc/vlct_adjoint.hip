@@ -275,11 +275,20 @@ __global__ __launch_bounds__(kBlock) void k_ad_faces(Geom g, Prims P, StateP st,
 // face the same work as k_ad_faces_row.
 constexpr int kAdMarch = 16;
 
-__host__ __device__ __forceinline__ idx_t ad_march_blocks(const Geom &g, int D)
+__host__ __device__ __forceinline__ idx_t ad_march_blocks(const Geom &g, int D,
+                                                          int m = kAdMarch)
 {
     const int T = D == 1 ? 2 : 1;
     const idx_t cols = (idx_t)g.n[0] * g.n[T];
-    return ((cols + kBlock - 1) / kBlock) * ((g.n[D] + kAdMarch - 1) / kAdMarch);
+    return ((cols + kBlock - 1) / kBlock) * ((g.n[D] + m - 1) / m);
+}
+
+// segment of the fused adjoint marches: 16 cells, or 8 on a grid whose
+// 16-cell launch would have fewer than 256 blocks (64^3 adjoint 0.93 -> 0.74
+// ms; 128^3, 512 blocks, is faster with 16)
+static int ad_march_segment(const Geom &g, int D)
+{
+    return ad_march_blocks(g, D, kAdMarch) < 256 ? 8 : kAdMarch;
 }
 
 template <int D, int RECON>
@@ -453,7 +462,7 @@ __global__ __launch_bounds__(kBlock) void k_ad_faces_row(Geom g, Prims P, StateP
 // above it (whose cotangent the top cell needs; its normal-field cotangent
 // stays with the segment that owns it), and as soon as a cell has the
 // cotangents of both its interface states it reverses its reconstruction.
-template <int D, int RECON>
+template <int D, int RECON, int M = kAdMarch>
 __global__ __launch_bounds__(kBlock) void k_ad_march_fused(Geom g, Prims P, StateP st,
                                                            StateP lout, AdStage S,
                                                            StateW lacc, const double *dt_dev,
@@ -473,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_ad_march_fused(Geom g, Prims P, Stat
     int x[3];
     x[0] = (int)(col % g.n[0]);
     x[T] = (int)(col / g.n[0]);
-    const int s0 = seg * kAdMarch, s1 = min(s0 + kAdMarch, nD);  // cells [s0, s1)
+    const int s0 = seg * M, s1 = min(s0 + M, nD);  // cells [s0, s1)
     const double c = factor * dt_dev[0] / g.dl[D];
     auto pid = [&](int along) {
         int q[3] = {x[0], x[1], x[2]};
@@ -831,10 +840,18 @@ static void stage_adjoint(const Geom &g, double factor, const StateP &lout, cons
     k_ad_row_fused<R><<<(unsigned)ad_row_fused_blocks(g), kBlock, 0, s>>>(g, P, st, lout,  \
                                                                            S, lacc, dt,    \
                                                                            factor);        \
-    k_ad_march_fused<1, R><<<(unsigned)ad_march_blocks(g, 1), kBlock, 0, s>>>(             \
-        g, P, st, lout, S, lacc, dt, factor);                                              \
-    k_ad_march_fused<2, R><<<(unsigned)ad_march_blocks(g, 2), kBlock, 0, s>>>(             \
-        g, P, st, lout, S, lacc, dt, factor);
+    if (ad_march_segment(g, 1) == 8)                                                       \
+        k_ad_march_fused<1, R, 8><<<(unsigned)ad_march_blocks(g, 1, 8), kBlock, 0, s>>>(   \
+            g, P, st, lout, S, lacc, dt, factor);                                          \
+    else                                                                                   \
+        k_ad_march_fused<1, R><<<(unsigned)ad_march_blocks(g, 1), kBlock, 0, s>>>(         \
+            g, P, st, lout, S, lacc, dt, factor);                                          \
+    if (ad_march_segment(g, 2) == 8)                                                       \
+        k_ad_march_fused<2, R, 8><<<(unsigned)ad_march_blocks(g, 2, 8), kBlock, 0, s>>>(   \
+            g, P, st, lout, S, lacc, dt, factor);                                          \
+    else                                                                                   \
+        k_ad_march_fused<2, R><<<(unsigned)ad_march_blocks(g, 2), kBlock, 0, s>>>(         \
+            g, P, st, lout, S, lacc, dt, factor);
 #define VLCT_AD_RECON(R)                                                                   \
     k_ad_recon<0, R><<<gc, kBlock, 0, s>>>(g, P, S);                                       \
     k_ad_recon<1, R><<<gc, kBlock, 0, s>>>(g, P, S);                                       \
