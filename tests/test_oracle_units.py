@@ -288,6 +288,64 @@ def test_hlld_transverse_rotation_covariance():
         assert np.abs(g - fr).max() <= 1e-12 * (np.abs(f).max() + 1.0)
 
 
+def _rotational_discontinuity(rho, p, bn, bt, phi_l, phi_r, v0, lab_speed, left_wave):
+    """An isolated rotational (Alfven) discontinuity of the ideal-MHD system
+    (Sec. 2.1): rho, P, u_n and |B_t| equal on both sides, B_t turned from
+    angle phi_l to phi_r.  In the wave's rest frame u_n = +-|B_n|/sqrt(rho) and
+    v_t = v0 + sign(u_n B_n) B_t / sqrt(rho) on each side, which makes every
+    component of the flux continuous (the jump conditions of the Alfven
+    family); the frame then moves along n so the wave travels at lab_speed.
+    left_wave: the u - c_A family (else u + c_A)."""
+    ca = abs(bn) / math.sqrt(rho)
+    un_rest = ca if left_wave else -ca
+    su = 1.0 if un_rest * bn > 0 else -1.0
+
+    def side(phi):
+        bt1, bt2 = bt * math.cos(phi), bt * math.sin(phi)
+        v1 = v0[0] + su * bt1 / math.sqrt(rho)
+        v2 = v0[1] + su * bt2 / math.sqrt(rho)
+        return np.array([rho, un_rest + lab_speed, v1, v2, p, bt1, bt2])
+    return side(phi_l), side(phi_r), ca
+
+
+@pytest.mark.parametrize("left_wave", [True, False])
+def test_hlld_resolves_isolated_rotational_discontinuity(left_wave):
+    """Miyoshi & Kusano's solver (Sec. 2.2 Step 3) resolves an isolated
+    rotational discontinuity exactly: the discontinuity moves at
+    S*_L = S_M - |B_n|/sqrt(rho*_L) (or S*_R = S_M + |B_n|/sqrt(rho*_R)), the
+    double-star state equals the far state, and the flux at x/t = 0 is the
+    physical flux of the side x/t = 0 lies on.  The wave moves at 0.3 c_A
+    away from the contact's side, so the flux is F*_L + S*_L (U**_L - U*_L)
+    (or its mirror) and every term of the double-star states -- both
+    sign(B_n) terms of v**, B** and the sign(B_n) correction of E** -- enters
+    it with weight S*; a flipped sign there changes the flux at O(1).
+    Checked against the Rankine-Hugoniot form F(W_far) exactly as well."""
+    rng = np.random.default_rng(31)
+    for _ in range(200):
+        rho = rng.uniform(0.3, 3.0)
+        p = rng.uniform(0.1, 2.0)
+        bn = rng.choice([-1.0, 1.0]) * rng.uniform(0.3, 2.0)
+        bt = rng.uniform(0.2, 2.0)
+        phi_l = rng.uniform(0, 2 * np.pi)
+        phi_r = phi_l + rng.uniform(0.3, np.pi)
+        v0 = rng.uniform(-1.0, 1.0, 2)
+        lab = (-0.3 if left_wave else 0.3) * abs(bn) / math.sqrt(rho)
+        Wl, Wr, ca = _rotational_discontinuity(rho, p, bn, bt, phi_l, phi_r, v0, lab, left_wave)
+        f = ref.hlld(Wl, Wr, bn, GAM)
+        # x/t = 0 lies behind a left-moving left wave (on its right side) and
+        # ahead of a right-moving right wave (on its left side)
+        far = Wr if left_wave else Wl
+        fe = ref.phys_flux(far, bn, GAM)
+        # Rankine-Hugoniot: the jump of F is the wave speed times the jump of U
+        Ul, Ur = _cons_from_prim(Wl, bn), _cons_from_prim(Wr, bn)
+        Fl, Fr = ref.phys_flux(Wl, bn, GAM), ref.phys_flux(Wr, bn, GAM)
+        assert np.abs((Fr - Fl) - lab * (Ur - Ul)).max() <= 1e-13 * (np.abs(Fl).max() + 1.0)
+        scale = np.abs(fe).max() + np.abs(Ur - Ul).max() * ca
+        assert np.abs(f - fe).max() <= 1e-13 * scale, (f, fe)
+        # the contact speed S_M selects the fan on the side the wave is in
+        assert (Wl[1] > 0) == left_wave
+
+
 def test_hlld_riemann_table_states_are_physical():
     """Every left/right pair of the paper's Riemann table gives a finite flux
     that equals the physical flux of either state when both are equal."""
