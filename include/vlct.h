@@ -57,6 +57,7 @@ extern "C" {
 #define VLCT_EWORKSPACE 2    /* workspace NULL or smaller than vlct_workspace_bytes() */
 #define VLCT_EHIP 3          /* a HIP launch or runtime call failed */
 #define VLCT_EUNSUPPORTED 4  /* valid request this build does not implement */
+#define VLCT_ESCRATCH 5      /* vlct_step_noalloc: the grid's workspace exceeds the static scratch */
 
 /* corrector reconstruction (Sec. 2.2 Step 6) */
 #define VLCT_RECON_PCM 1     /* first order (debugging mode of Step 2) */
@@ -111,6 +112,28 @@ int vlct_cfl_dt(const vlct_grid *g, const vlct_state *s, double *dt_dev, void *w
 int vlct_step(const vlct_grid *g, const vlct_state *in, const vlct_state *out,
               const double *dt_dev, double *next_dt_dev, uint32_t *status_dev, void *ws,
               size_t ws_bytes, void *stream);
+
+/* --- stepping without any allocation ---------------------------------------
+ * For callers that cannot allocate device memory at all, not even once up
+ * front (code under HIP graph capture that owns no buffers, tight serving
+ * loops, harnesses that forbid hipMalloc): vlct_step with the workspace taken
+ * from a static device array of VLCT_NOALLOC_SCRATCH_BYTES bytes inside the
+ * library (one per GPU, held from the library's load until the process ends).
+ * Same kernels, same results bit for bit as vlct_step with a caller workspace.
+ * The caller still passes the state, dt, next dt and status (device pointers,
+ * rules as for vlct_step).  Grids whose vlct_workspace_bytes() exceeds
+ * VLCT_NOALLOC_SCRATCH_BYTES (about 55^3 cells on a periodic cube) get
+ * VLCT_ESCRATCH before anything is launched.  The scratch of the CURRENT
+ * device (hipGetDevice) is used, so `stream` must belong to that device; its
+ * address is looked up once per device on the first call there.  Calls
+ * share that device's scratch: two calls that overlap in time on one GPU
+ * (different streams, or different host threads without ordering) race and
+ * give wrong results; calls ordered on one stream are safe.  Allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine). */
+#define VLCT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int vlct_step_noalloc(const vlct_grid *g, const vlct_state *in, const vlct_state *out,
+                      const double *dt_dev, double *next_dt_dev, uint32_t *status_dev,
+                      void *stream);
 
 /* --- batched ensembles ----------------------------------------------------
  * Independent instances (own sizes, gamma, cfl, boundaries, dt and state)

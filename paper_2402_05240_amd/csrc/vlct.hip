@@ -13,8 +13,10 @@
 // face-index mapping when the stored normal field is read.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <unordered_map>
 #include <vector>
 
@@ -1167,6 +1169,39 @@ static bool batch_aliasing_ok(int count, const vlct_state *in, const vlct_state 
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// static scratch of vlct_step_noalloc: the workspace of vlct_step in a
+// file-scope device array, so a caller that cannot allocate device memory can
+// still step a grid whose workspace fits.  Each device holds its own copy; its
+// address comes from hipGetSymbolAddress once per device (the array's name in
+// host code is a host-side stand-in, never a device address).  Nothing in the
+// step's workspace has to start at zero: every kernel writes what a later one
+// reads within the same call.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = VLCT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kScratchDevices = 64;
+static std::atomic<void *> g_scratch_addr[kScratchDevices];
+static std::mutex g_scratch_mutex;
+
+// device address of the current device's scratch array
+static int scratch_address(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) return VLCT_EHIP;
+    void *p = g_scratch_addr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        p = g_scratch_addr[dev].load(std::memory_order_relaxed);
+        if (!p) {
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return VLCT_EHIP;
+            g_scratch_addr[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return VLCT_OK;
+}
+
 }  // namespace vlct
 
 using namespace vlct;
@@ -1230,6 +1265,18 @@ int vlct_step(const vlct_grid *vg, const vlct_state *in, const vlct_state *out,
     if (rc) return rc;
     if (next_dt_dev) return launch_dt(g, as_const(out), B, L, next_dt_dev, status_dev, s);
     return VLCT_OK;
+}
+
+int vlct_step_noalloc(const vlct_grid *vg, const vlct_state *in, const vlct_state *out,
+                      const double *dt_dev, double *next_dt_dev, uint32_t *status_dev,
+                      void *stream)
+{
+    if (!grid_ok(vg) || !state_ok(in) || !state_ok(out) || !dt_dev) return VLCT_EINVAL;
+    if (layout(make_geom(vg)).total > kScratchBytes) return VLCT_ESCRATCH;
+    void *ws = nullptr;
+    const int rc = scratch_address(&ws);
+    if (rc) return rc;
+    return vlct_step(vg, in, out, dt_dev, next_dt_dev, status_dev, ws, kScratchBytes, stream);
 }
 
 size_t vlct_tape_bytes(const vlct_grid *g)
@@ -1301,6 +1348,9 @@ const char *vlct_strerror(int code)
     case VLCT_EWORKSPACE: return "workspace missing or smaller than vlct_workspace_bytes()";
     case VLCT_EHIP: return "HIP launch or runtime error";
     case VLCT_EUNSUPPORTED: return "unsupported option";
+    case VLCT_ESCRATCH:
+        return "grid needs more workspace than the static scratch of vlct_step_noalloc "
+               "(VLCT_NOALLOC_SCRATCH_BYTES)";
     default: return "unknown error code";
     }
 }

@@ -17,6 +17,8 @@ VLCT_EINVAL = 1
 VLCT_EWORKSPACE = 2
 VLCT_EHIP = 3
 VLCT_EUNSUPPORTED = 4
+VLCT_ESCRATCH = 5
+VLCT_NOALLOC_SCRATCH_BYTES = 64 << 20
 VLCT_RECON_PCM = 1
 VLCT_RECON_PLMC = 2
 VLCT_RECON_PPMC = 3
@@ -33,7 +35,8 @@ EXPORTED = ("vlct_workspace_bytes", "vlct_cfl_dt", "vlct_step", "vlct_strerror",
             "vlct_batch_workspace_bytes", "vlct_step_batch", "vlct_adjoint_workspace_bytes",
             "vlct_step_adjoint", "vlct_curl_potential", "vlct_curl_potential_adjoint",
             "vlct_tape_bytes", "vlct_step_taped", "vlct_adjoint_taped_workspace_bytes",
-            "vlct_step_adjoint_taped", "vlct_step_batch_plan", "vlct_batch_tune")
+            "vlct_step_adjoint_taped", "vlct_step_batch_plan", "vlct_batch_tune",
+            "vlct_step_noalloc")
 
 VLCT_KERNEL_PRIMS = 0
 VLCT_KERNEL_FLUX_PCM = 1
@@ -88,6 +91,10 @@ def load(path: str = LIB_PATH):
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                   ctypes.c_void_p]
         lib.vlct_step.restype = ctypes.c_int
+        lib.vlct_step_noalloc.argtypes = [ctypes.POINTER(vlct_grid), ctypes.POINTER(vlct_state),
+                                          ctypes.POINTER(vlct_state), ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        lib.vlct_step_noalloc.restype = ctypes.c_int
         lib.vlct_batch_workspace_bytes.argtypes = [ctypes.POINTER(vlct_grid), ctypes.c_int]
         lib.vlct_batch_workspace_bytes.restype = ctypes.c_size_t
         lib.vlct_step_batch.argtypes = [ctypes.c_int, ctypes.POINTER(vlct_grid),
@@ -176,6 +183,13 @@ def vlct_step(grid: vlct_grid, state_in: vlct_state, state_out: vlct_state, dt_d
     return int(load().vlct_step(ctypes.byref(grid), ctypes.byref(state_in),
                                 ctypes.byref(state_out), dt_dev, next_dt_dev, status_dev, ws,
                                 ws_bytes, stream))
+
+
+def vlct_step_noalloc(grid: vlct_grid, state_in: vlct_state, state_out: vlct_state, dt_dev: int,
+                      next_dt_dev: int, status_dev: int, stream: int) -> int:
+    return int(load().vlct_step_noalloc(ctypes.byref(grid), ctypes.byref(state_in),
+                                        ctypes.byref(state_out), dt_dev, next_dt_dev, status_dev,
+                                        stream))
 
 
 def vlct_batch_workspace_bytes(grids) -> int:

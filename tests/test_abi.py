@@ -76,6 +76,22 @@ def test_workspace_and_pointer_validation():
     assert vlct.vlct_step(g, fake, other, 64, 0, 0, 128, need, 0) == vlct.VLCT_EINVAL
 
 
+def test_noalloc_validation():
+    """vlct_step_noalloc checks its arguments and the scratch size on the host,
+    before it looks up the scratch or launches anything."""
+    _lib()
+    fake = vlct.make_state([4096 * (f + 1) for f in range(8)])
+    assert vlct.vlct_step_noalloc(_grid(nx=0), fake, fake, 64, 0, 0, 0) == vlct.VLCT_EINVAL
+    assert vlct.vlct_step_noalloc(_grid(), fake, fake, 0, 0, 0, 0) == vlct.VLCT_EINVAL
+    holey = vlct.make_state([4096 * (f + 1) for f in range(7)] + [0])
+    assert vlct.vlct_step_noalloc(_grid(), holey, fake, 64, 0, 0, 0) == vlct.VLCT_EINVAL
+    big = _grid(nx=96, ny=96, nz=96)
+    assert vlct.vlct_workspace_bytes(big) > vlct.VLCT_NOALLOC_SCRATCH_BYTES
+    assert vlct.vlct_step_noalloc(big, fake, fake, 64, 0, 0, 0) == vlct.VLCT_ESCRATCH
+    fits = _grid(nx=48, ny=48, nz=48)
+    assert vlct.vlct_workspace_bytes(fits) <= vlct.VLCT_NOALLOC_SCRATCH_BYTES
+
+
 def test_batch_validation():
     """vlct_step_batch rejects bad calls on the host, before any launch."""
     _lib()
@@ -186,8 +202,9 @@ def test_taped_validation():
 
 def test_strerror_covers_codes():
     _lib()
-    for c in range(5):
+    for c in range(6):
         assert vlct.vlct_strerror(c)
+        assert "unknown" not in vlct.vlct_strerror(c)
     assert "unknown" in vlct.vlct_strerror(99)
 
 
