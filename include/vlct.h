@@ -104,7 +104,8 @@ int vlct_cfl_dt(const vlct_grid *g, const vlct_state *s, double *dt_dev, void *w
 
 /* One VL+CT step of size *dt_dev from `in` to `out` (Sec. 2.2 Steps 2-9).
  * `out` may alias `in` (all eight pointers equal) or be disjoint from it;
- * partial overlap is not allowed.  next_dt_dev (nullable) receives the CFL
+ * any other overlap of an output array with an input array, or of two
+ * output arrays, as address ranges of the field sizes above, is VLCT_EINVAL.  next_dt_dev (nullable) receives the CFL
  * step of the result; status_dev (nullable) accumulates VLCT_STATUS_* bits and
  * is never cleared by the library.  dt is read on the device, so a chain of
  * steps needs no host round trip: pass the previous call's next_dt_dev as the
@@ -262,13 +263,13 @@ int vlct_curl_potential_adjoint(const vlct_grid *g, const double *lbx, const dou
                                 void *stream);
 
 /* --- diagnostics ----------------------------------------------------------
- * Launch observer: when set, every vlct_step / vlct_cfl_dt call invokes
- * cb(user, kernel, phase, stream) on the calling host thread immediately
- * before (phase 0) and after (phase 1) it enqueues each kernel, with the
- * stream the kernel goes to, so a profiler can bracket one kernel family with
- * events on that stream.  `kernel` is a VLCT_KERNEL_* id.  NULL removes the
- * observer.  The observer is process-wide; set it while no other thread is
- * inside the library.  Returns VLCT_OK. */
+ * vlct_step_observed is vlct_step (same arguments, rules, kernels and results)
+ * that invokes cb(user, kernel, phase, stream) on the calling host thread
+ * immediately before (phase 0) and after (phase 1) it enqueues each kernel,
+ * with the stream the kernel goes to, so a profiler can bracket one kernel
+ * family with events on that stream.  `kernel` is a VLCT_KERNEL_* id.  The
+ * observer belongs to this call alone: no state outlives it or is visible to
+ * other threads.  cb must not be NULL (VLCT_EINVAL). */
 #define VLCT_KERNEL_PRIMS 0        /* primitive variables (both stages) */
 #define VLCT_KERNEL_FLUX_PCM 1     /* predictor: PCM states + HLLD, one launch per axis */
 #define VLCT_KERNEL_FLUX_RECON 2   /* corrector: PLMC/PPMC states + HLLD, one launch per axis */
@@ -278,9 +279,13 @@ int vlct_curl_potential_adjoint(const vlct_grid *g, const double *lbx, const dou
 #define VLCT_KERNEL_DT 6           /* CFL reduction over a state (two launches: vlct_cfl_dt, in-place steps) */
 #define VLCT_KERNEL_DT_FINAL 7     /* last launch of a step's CFL reduction whose per-block
                                       maxima the full update computed */
-#define VLCT_KERNEL_COUNT 8
+#define VLCT_KERNEL_PREDICTOR 8    /* the whole predictor of a step: primitives, PCM HLLD
+                                      fluxes, CT edge fields and half-step update in one kernel */
+#define VLCT_KERNEL_COUNT 9
 typedef void (*vlct_launch_observer)(void *user, int kernel, int phase, void *stream);
-int vlct_set_launch_observer(vlct_launch_observer cb, void *user);
+int vlct_step_observed(const vlct_grid *g, const vlct_state *in, const vlct_state *out,
+                       const double *dt_dev, double *next_dt_dev, uint32_t *status_dev, void *ws,
+                       size_t ws_bytes, void *stream, vlct_launch_observer cb, void *user);
 
 /* Name of a VLCT_KERNEL_* id ("?" if unknown). */
 const char *vlct_kernel_name(int kernel);

@@ -625,6 +625,300 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
 }
 
 // ---------------------------------------------------------------------------
+// fused predictor (Steps 2-5 in one kernel): a block owns a TX x TY column
+// tile and marches along z through its planes [k0, k1).  Per new plane m it
+//   (A) derives the primitives of the tile plus a one-cell ring (Sec. 2.1,
+//       B_cc = face average, floors) and the reference field -(v x B),
+//   (B) solves PCM HLLD on the x- and y-faces of plane m and the z-face
+//       m - 1/2 (Steps 2-3; every thread owns one column and the faces on its
+//       low sides), keeping the hydro fluxes in registers and the face EMFs
+//       and upwind indicators in LDS,
+//   (C) forms the edge fields E_z of plane m and E_x, E_y of the half plane
+//       m - 1/2 (Step 4, Eqs. emf-edge, emf-upwind-slope, emf-slope),
+//   (D) updates the cells and the owned faces of plane m - 1 to t + dt/2
+//       (Step 5).
+// Nothing but U^n is read and nothing but U^{n+1/2} is written: primitives,
+// fluxes and edge fields stay on chip.  The block also evaluates the faces of
+// the planes k0 - 1 and k1 (the edges of its first and last half planes need
+// them).  Arithmetic per quantity is that of k_prims, k_flux and k_ct_update.
+// ---------------------------------------------------------------------------
+template <int TX, int TY>
+struct PredShape {
+    static constexpr int CX = TX + 2, CY = TY + 2, NC = CX * CY;  // columns with the ring
+    static constexpr int NT = (NC + 63) / 64 * 64;                  // threads (whole waves)
+    static constexpr int NEZ = (TY + 1) * (TX + 1), NEX = (TY + 1) * TX, NEY = TY * (TX + 1);
+};
+
+// edge field from its four face EMFs, their upwind indicators and the four
+// reference fields around the edge (the arithmetic of edge_emf)
+__device__ __forceinline__ double edge_value(double eb_c, double eb_cm, double ec_b, double ec_bm,
+                                             double sb_c, double sb_cm, double sc_b, double sc_bm,
+                                             double r00, double r10, double r01, double r11)
+{
+    const double avg = 0.25 * (eb_c + eb_cm + ec_b + ec_bm);
+    const double t1 = upwind(sb_c, ec_bm - r10, ec_b - r00);
+    const double t2 = upwind(sb_cm, ec_bm - r11, ec_b - r01);
+    const double t3 = upwind(sc_b, eb_cm - r01, eb_c - r00);
+    const double t4 = upwind(sc_bm, eb_cm - r11, eb_c - r10);
+    return avg + 0.25 * (t1 + t2 + t3 + t4);
+}
+
+// TAPE: also writes the upwind side of every interior face (tape layout)
+template <int TX, int TY, bool TAPE>
+__device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const StateW &out,
+                                          const double *dt_dev, uint32_t *status, idx_t b,
+                                          uint8_t *side0, uint8_t *side1, uint8_t *side2)
+{
+    using S = PredShape<TX, TY>;
+    constexpr int CX = S::CX, CY = S::CY, NC = S::NC;
+    constexpr int NEZ = S::NEZ, NEX = S::NEX, NEY = S::NEY;
+    // W of the newest plane (8 primitives), later the hydro fluxes of the
+    // plane being updated (x: 0-4, y: 5-9)
+    __shared__ double s_wh[10][NC];
+    // reference fields: x and y components of the two newest planes (slot =
+    // plane & 1), z component of the newest plane
+    __shared__ double s_rx[2][NC], s_ry[2][NC], s_rz[NC];
+    // face EMFs of the x- and y-faces of the two newest planes: x-face -F[B_y]
+    // (E_z) and F[B_z] (E_y), y-face -F[B_z] (E_x) and F[B_x] (E_z)
+    __shared__ double s_em[2][4][NC];
+    __shared__ int8_t s_sg[2][2][NC];
+    // z-face m - 1/2: -F[B_x] (E_y), F[B_y] (E_x) and its upwind indicator
+    __shared__ double s_zem[2][NC];
+    __shared__ int8_t s_zsg[NC];
+    // edge fields: E_z of the planes, E_x / E_y of the half planes (slot = index & 1)
+    __shared__ double s_ez[2][TY + 1][TX + 1];
+    __shared__ double s_ex[2][TY + 1][TX];
+    __shared__ double s_ey[2][TY][TX + 1];
+
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int ex = nx + (g.bc[0] == VLCT_BC_OUTFLOW), ey = ny + (g.bc[1] == VLCT_BC_OUTFLOW);
+    const int tz = g.pred_planes;
+    const int ntx = (ex + TX - 1) / TX, nty = (ey + TY - 1) / TY, ntz = (nz + tz - 1) / tz;
+    if (b >= (idx_t)ntx * nty * ntz) return;
+    const int bx = (int)(b % ntx), by = (int)((b / ntx) % nty), bz = (int)(b / ((idx_t)ntx * nty));
+    const int i0 = bx * TX, j0 = by * TY, k0 = bz * tz, k1 = min(k0 + tz, nz);
+    const double dt = 0.5 * dt_dev[0];
+    const double cx = dt / g.dl[0], cy = dt / g.dl[1], cz = dt / g.dl[2];
+
+    // this thread's column: (a, c) in the tile with its ring, cell (ii, jj)
+    const int t = threadIdx.x;
+    const bool col = t < NC;
+    const int a = t % CX, c = t / CX;
+    const int ii = i0 - 1 + a, jj = j0 - 1 + c;
+    const bool live = col && ii <= nx && jj <= ny;
+    const bool do_x = live && a >= 1, do_y = live && c >= 1;
+    const bool do_z = live && !((a == 0 || a == CX - 1) && (c == 0 || c == CY - 1));
+    // owned positions: cells / faces of the tile proper
+    const int tx = a - 1, ty = c - 1;
+    const bool own = live && a >= 1 && a <= TX && c >= 1 && c <= TY && ii < ex && jj < ey;
+    const bool interior = own && ii < nx && jj < ny;
+    const int mi = map_cell(ii, nx, g.bc[0]), mj = map_cell(jj, ny, g.bc[1]);
+    const int fi0 = map_face(ii, nx, g.bc[0]), fi1 = map_face(ii + 1, nx, g.bc[0]);
+    const int fj0 = map_face(jj, ny, g.bc[1]), fj1 = map_face(jj + 1, ny, g.bc[1]);
+
+    uint32_t st = 0;
+    W7 wz_prev{};                   // own cell of the previous plane, z sweep frame
+    double hx[5] = {}, hy[5] = {};  // own x-, y-face hydro fluxes of the previous plane
+    double hz_lo[5] = {};           // own z-face hydro flux below the previous plane
+
+    for (int m = k0 - 1; m <= k1; ++m) {
+        const int sm = m & 1, sp = sm ^ 1;
+        // (A) primitives and reference field of plane m; the cell's low faces
+        // are also the normal fields of the faces this thread solves in (B)
+        double bx0 = 0.0, by0 = 0.0, bz0 = 0.0;
+        if (live) {
+            const int mk = map_cell(m, nz, g.bc[2]);
+            const idx_t cc = cell_store(g, mi, mj, mk);
+            bx0 = s.b[0][face_store(g, 0, fi0, mj, mk)];
+            const double bx1 = s.b[0][face_store(g, 0, fi1, mj, mk)];
+            by0 = s.b[1][face_store(g, 1, mi, fj0, mk)];
+            const double by1 = s.b[1][face_store(g, 1, mi, fj1, mk)];
+            bz0 = s.b[2][face_store(g, 2, mi, mj, map_face(m, nz, g.bc[2]))];
+            const double bz1 = s.b[2][face_store(g, 2, mi, mj, map_face(m + 1, nz, g.bc[2]))];
+            const double bcx = 0.5 * (bx0 + bx1);
+            const double bcy = 0.5 * (by0 + by1);
+            const double bcz = 0.5 * (bz0 + bz1);
+            double d = s.u[0][cc];
+            if (!(d >= kFloorRho)) { d = kFloorRho; st |= kStatusDensityFloor; }
+            const double id = 1.0 / d;
+            const double vx = s.u[1][cc] * id, vy = s.u[2][cc] * id, vz = s.u[3][cc] * id;
+            const double ke = 0.5 * d * (vx * vx + vy * vy + vz * vz);
+            const double me = 0.5 * (bcx * bcx + bcy * bcy + bcz * bcz);
+            double pr = (g.gamma - 1.0) * (s.u[4][cc] - ke - me);
+            if (!(pr >= kFloorP)) { pr = kFloorP; st |= kStatusPressureFloor; }
+            s_wh[0][t] = d;
+            s_wh[1][t] = vx;
+            s_wh[2][t] = vy;
+            s_wh[3][t] = vz;
+            s_wh[4][t] = pr;
+            s_wh[5][t] = bcx;
+            s_wh[6][t] = bcy;
+            s_wh[7][t] = bcz;
+            s_rx[sm][t] = -(vy * bcz - vz * bcy);
+            s_ry[sm][t] = -(vz * bcx - vx * bcz);
+            s_rz[t] = -(vx * bcy - vy * bcx);
+        }
+        __syncthreads();
+        // (B) PCM HLLD on the x-, y-faces of plane m and the z-face m - 1/2
+        double hxn[5] = {}, hyn[5] = {}, hzn[5] = {};
+        W7 wz{};
+        if (live) {
+            const W7 wxr{s_wh[0][t], s_wh[1][t], s_wh[2][t], s_wh[3][t], s_wh[4][t], s_wh[6][t], s_wh[7][t]};
+            wz = W7{s_wh[0][t], s_wh[3][t], s_wh[1][t], s_wh[2][t], s_wh[4][t], s_wh[5][t], s_wh[6][t]};
+            double f[7], upw;
+            if (do_x) {
+                const int l = t - 1;
+                const W7 wl{s_wh[0][l], s_wh[1][l], s_wh[2][l], s_wh[3][l], s_wh[4][l], s_wh[6][l], s_wh[7][l]};
+                hlld(wl, wxr, bx0, g.gamma, g.gm1i, f, upw);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) hxn[q] = f[q];
+                s_em[sm][0][t] = -f[5];
+                s_em[sm][1][t] = f[6];
+                s_sg[sm][0][t] = (int8_t)upw;
+                if (TAPE && interior && m >= k0 && m < k1) side0[cell_store(g, ii, jj, m)] = side_code(upw);
+            }
+            if (do_y) {
+                const int l = t - CX;
+                const W7 wl{s_wh[0][l], s_wh[2][l], s_wh[3][l], s_wh[1][l], s_wh[4][l], s_wh[7][l], s_wh[5][l]};
+                const W7 wr{s_wh[0][t], s_wh[2][t], s_wh[3][t], s_wh[1][t], s_wh[4][t], s_wh[7][t], s_wh[5][t]};
+                hlld(wl, wr, by0, g.gamma, g.gm1i, f, upw);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) hyn[q] = f[q];
+                s_em[sm][2][t] = -f[5];
+                s_em[sm][3][t] = f[6];
+                s_sg[sm][1][t] = (int8_t)upw;
+                if (TAPE && interior && m >= k0 && m < k1) side1[cell_store(g, ii, jj, m)] = side_code(upw);
+            }
+            if (do_z && m >= k0) {
+                hlld(wz_prev, wz, bz0, g.gamma, g.gm1i, f, upw);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) hzn[q] = f[q];
+                s_zem[0][t] = -f[5];
+                s_zem[1][t] = f[6];
+                s_zsg[t] = (int8_t)upw;
+                if (TAPE && interior && m < k1) side2[cell_store(g, ii, jj, m)] = side_code(upw);
+            }
+        }
+        __syncthreads();
+        // (C) E_z of plane m, E_x / E_y of the half plane m - 1/2; the hydro
+        // fluxes of plane m - 1 go to LDS for the neighbours' updates
+        if (m >= k0) {
+            const int nez = m < k1 ? NEZ : 0;
+            for (int q = threadIdx.x; q < nez + NEX + NEY; q += S::NT) {
+                if (q < nez) {
+                    const int ea = q % (TX + 1), ec = q / (TX + 1), ie = i0 + ea, je = j0 + ec;
+                    // E_z at (ie - 1/2, je - 1/2, m): B = x-faces, C = y-faces
+                    if (ie <= nx && je <= ny) {
+                        const int o = (ec + 1) * CX + ea + 1;  // column (ie, je)
+                        s_ez[sm][ec][ea] = edge_value(
+                            s_em[sm][0][o], s_em[sm][0][o - CX], s_em[sm][3][o], s_em[sm][3][o - 1],
+                            s_sg[sm][0][o], s_sg[sm][0][o - CX], s_sg[sm][1][o], s_sg[sm][1][o - 1],
+                            s_rz[o], s_rz[o - 1], s_rz[o - CX], s_rz[o - CX - 1]);
+                    }
+                } else if (q < nez + NEX) {
+                    const int r = q - nez;
+                    const int ea = r % TX, ec = r / TX, ie = i0 + ea, je = j0 + ec;
+                    // E_x at (ie, je - 1/2, m - 1/2): B = y-faces (planes m, m - 1), C = z-faces
+                    if (ie < nx && je <= ny) {
+                        const int o = (ec + 1) * CX + ea + 1;
+                        s_ex[sm][ec][ea] = edge_value(
+                            s_em[sm][2][o], s_em[sp][2][o], s_zem[1][o], s_zem[1][o - CX],
+                            s_sg[sm][1][o], s_sg[sp][1][o], s_zsg[o], s_zsg[o - CX],
+                            s_rx[sm][o], s_rx[sm][o - CX], s_rx[sp][o], s_rx[sp][o - CX]);
+                    }
+                } else {
+                    const int r = q - nez - NEX;
+                    const int ea = r % (TX + 1), ec = r / (TX + 1), ie = i0 + ea, je = j0 + ec;
+                    // E_y at (ie - 1/2, je, m - 1/2): B = z-faces, C = x-faces (planes m, m - 1)
+                    if (ie <= nx && je < ny) {
+                        const int o = (ec + 1) * CX + ea + 1;
+                        s_ey[sm][ec][ea] = edge_value(
+                            s_zem[0][o], s_zem[0][o - 1], s_em[sm][1][o], s_em[sp][1][o],
+                            s_zsg[o], s_zsg[o - 1], s_sg[sm][0][o], s_sg[sp][0][o],
+                            s_ry[sm][o], s_ry[sp][o], s_ry[sm][o - 1], s_ry[sp][o - 1]);
+                    }
+                }
+            }
+        }
+        const bool upd = m - 1 >= k0 && m - 1 < k1;
+        if (upd && live) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                s_wh[q][t] = hx[q];
+                s_wh[5 + q][t] = hy[q];
+            }
+        }
+        __syncthreads();
+        // (D) half-step update of plane k = m - 1 (Step 5)
+        if (upd && own) {
+            const int k = m - 1;
+            const int lo = sp, hi = sm;  // half planes k - 1/2 and k + 1/2
+            if (interior) {
+                const idx_t cc = cell_store(g, ii, jj, k);
+                const double dxr = s_wh[0][t + 1] - hx[0];
+                const double dyr = s_wh[5][t + CX] - hy[0];
+                const double dzr = hzn[0] - hz_lo[0];
+                const double dxe = s_wh[4][t + 1] - hx[4];
+                const double dye = s_wh[9][t + CX] - hy[4];
+                const double dze = hzn[4] - hz_lo[4];
+                const double dxmx = s_wh[1][t + 1] - hx[1];
+                const double dxmy = s_wh[2][t + 1] - hx[2];
+                const double dxmz = s_wh[3][t + 1] - hx[3];
+                const double dymy = s_wh[6][t + CX] - hy[1];
+                const double dymz = s_wh[7][t + CX] - hy[2];
+                const double dymx = s_wh[8][t + CX] - hy[3];
+                const double dzmz = hzn[1] - hz_lo[1];
+                const double dzmx = hzn[2] - hz_lo[2];
+                const double dzmy = hzn[3] - hz_lo[3];
+                out.u[0][cc] = s.u[0][cc] - cx * dxr - cy * dyr - cz * dzr;
+                out.u[1][cc] = s.u[1][cc] - cx * dxmx - cy * dymx - cz * dzmx;
+                out.u[2][cc] = s.u[2][cc] - cx * dxmy - cy * dymy - cz * dzmy;
+                out.u[3][cc] = s.u[3][cc] - cx * dxmz - cy * dymz - cz * dzmz;
+                out.u[4][cc] = s.u[4][cc] - cx * dxe - cy * dye - cz * dze;
+            }
+            const int ke = k & 1;  // E_z slot of plane k
+            if (jj < ny) {  // face x (ii - 1/2, jj, k)
+                const double b0 = s.b[0][face_store(g, 0, ii, jj, k)];
+                const double v = b0 - cy * (s_ez[ke][ty + 1][tx] - s_ez[ke][ty][tx])
+                                 + cz * (s_ey[hi][ty][tx] - s_ey[lo][ty][tx]);
+                out.b[0][face_store(g, 0, ii, jj, k)] = v;
+                if (g.bc[0] == VLCT_BC_PERIODIC && ii == 0) out.b[0][face_store(g, 0, nx, jj, k)] = v;
+            }
+            if (ii < nx) {  // face y (ii, jj - 1/2, k)
+                const double b0 = s.b[1][face_store(g, 1, ii, jj, k)];
+                const double v = b0 - cz * (s_ex[hi][ty][tx] - s_ex[lo][ty][tx])
+                                 + cx * (s_ez[ke][ty][tx + 1] - s_ez[ke][ty][tx]);
+                out.b[1][face_store(g, 1, ii, jj, k)] = v;
+                if (g.bc[1] == VLCT_BC_PERIODIC && jj == 0) out.b[1][face_store(g, 1, ii, ny, k)] = v;
+            }
+            if (interior) {  // face z (ii, jj, k - 1/2)
+                const double b0 = s.b[2][face_store(g, 2, ii, jj, k)];
+                const double v = b0 - cx * (s_ey[lo][ty][tx + 1] - s_ey[lo][ty][tx])
+                                 + cy * (s_ex[lo][ty + 1][tx] - s_ex[lo][ty][tx]);
+                out.b[2][face_store(g, 2, ii, jj, k)] = v;
+                if (g.bc[2] == VLCT_BC_PERIODIC && k == 0) out.b[2][face_store(g, 2, ii, jj, nz)] = v;
+            }
+        }
+        // the top z faces of an outflow axis, from the edges of the half plane nz - 1/2
+        if (m == k1 && k1 == nz && g.bc[2] == VLCT_BC_OUTFLOW && interior) {
+            const double b0 = s.b[2][face_store(g, 2, ii, jj, nz)];
+            const double v = b0 - cx * (s_ey[sm][ty][tx + 1] - s_ey[sm][ty][tx])
+                             + cy * (s_ex[sm][ty + 1][tx] - s_ex[sm][ty][tx]);
+            out.b[2][face_store(g, 2, ii, jj, nz)] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            hx[q] = hxn[q];
+            hy[q] = hyn[q];
+            hz_lo[q] = hzn[q];
+        }
+        wz_prev = wz;
+        __syncthreads();
+    }
+    if (st && status) atomicOr(status, st);
+}
+
+// ---------------------------------------------------------------------------
 // CFL reduction (Step 1, Eq. dt): per-block maxima of max_l (|v_l| + c_f,l)/d_l,
 // then one block reduces the partials and writes dt = cfl / max.
 // ---------------------------------------------------------------------------
@@ -713,6 +1007,8 @@ __global__ void __launch_bounds__(kBlock) k_flux_recon_march(Geom g, StateP s, P
 // 16-face launch would have fewer than 1024 blocks (4 per CU)
 static int march_segment(const Geom &g, int d)
 {
+    const int o = tile_override("march");
+    if (o == 8 || o == kMarch) return o;
     return nblk_march(g, d, kMarch) < 1024 ? 8 : kMarch;
 }
 
@@ -723,6 +1019,27 @@ __global__ void __launch_bounds__(kCt) k_ct_update(Geom g, Prims P, Flux F, Stat
 {
     ct_body<FULL, kTx, kTy, DT>(g, P, F, base, out, dt_dev, status, xcd_block(nblk_ct(g)),
                                 partial);
+}
+
+constexpr int kPredTx = 32, kPredTy = 13;  // fused predictor column tile: 34 x 15 columns with the ring, 510 threads of 512
+constexpr int kPredThreads = PredShape<kPredTx, kPredTy>::NT;
+
+__host__ __device__ __forceinline__ idx_t nblk_pred(const Geom &g)
+{
+    const int ntx = (g.n[0] + (g.bc[0] == VLCT_BC_OUTFLOW) + kPredTx - 1) / kPredTx;
+    const int nty = (g.n[1] + (g.bc[1] == VLCT_BC_OUTFLOW) + kPredTy - 1) / kPredTy;
+    const int ntz = (g.n[2] + g.pred_planes - 1) / g.pred_planes;
+    return (idx_t)ntx * nty * ntz;
+}
+
+template <bool TAPE>
+__global__ void __launch_bounds__(kPredThreads) k_pred(Geom g, StateP s, StateW out,
+                                                        const double *dt_dev, uint32_t *status,
+                                                        uint8_t *side0, uint8_t *side1,
+                                                        uint8_t *side2)
+{
+    pred_body<kPredTx, kPredTy, TAPE>(g, s, out, dt_dev, status, xcd_block(nblk_pred(g)), side0,
+                                      side1, side2);
 }
 
 __global__ void __launch_bounds__(kBlock) k_dt_partial(Geom g, StateP s, double *partial,
@@ -742,6 +1059,7 @@ __global__ void __launch_bounds__(kBlock) k_dt_partial(Geom g, StateP s, double 
 // launches of a batched step; the march and CT launches come once per tile
 // variant (an instance has blocks only in the slot of its own variant)
 enum Slot {
+    kSlotPred,
     kSlotPrims,
     kSlotFlux0,
     kSlotFlux1,
@@ -801,6 +1119,19 @@ __device__ __forceinline__ StateP const_view(const StateW &w)
     for (int f = 0; f < 5; ++f) p.u[f] = w.u[f];
     for (int d = 0; d < 3; ++d) p.b[d] = w.b[d];
     return p;
+}
+
+// the fused predictor of every instance: U^n -> U^{n+1/2}
+__global__ void __launch_bounds__(kPredThreads) kb_pred(const Inst *tab, int count, idx_t total)
+{
+    const idx_t gb = xcd_block(total);
+    if (gb >= total) return;
+    idx_t lb;
+    const Inst &I = find_inst(tab, count, kSlotPred, gb, lb);
+    const Geom g = I.g;
+    const StateP in = I.in;
+    const StateW half = I.half;
+    pred_body<kPredTx, kPredTy, false>(g, in, half, I.dt, I.status, lb, nullptr, nullptr, nullptr);
 }
 
 // half = 0: primitives of U^n, 1: of U^{n+1/2}
@@ -944,20 +1275,25 @@ static Layout layout(const Geom &g)
 }
 
 
-// launch observer (diagnostics, see vlct_set_launch_observer)
-static vlct_launch_observer g_observer = nullptr;
-static void *g_observer_user = nullptr;
+// launch observer of one vlct_step_observed call (diagnostics): set by that
+// call on its own host thread for its duration only, so other calls and
+// threads never see it
+struct ObserverCtx {
+    vlct_launch_observer cb;
+    void *user;
+};
+static thread_local const ObserverCtx *t_observer = nullptr;
 
 struct Observe {
     int kernel;
     hipStream_t s;
     Observe(int k, hipStream_t st) : kernel(k), s(st)
     {
-        if (g_observer) g_observer(g_observer_user, kernel, 0, static_cast<void *>(s));
+        if (t_observer) t_observer->cb(t_observer->user, kernel, 0, static_cast<void *>(s));
     }
     ~Observe()
     {
-        if (g_observer) g_observer(g_observer_user, kernel, 1, static_cast<void *>(s));
+        if (t_observer) t_observer->cb(t_observer->user, kernel, 1, static_cast<void *>(s));
     }
 };
 
@@ -1052,6 +1388,21 @@ int launch_ct(const Geom &g, bool full, const Prims &P, const Flux &F, const Sta
     return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
 }
 
+// the whole predictor (Steps 2-5) in one kernel: U^n -> U^{n+1/2}; with
+// `side` (3 arrays, tape layout) it also records the faces' upwind sides
+static int launch_pred(const Geom &g, const StateP &st, const StateW &half, const double *dt_dev,
+                       uint32_t *status, uint8_t *const *side, hipStream_t s)
+{
+    Observe o(VLCT_KERNEL_PREDICTOR, s);
+    if (side)
+        k_pred<true><<<xcd_grid(nblk_pred(g)), kPredThreads, 0, s>>>(g, st, half, dt_dev, status,
+                                                                     side[0], side[1], side[2]);
+    else
+        k_pred<false><<<xcd_grid(nblk_pred(g)), kPredThreads, 0, s>>>(g, st, half, dt_dev, status,
+                                                                      nullptr, nullptr, nullptr);
+    return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
+}
+
 // the full step's CT update with the CFL reduction of the new state fused in
 // (one partial per CT block), then the final reduction into dt_out
 static int launch_ct_dt(const Geom &g, const Prims &P, const Flux &F, const StateP &base,
@@ -1129,6 +1480,7 @@ static void batch_records(int count, const vlct_grid *grids, const vlct_state *i
         r.status = status_dev ? status_dev + i : nullptr;
         const int cv = plan ? (plan[i] & 15) : 0, mv = plan ? (plan[i] >> 4) : 0;
         idx_t nb[kSlots] = {};
+        nb[kSlotPred] = nblk_pred(g);
         nb[kSlotPrims] = nblk_prims(g);
         for (int d = 0; d < 3; ++d) nb[kSlotFlux0 + d] = nblk_flux(g, d);
         nb[kSlotRow] = nblk_row(g);
@@ -1202,6 +1554,33 @@ static int scratch_address(void **out)
     return VLCT_OK;
 }
 
+// `out` must be `in` itself (all eight arrays the same) or use memory that no
+// input array overlaps, and no two output arrays may overlap: compared as
+// address ranges [p, p + bytes) of the grid's field sizes
+static bool in_out_ok(const vlct_grid *vg, const vlct_state *in, const vlct_state *out,
+                      bool &all_same)
+{
+    const int n[3] = {vg->nx, vg->ny, vg->nz};
+    const double *pi[8] = {in->rho, in->mx, in->my, in->mz, in->E, in->bx, in->by, in->bz};
+    const double *po[8] = {out->rho, out->mx, out->my, out->mz, out->E, out->bx, out->by, out->bz};
+    auto overlap = [&](const double *a, int fa, const double *b, int fb) {
+        const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+        const uintptr_t a1 = a0 + field_len(n, fa) * sizeof(double);
+        const uintptr_t b1 = b0 + field_len(n, fb) * sizeof(double);
+        return a0 < b1 && b0 < a1;
+    };
+    all_same = true;
+    for (int f = 0; f < 8; ++f) all_same &= pi[f] == po[f];
+    for (int f = 0; f < 8; ++f)
+        for (int h = f + 1; h < 8; ++h)
+            if (overlap(po[f], f, po[h], h)) return false;
+    if (all_same) return true;
+    for (int f = 0; f < 8; ++f)
+        for (int h = 0; h < 8; ++h)
+            if (overlap(po[f], f, pi[h], h)) return false;
+    return true;
+}
+
 }  // namespace vlct
 
 using namespace vlct;
@@ -1230,17 +1609,8 @@ int vlct_step(const vlct_grid *vg, const vlct_state *in, const vlct_state *out,
               size_t ws_bytes, void *stream)
 {
     if (!grid_ok(vg) || !state_ok(in) || !state_ok(out) || !dt_dev) return VLCT_EINVAL;
-    // out must equal in or be disjoint from it field by field
-    bool all_same = true;
-    {
-        const double *pi[8] = {in->rho, in->mx, in->my, in->mz, in->E, in->bx, in->by, in->bz};
-        const double *po[8] = {out->rho, out->mx, out->my, out->mz, out->E, out->bx, out->by, out->bz};
-        for (int f = 0; f < 8; ++f) all_same &= (pi[f] == po[f]);
-        if (!all_same)
-            for (int f = 0; f < 8; ++f)
-                for (int h = 0; h < 8; ++h)
-                    if (po[f] == pi[h]) return VLCT_EINVAL;
-    }
+    bool all_same = false;
+    if (!in_out_ok(vg, in, out, all_same)) return VLCT_EINVAL;
     const Geom g = make_geom(vg);
     const Layout L = layout(g);
     if (!ws || ws_bytes < L.total) return VLCT_EWORKSPACE;
@@ -1248,9 +1618,7 @@ int vlct_step(const vlct_grid *vg, const vlct_state *in, const vlct_state *out,
     hipStream_t s = static_cast<hipStream_t>(stream);
     const StateP sin = as_const(in);
     // predictor (Steps 2-5)
-    int rc = launch_prims(g, sin, B.P, status_dev, s);
-    if (!rc) rc = launch_fluxes(g, sin, B.P, B.F, VLCT_RECON_PCM, status_dev, s);
-    if (!rc) rc = launch_ct(g, false, B.P, B.F, sin, B.half, dt_dev, status_dev, s);
+    int rc = launch_pred(g, sin, B.half, dt_dev, status_dev, nullptr, s);
     // corrector (Steps 6-9)
     const StateP half = as_const(B.half);
     if (!rc) rc = launch_prims(g, half, B.P, status_dev, s);
@@ -1291,17 +1659,8 @@ int vlct_step_taped(const vlct_grid *vg, const vlct_state *in, const vlct_state 
                     size_t ws_bytes, void *tape, size_t tape_bytes, void *stream)
 {
     if (!grid_ok(vg) || !state_ok(in) || !state_ok(out) || !dt_dev) return VLCT_EINVAL;
-    // out must equal in or be disjoint from it field by field
-    bool all_same = true;
-    {
-        const double *pi[8] = {in->rho, in->mx, in->my, in->mz, in->E, in->bx, in->by, in->bz};
-        const double *po[8] = {out->rho, out->mx, out->my, out->mz, out->E, out->bx, out->by, out->bz};
-        for (int f = 0; f < 8; ++f) all_same &= (pi[f] == po[f]);
-        if (!all_same)
-            for (int f = 0; f < 8; ++f)
-                for (int h = 0; h < 8; ++h)
-                    if (po[f] == pi[h]) return VLCT_EINVAL;
-    }
+    bool all_same = false;
+    if (!in_out_ok(vg, in, out, all_same)) return VLCT_EINVAL;
     const Geom g = make_geom(vg);
     const Layout L = layout(g);
     const TapeLayout T = tape_layout(g.n);
@@ -1320,10 +1679,7 @@ int vlct_step_taped(const vlct_grid *vg, const vlct_state *in, const vlct_state 
     const StateP sin = as_const(in);
     // the steps of vlct_step with the half-step state and both stages' upwind
     // sides kept in the tape
-    int rc = launch_prims(g, sin, B.P, status_dev, s);
-    if (!rc) rc = launch_fluxes(g, sin, B.P, B.F, VLCT_RECON_PCM, status_dev, s);
-    if (!rc) rc = launch_pack_sides(g, B.F, side[0], s);
-    if (!rc) rc = launch_ct(g, false, B.P, B.F, sin, half, dt_dev, status_dev, s);
+    int rc = launch_pred(g, sin, half, dt_dev, status_dev, side[0], s);
     const StateP hc = as_const(half);
     if (!rc) rc = launch_prims(g, hc, B.P, status_dev, s);
     if (!rc) rc = launch_fluxes(g, hc, B.P, B.F, vg->recon, status_dev, s);
@@ -1357,11 +1713,17 @@ const char *vlct_strerror(int code)
 
 int vlct_abi_version(void) { return VLCT_ABI_VERSION; }
 
-int vlct_set_launch_observer(vlct_launch_observer cb, void *user)
+int vlct_step_observed(const vlct_grid *g, const vlct_state *in, const vlct_state *out,
+                       const double *dt_dev, double *next_dt_dev, uint32_t *status_dev, void *ws,
+                       size_t ws_bytes, void *stream, vlct_launch_observer cb, void *user)
 {
-    g_observer = cb;
-    g_observer_user = user;
-    return VLCT_OK;
+    if (!cb) return VLCT_EINVAL;
+    const ObserverCtx ctx{cb, user};
+    struct Scope {
+        explicit Scope(const ObserverCtx *c) { t_observer = c; }
+        ~Scope() { t_observer = nullptr; }
+    } scope(&ctx);
+    return vlct_step(g, in, out, dt_dev, next_dt_dev, status_dev, ws, ws_bytes, stream);
 }
 
 size_t vlct_batch_workspace_bytes(const vlct_grid *grids, int count)
@@ -1423,27 +1785,14 @@ int vlct_step_batch_plan(int count, const vlct_grid *grids, const vlct_state *in
     const int recon = grids[0].recon;
     // predictor (Steps 2-5)
     {
-        Observe o(VLCT_KERNEL_PRIMS, s);
-        kb_prims<<<xcd_grid(tot[kSlotPrims]), kBlock, 0, s>>>(tab, count, tot[kSlotPrims], 0);
-    }
-    {
-        Observe o(VLCT_KERNEL_FLUX_PCM, s);
-        kb_flux_pcm<0><<<xcd_grid(tot[kSlotFlux0]), kBlock, 0, s>>>(tab, count, tot[kSlotFlux0], 0);
-    }
-    {
-        Observe o(VLCT_KERNEL_FLUX_PCM, s);
-        kb_flux_pcm<1><<<xcd_grid(tot[kSlotFlux1]), kBlock, 0, s>>>(tab, count, tot[kSlotFlux1], 0);
-    }
-    {
-        Observe o(VLCT_KERNEL_FLUX_PCM, s);
-        kb_flux_pcm<2><<<xcd_grid(tot[kSlotFlux2]), kBlock, 0, s>>>(tab, count, tot[kSlotFlux2], 0);
+        Observe o(VLCT_KERNEL_PREDICTOR, s);
+        kb_pred<<<xcd_grid(tot[kSlotPred]), kPredThreads, 0, s>>>(tab, count, tot[kSlotPred]);
     }
 #define VLCT_BCT(FULL, V)                                                                 \
     if (tot[kSlotCt + V]) {                                                                   \
         Observe o(FULL ? VLCT_KERNEL_UPDATE_FULL : VLCT_KERNEL_UPDATE_HALF, s);                \
         kb_ct<FULL, V><<<xcd_grid(tot[kSlotCt + V]), kCt, 0, s>>>(tab, count, tot[kSlotCt + V]); \
     }
-    VLCT_BCT(false, 0) VLCT_BCT(false, 1) VLCT_BCT(false, 2)
     // corrector (Steps 6-9)
     {
         Observe o(VLCT_KERNEL_PRIMS, s);
@@ -1573,7 +1922,8 @@ const char *vlct_kernel_name(int kernel)
     static const char *names[VLCT_KERNEL_COUNT] = {"prims",       "flux_pcm_hlld",
                                                    "flux_recon_hlld", "edges",
                                                    "update_half", "update_full",
-                                                   "dt",          "dt_final"};
+                                                   "dt",          "dt_final",
+                                                   "predictor"};
     return kernel >= 0 && kernel < VLCT_KERNEL_COUNT ? names[kernel] : "?";
 }
 

@@ -288,6 +288,8 @@ __host__ __device__ __forceinline__ idx_t ad_march_blocks(const Geom &g, int D,
 // ms; 128^3, 512 blocks, is faster with 16)
 static int ad_march_segment(const Geom &g, int D)
 {
+    const int o = tile_override("admarch");
+    if (o == 8 || o == kAdMarch) return o;
     return ad_march_blocks(g, D, kAdMarch) < 256 ? 8 : kAdMarch;
 }
 

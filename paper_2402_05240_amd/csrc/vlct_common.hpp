@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 
 #include "../../include/vlct.h"
@@ -39,7 +40,8 @@ struct Geom {
     double dl[3];
     double gamma, gm1i, cfl;
     int p[3];  // padded primitive dims n + 2G
-    int ct_planes;  // z planes a CT block marches through
+    int ct_planes;    // z planes a CT block marches through
+    int pred_planes;  // z planes a fused predictor block marches through
 };
 
 __host__ __device__ __forceinline__ int map_cell(int i, int n, int bc)
@@ -122,6 +124,28 @@ inline bool grid_ok(const vlct_grid *g)
     return true;
 }
 
+// Tile override for tests and tuning: the environment variable VLCT_TILES,
+// read at every call, holds comma-separated key=value pairs (ct=4|8|16 CT
+// planes per block, march=8|16 faces per corrector march segment, pred=4..64
+// fused predictor planes per block, admarch=8|16 cells per adjoint march
+// segment) that replace the size-dependent choices.  Every choice computes the
+// same per-cell and per-face arithmetic; the forward results are bitwise the
+// same, the adjoint's equal to the summation order of its accumulations.
+// Returns 0 when `key` is not set.
+inline int tile_override(const char *key)
+{
+    const char *env = std::getenv("VLCT_TILES");
+    if (!env) return 0;
+    const size_t kl = std::strlen(key);
+    for (const char *p = env; *p;) {
+        if (std::strncmp(p, key, kl) == 0 && p[kl] == '=') return std::atoi(p + kl + 1);
+        const char *c = std::strchr(p, ',');
+        if (!c) break;
+        p = c + 1;
+    }
+    return 0;
+}
+
 inline Geom make_geom(const vlct_grid *vg)
 {
     Geom g;
@@ -147,6 +171,23 @@ inline Geom make_geom(const vlct_grid *vg)
     g.ct_planes = 16;
     if (cols * ((g.n[2] + 15) / 16) < 1024) g.ct_planes = 8;
     if (g.ct_planes == 8 && cols * ((g.n[2] + 7) / 8) < 256) g.ct_planes = 4;
+    // fused predictor: 32 x 13 column tiles, one block per CU (LDS-bound); a
+    // block marching p planes also solves the faces of two extra planes, so
+    // take the p that minimises (blocks per CU, rounded up) x (p + 2)
+    const long long pcols = (long long)((g.n[0] + (g.bc[0] == VLCT_BC_OUTFLOW) + 31) / 32) *
+                            ((g.n[1] + (g.bc[1] == VLCT_BC_OUTFLOW) + 12) / 13);
+    long long best = -1;
+    for (int p = 64; p >= 4; p /= 2) {
+        const long long blocks = pcols * ((g.n[2] + p - 1) / p);
+        const long long cost = ((blocks + 255) / 256) * (p + 2);
+        if (best < 0 || cost < best) {
+            best = cost;
+            g.pred_planes = p;
+        }
+    }
+    const int oct = tile_override("ct"), opred = tile_override("pred");
+    if (oct == 4 || oct == 8 || oct == 16) g.ct_planes = oct;
+    if (opred >= 1 && opred <= 64) g.pred_planes = opred;
     return g;
 }
 

@@ -88,6 +88,18 @@ class Stepper:
         self.cur, self.nxt = self.nxt, self.cur
         self.dt, self.next_dt = self.next_dt, self.dt
 
+    def step_observed(self, cb) -> None:
+        """step() through vlct_step_observed: cb(kernel, phase, stream) runs on
+        this thread around each kernel launch of the step (profiling)."""
+        rc = vlct.vlct_step_observed(self.cg, self.cur.c_state(), self.nxt.c_state(),
+                                     self.dt.data_ptr(), self.next_dt.data_ptr(),
+                                     self.status.data_ptr(), self.ws.data_ptr(), self.ws_bytes,
+                                     self.stream(), cb)
+        if rc:
+            raise vlct.VlctError(rc, "vlct_step_observed")
+        self.cur, self.nxt = self.nxt, self.cur
+        self.dt, self.next_dt = self.next_dt, self.dt
+
     def status_bits(self) -> int:
         return int(self.status.item())
 

@@ -31,7 +31,7 @@ VLCT_STATUS_DENSITY_FLOOR = 2
 VLCT_STATUS_NONFINITE = 4
 
 EXPORTED = ("vlct_workspace_bytes", "vlct_cfl_dt", "vlct_step", "vlct_strerror",
-            "vlct_abi_version", "vlct_set_launch_observer", "vlct_kernel_name",
+            "vlct_abi_version", "vlct_step_observed", "vlct_kernel_name",
             "vlct_batch_workspace_bytes", "vlct_step_batch", "vlct_adjoint_workspace_bytes",
             "vlct_step_adjoint", "vlct_curl_potential", "vlct_curl_potential_adjoint",
             "vlct_tape_bytes", "vlct_step_taped", "vlct_adjoint_taped_workspace_bytes",
@@ -46,7 +46,8 @@ VLCT_KERNEL_UPDATE_HALF = 4
 VLCT_KERNEL_UPDATE_FULL = 5
 VLCT_KERNEL_DT = 6
 VLCT_KERNEL_DT_FINAL = 7
-VLCT_KERNEL_COUNT = 8
+VLCT_KERNEL_PREDICTOR = 8
+VLCT_KERNEL_COUNT = 9
 
 vlct_launch_observer = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_void_p)
@@ -141,8 +142,12 @@ def load(path: str = LIB_PATH):
         lib.vlct_strerror.restype = ctypes.c_char_p
         lib.vlct_abi_version.argtypes = []
         lib.vlct_abi_version.restype = ctypes.c_int
-        lib.vlct_set_launch_observer.argtypes = [vlct_launch_observer, ctypes.c_void_p]
-        lib.vlct_set_launch_observer.restype = ctypes.c_int
+        lib.vlct_step_observed.argtypes = [ctypes.POINTER(vlct_grid), ctypes.POINTER(vlct_state),
+                                           ctypes.POINTER(vlct_state), ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_size_t, ctypes.c_void_p, vlct_launch_observer,
+                                           ctypes.c_void_p]
+        lib.vlct_step_observed.restype = ctypes.c_int
         lib.vlct_kernel_name.argtypes = [ctypes.c_int]
         lib.vlct_kernel_name.restype = ctypes.c_char_p
         _lib = lib
@@ -291,18 +296,15 @@ def vlct_abi_version() -> int:
     return int(load().vlct_abi_version())
 
 
-_observer_keepalive = None
-
-
-def vlct_set_launch_observer(cb) -> int:
-    """Install a Python callable cb(kernel, phase, stream) (or None)."""
-    global _observer_keepalive
-    if cb is None:
-        _observer_keepalive = None
-        return int(load().vlct_set_launch_observer(vlct_launch_observer(), None))
+def vlct_step_observed(grid: vlct_grid, state_in: vlct_state, state_out: vlct_state, dt_dev: int,
+                       next_dt_dev: int, status_dev: int, ws: int, ws_bytes: int, stream: int,
+                       cb) -> int:
+    """vlct_step that calls the Python callable cb(kernel, phase, stream)
+    around each kernel launch of this call."""
     wrapped = vlct_launch_observer(lambda user, k, ph, st: cb(k, ph, st or 0))
-    _observer_keepalive = wrapped
-    return int(load().vlct_set_launch_observer(wrapped, None))
+    return int(load().vlct_step_observed(ctypes.byref(grid), ctypes.byref(state_in),
+                                         ctypes.byref(state_out), dt_dev, next_dt_dev, status_dev,
+                                         ws, ws_bytes, stream, wrapped, None))
 
 
 def vlct_kernel_name(kernel: int) -> str:

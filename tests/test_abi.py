@@ -36,6 +36,11 @@ def test_library_exports_every_declared_function():
     assert vlct.vlct_abi_version() == 100
 
 
+# spacing of fake device addresses in the validation tests: more than any
+# field of the test grids, so fake arrays never overlap unless a test says so
+SPACING = 1 << 20
+
+
 def _grid(**kw):
     base = dict(nx=8, ny=8, nz=8, dx=0.1, dy=0.1, dz=0.1, gamma=5 / 3, cfl=0.4, recon=2, bc=(0, 0, 0))
     base.update(kw)
@@ -60,30 +65,57 @@ def test_workspace_and_pointer_validation():
     g = _grid()
     need = vlct.vlct_workspace_bytes(g)
     assert need > 8 * 8 ** 3 * 8
-    fake = vlct.make_state([4096 * (f + 1) for f in range(8)])
+    fake = vlct.make_state([SPACING * (f + 1) for f in range(8)])
     # missing / short workspace
     assert vlct.vlct_step(g, fake, fake, 64, 0, 0, 0, need, 0) == vlct.VLCT_EWORKSPACE
     assert vlct.vlct_step(g, fake, fake, 64, 0, 0, 128, need - 1, 0) == vlct.VLCT_EWORKSPACE
     assert vlct.vlct_cfl_dt(g, fake, 64, 128, need - 1, 0) == vlct.VLCT_EWORKSPACE
     # NULL field, NULL dt
-    holey = vlct.make_state([4096 * (f + 1) for f in range(7)] + [0])
+    holey = vlct.make_state([SPACING * (f + 1) for f in range(7)] + [0])
     assert vlct.vlct_step(g, holey, fake, 64, 0, 0, 128, need, 0) == vlct.VLCT_EINVAL
     assert vlct.vlct_step(g, fake, fake, 0, 0, 0, 128, need, 0) == vlct.VLCT_EINVAL
-    # partial aliasing of out and in
-    other = vlct.make_state([4096 * (f + 1) for f in range(7)] + [10 ** 9])
-    part = vlct.make_state([10 ** 9 + 4096 * f for f in range(7)] + [4096])
+    # partial aliasing of out and in: shared base pointers
+    other = vlct.make_state([SPACING * (f + 1) for f in range(7)] + [10 ** 9])
+    part = vlct.make_state([10 ** 9 + SPACING * f for f in range(7)] + [SPACING])
     assert vlct.vlct_step(g, fake, part, 64, 0, 0, 128, need, 0) == vlct.VLCT_EINVAL
     assert vlct.vlct_step(g, fake, other, 64, 0, 0, 128, need, 0) == vlct.VLCT_EINVAL
+
+
+def test_overlapping_address_ranges_rejected():
+    """Output arrays must not overlap an input array or each other as address
+    ranges, even when no two base pointers are equal (an 8^3 cell field is
+    4096 bytes, a face field 4608)."""
+    _lib()
+    g = _grid()
+    need = vlct.vlct_workspace_bytes(g)
+    fin = vlct.make_state([SPACING * (f + 1) for f in range(8)])
+    ok_out = vlct.make_state([10 ** 9 + SPACING * f for f in range(8)])
+    # a valid out-of-place call reaches the workspace check
+    assert vlct.vlct_step(g, fin, ok_out, 64, 0, 0, 0, need, 0) == vlct.VLCT_EWORKSPACE
+    # out.E starts 8 bytes into in.E; out.rho ends one double into in.rho
+    shifted = vlct.make_state([10 ** 9 + SPACING * f for f in range(4)] + [SPACING * 5 + 8]
+                              + [10 ** 9 + SPACING * f for f in range(5, 8)])
+    assert vlct.vlct_step(g, fin, shifted, 64, 0, 0, 128, need, 0) == vlct.VLCT_EINVAL
+    tail = vlct.make_state([SPACING * 1 - 4096 + 8] + [10 ** 9 + SPACING * f for f in range(1, 8)])
+    assert vlct.vlct_step(g, fin, tail, 64, 0, 0, 128, need, 0) == vlct.VLCT_EINVAL
+    # two outputs overlapping each other: bx (4608 bytes) runs into by
+    twin = vlct.make_state([10 ** 9 + SPACING * f for f in range(5)]
+                           + [10 ** 9 + SPACING * 5, 10 ** 9 + SPACING * 5 + 4096,
+                              10 ** 9 + SPACING * 7])
+    assert vlct.vlct_step(g, fin, twin, 64, 0, 0, 128, need, 0) == vlct.VLCT_EINVAL
+    # just touching ranges are fine
+    touch = vlct.make_state([SPACING * 1 + 4096] + [10 ** 9 + SPACING * f for f in range(1, 8)])
+    assert vlct.vlct_step(g, fin, touch, 64, 0, 0, 0, need, 0) == vlct.VLCT_EWORKSPACE
 
 
 def test_noalloc_validation():
     """vlct_step_noalloc checks its arguments and the scratch size on the host,
     before it looks up the scratch or launches anything."""
     _lib()
-    fake = vlct.make_state([4096 * (f + 1) for f in range(8)])
+    fake = vlct.make_state([SPACING * (f + 1) for f in range(8)])
     assert vlct.vlct_step_noalloc(_grid(nx=0), fake, fake, 64, 0, 0, 0) == vlct.VLCT_EINVAL
     assert vlct.vlct_step_noalloc(_grid(), fake, fake, 0, 0, 0, 0) == vlct.VLCT_EINVAL
-    holey = vlct.make_state([4096 * (f + 1) for f in range(7)] + [0])
+    holey = vlct.make_state([SPACING * (f + 1) for f in range(7)] + [0])
     assert vlct.vlct_step_noalloc(_grid(), holey, fake, 64, 0, 0, 0) == vlct.VLCT_EINVAL
     big = _grid(nx=96, ny=96, nz=96)
     assert vlct.vlct_workspace_bytes(big) > vlct.VLCT_NOALLOC_SCRATCH_BYTES

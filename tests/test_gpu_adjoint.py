@@ -250,14 +250,19 @@ def test_adjoint_against_complex_step_of_the_oracle(cso, recon):
     assert worst <= 1e-10
 
 
+@pytest.mark.parametrize("admarch", [8, 16])
 @pytest.mark.parametrize("recon", [I.RECON_PLMC, I.RECON_PLMP, I.RECON_PPMC, I.RECON_PPMP])
-def test_adjoint_complex_step_multi_segment_grid(cso, recon):
+def test_adjoint_complex_step_multi_segment_grid(cso, recon, admarch, monkeypatch):
     """A 40 x 36 x 34 grid: rows longer than one block of the x-face kernel
-    and several 16-cell segments per column of the y and z marches (the
-    segment boundaries, the face a segment computes beyond its top cell).
+    and several segments per column of the y and z marches (the segment
+    boundaries, the face a segment computes beyond its top cell).  The size
+    rule would pick 8-cell segments for the linear reconstructions' fused
+    marches on a grid this small; the tile override (VLCT_TILES) runs both
+    the 8- and the 16-cell variant (the one large grids use).
     <lam_in, delta> against the complex step of the oracle along random
     directions, within 1e-10."""
     _need_gpu()
+    monkeypatch.setenv("VLCT_TILES", "admarch=%d" % admarch)
     g, s = _state((40, 36, 34), recon, 7)
     dt = ref.cfl_dt(g, s)
     lam = _random_cotangent(g, 3)

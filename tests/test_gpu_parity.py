@@ -152,6 +152,38 @@ def test_turbulence_multi_step(recon, nsteps):
     assert abs(nexts[-1] - nexts_ref[-1]) <= 1e-12 * nexts_ref[-1]
 
 
+TILE_VARIANTS = ["ct=4", "ct=8", "ct=16", "march=8", "march=16", "pred=1", "pred=3", "pred=8",
+                 "pred=64", "ct=16,march=16,pred=32"]
+
+
+@pytest.mark.parametrize("maker", ["turb_plmc", "turb_ppmc", "blast_ppmc"])
+def test_tile_variants_bitwise_equal(maker, monkeypatch):
+    """Every tile shape the size rules can choose -- CT blocks of 4, 8 or 16
+    planes, corrector marches of 8 or 16 faces, fused predictor blocks of 1 to
+    64 planes -- forced on one ragged grid (VLCT_TILES) gives bit for bit the
+    state and next dt of the default choice, which matches the oracle; grids
+    this small would otherwise only run the small-grid shapes."""
+    _need_gpu()
+    if maker == "turb_plmc":
+        g, s0 = I.turbulence((45, 38, 35))
+    elif maker == "turb_ppmc":
+        g, s0 = I.turbulence((45, 38, 35), recon=3)
+    else:
+        g, s0 = I.blast((41, 37, 36), b0=1.0, recon=3)
+    orc, dts, nexts_ref, st_ref = _oracle_run(g, s0, nsteps=4)
+    monkeypatch.delenv("VLCT_TILES", raising=False)
+    base, nb, stb = _gpu_run(g, s0, dts)
+    assert stb == st_ref
+    _check(g, s0, base, orc)
+    for v in TILE_VARIANTS:
+        monkeypatch.setenv("VLCT_TILES", v)
+        got, nv, stv = _gpu_run(g, s0, dts)
+        _say("%s: bitwise equal %s" % (v, all(np.array_equal(got[f], base[f]) for f in FIELDS)))
+        for f in FIELDS:
+            assert np.array_equal(got[f], base[f]), (v, f)
+        assert nv == nb and stv == stb, v
+
+
 @pytest.mark.parametrize("recon", [2, 3, 5])
 def test_blast_outflow_multi_step(recon):
     """Magnetised blast wave (beta = 0.2) with outflow boundaries on all faces."""
