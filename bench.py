@@ -22,29 +22,36 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP64 operations per face of a flux kernel (one reconstruction --
-# each cell's serves its two faces -- and one HLLD solve), counted by
-# paper_2402_05240_amd/csrc/flop_count.cpp (add/sub/mul/div/sqrt = 1 FLOP each,
-# mean over smooth random stencils).
-FLOPS_PER_FACE = {1: 291.0, 2: 663.0, 3: 1089.6, 4: 382.0, 5: 769.1}
+# Algorithmic FP64 operations per unit of the compute-heavy kernel families,
+# counted by paper_2402_05240_amd/csrc/flop_count.cpp (add/sub/mul/div/sqrt = 1
+# FLOP each, mean over smooth random stencils): a corrector face needs one
+# reconstruction (each cell's serves its two faces) and one HLLD solve; a
+# predictor cell three PCM HLLD solves plus its primitives, edge fields and
+# updates.
+FLOPS_PER_FACE = {1: 268.0, 2: 640.0, 3: 1067.0, 4: 359.0, 5: 746.1}
+FLOPS_PER_PRED_CELL = 999.0
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 F64 = 8
-# Algorithmic HBM bytes per unit of each kernel family (units: cells, or padded
-# cells for the primitive kernel):
-#   prims      reads 5 cell + 3 face fields, writes 8 primitives
-#   ct_update  reads 5 cell + 3 face fields, 3 axes x 8 flux components and
-#              6 primitives (v, B_cc for -v x B), writes 5 + 3 fields; the
-#              full update also evaluates the CFL condition of the new state
-#              from values it already holds (no further bytes)
-#   dt         reads 5 cell + 3 face fields (the CFL kernel of vlct_cfl_dt and
-#              of in-place steps)
-BYTES_PER_UNIT = {"prims": 16 * F64, "ct_update": 46 * F64, "dt": 8 * F64,
-                  "predictor": 16 * F64}
-# a fully fused step would move the state in and out once
+# The algorithmic minimum of the whole step (the scope's per-unit figure): read
+# U^n and write U^{n+1}, 8 + 8 doubles per cell update.
 STEP_MIN_BYTES_PER_CELL = 16 * F64
+# Design HBM bytes per unit of each kernel family as written (units: cells,
+# ghost cells for the ghost-layer primitive kernel):
+#   predictor  reads U^n (5 cell + 3 face fields), writes U^{n+1/2} (8) and
+#              the interior half-step primitives (8)
+#   prims      (ghost layers) reads 8 fields, writes 8 primitives
+#   ct_update  reads 5 cell + 3 face fields of U^n, 3 axes x 7 flux components
+#              and the upwind bytes, 6 primitives (v, B_cc for -v x B); writes
+#              5 + 3 fields (the CFL maxima of the new state cost no bytes)
+#   dt         reads 5 cell + 3 face fields (vlct_cfl_dt and in-place steps)
+#   flux_recon_hlld  8 primitives + normal field in, 7 flux components + the
+#              upwind byte out, per face
+BYTES_PER_UNIT = {"predictor": 24 * F64, "prims": 16 * F64, "ct_update": 43 * F64 + 3,
+                  "dt": 8 * F64, "flux_recon_hlld": 16 * F64 + 1, "flux_pcm_hlld": 16 * F64 + 1}
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "hbm_counters_turbulence_plmc_256.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "fp64_valu_turbulence_plmc_256.json")
 SOURCES = ("paper_2402_05240_amd/csrc/vlct.hip", "paper_2402_05240_amd/csrc/vlct_common.hpp",
            "paper_2402_05240_amd/csrc/mhd_physics.hpp", "paper_2402_05240_amd/build.py")
 
@@ -140,6 +147,41 @@ class KernelTimer:
         return out
 
 
+WORKLOAD_STEPS = {"turbulence_ppmc_256": 20, "blast_ppmc_512": 50, "linear_fast_32": 82}
+
+
+def workload_bench(name, warmup=3):
+    """Cell updates per second of one more workload: its run length (100 steps
+    of turbulence are timed as 20, the blast's 50 steps and the linear wave's
+    82-step period in full), dt chained on the device, with the bytes per
+    cell update the fused minimum implies."""
+    import torch
+    from paper_2402_05240_amd.device import Stepper
+    g, s0 = make_workload(name)
+    st = Stepper(g, device="cuda:0").upload(s0)
+    st.compute_dt()
+    for _ in range(warmup):
+        st.step()
+    steps = WORKLOAD_STEPS[name]
+    st.upload(s0)
+    del s0
+    st.compute_dt()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        st.step()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    value = g.ncells / (ms * 1e-3)
+    return {"grid": [g.nx, g.ny, g.nz], "reconstruction": RECON_NAMES[g.recon],
+            "bc": ["periodic" if x == 0 else "outflow" for x in g.bc], "steps": steps,
+            "ms_per_step": ms, "value": value, "unit": "cell updates/s",
+            "frac_hbm_min": STEP_MIN_BYTES_PER_CELL * value / (PEAK_HBM_GBS * 1e9),
+            "status": st.status_bits()}
+
+
 def make_workload(name):
     from paper_2402_05240_amd import inputs as I
     w = WORKLOADS[name]
@@ -182,26 +224,40 @@ def cpu_baseline(g, s, planes: int, steps: int, threads: int):
 HEADLINE_METRIC = "FP64 cell updates/s (PLMC+HLLD, 256^3); % HBM peak; adjoint/forward cost"
 
 
-def load_traffic(workload):
-    """Per-launch HBM bytes of each kernel family from the committed counter
-    summary, when it was taken on this workload with these kernel sources."""
+def _load_profile(path, workload):
+    """A committed counter summary, when it was taken on this workload with
+    these kernel sources (else {})."""
     try:
-        with open(COUNTERS_FILE) as f:
+        with open(path) as f:
             c = json.load(f)
     except (OSError, ValueError):
         return {}
     if c.get("source_sha256") != source_hash() or c.get("workload") != workload:
         return {}
-    return {k: v["traffic_bytes_per_launch"] for k, v in c.get("families", {}).items()}
+    return c.get("families", {})
+
+
+def load_traffic(workload):
+    """Per-launch HBM bytes of each kernel family (FETCH_SIZE + WRITE_SIZE)."""
+    return {k: v["traffic_bytes_per_launch"]
+            for k, v in _load_profile(COUNTERS_FILE, workload).items()}
+
+
+def load_valu(workload):
+    """Per-family FP64 VALU counters (instructions per launch, VALU busy)."""
+    return _load_profile(VALU_FILE, workload)
 
 
 def rooflines(g, kern, steps, workload=None):
     """Roofline of every kernel family, from the launches timed with HIP events
     on the library's stream: achieved = algorithmic work per launch / average
-    launch duration."""
+    launch duration, against the roof the family's counters say binds it (FP64
+    VALU issue when the VALU is busier than HBM is, else HBM bandwidth); with
+    no counters for these sources, the design's label."""
     ncell = g.ncells
-    npad = (g.nx + 6) * (g.ny + 6) * (g.nz + 6)
+    nghost = (g.nx + 6) * (g.ny + 6) * (g.nz + 6) - ncell
     traffic = load_traffic(workload) if workload else {}
+    valu = load_valu(workload) if workload else {}
     fam = {}
     for name, v in kern.items():
         key = "ct_update" if name in ("update_half", "update_full") else name
@@ -216,37 +272,159 @@ def rooflines(g, kern, steps, workload=None):
         if key == "dt_final":
             # one block reducing the CT blocks' CFL maxima: launch latency
             r.update({"bound": "latency", "achieved": None, "peak": None, "unit": None,
-                      "frac": None, "per_unit": "the maxima of the full update's blocks"})
-            r["bytes_per_step"] = 0.0
-            r["traffic"] = None
+                      "frac": None, "per_unit": "the maxima of the full update's blocks",
+                      "bytes_per_step": 0.0, "traffic": None})
             out[key] = r
             continue
-        if key in ("flux_recon_hlld", "flux_pcm_hlld"):
-            recon = g.recon if key == "flux_recon_hlld" else 1
-            # one axis' faces per launch (n faces per row of a periodic axis)
-            flops = FLOPS_PER_FACE[recon] * ncell
-            ach = flops / (avg_ms * 1e-3) / 1e12
-            r.update({"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS,
-                      "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS,
-                      "flops_per_launch": flops, "per_unit": "%.1f FLOP per face" %
-                      FLOPS_PER_FACE[recon]})
-            # HBM bytes of the flux kernels: 8 primitives + normal field in,
-            # 8 flux components out, per face
-            r["bytes_per_step"] = 17 * F64 * ncell * f["launches"] / steps
-        else:
-            units = npad if key == "prims" else ncell
-            nbytes = BYTES_PER_UNIT[key] * units
-            ach = nbytes / (avg_ms * 1e-3) / 1e9
-            r.update({"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                      "frac": ach / PEAK_HBM_GBS, "bytes_per_launch": nbytes,
-                      "per_unit": "%d B per %s" % (BYTES_PER_UNIT[key],
-                                                   "padded cell" if key == "prims" else "cell")})
-            r["bytes_per_step"] = nbytes * f["launches"] / steps
-        r["traffic"] = traffic.get(key)
-        if r["traffic"] is not None:
+        units = nghost if key == "prims" else ncell
+        nbytes = BYTES_PER_UNIT.get(key, 0) * units
+        flops = None
+        if key == "flux_recon_hlld":
+            flops = FLOPS_PER_FACE[g.recon] * ncell   # one axis' faces per launch
+        elif key == "flux_pcm_hlld":
+            flops = FLOPS_PER_FACE[1] * ncell
+        elif key == "predictor":
+            flops = FLOPS_PER_PRED_CELL * ncell
+        gbs = nbytes / (avg_ms * 1e-3) / 1e9
+        r["hbm_design"] = {"bytes_per_launch": nbytes, "achieved": gbs, "unit": "GB/s",
+                           "frac": gbs / PEAK_HBM_GBS,
+                           "per_unit": "%d B per %s" % (BYTES_PER_UNIT.get(key, 0),
+                                                        "ghost cell" if key == "prims" else
+                                                        ("face" if "flux" in key else "cell"))}
+        r["bytes_per_step"] = nbytes * f["launches"] / steps
+        if flops is not None:
+            tf = flops / (avg_ms * 1e-3) / 1e12
+            r["fp64_counted"] = {"flops_per_launch": flops, "achieved": tf, "unit": "TFLOP/s",
+                                 "frac": tf / PEAK_FP64_TFLOPS}
+        tr = traffic.get(key)
+        r["traffic"] = tr
+        if tr is not None:
             r["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"
+            r["traffic_frac"] = tr / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS
+        vc = valu.get(key)
+        if vc:
+            r["fp64_valu"] = vc
+        # the binding roof: from the counters when they exist
+        if vc and tr is not None:
+            bound = "alu" if vc["valu_busy"] >= r["traffic_frac"] else "hbm"
+            r["bound_from"] = "counters (VALU busy %.2f vs HBM traffic %.2f of peak)" % (
+                vc["valu_busy"], r["traffic_frac"])
+        else:
+            bound = "alu" if flops is not None else "hbm"
+            r["bound_from"] = "design label (no counters for these sources)"
+        if bound == "alu" and flops is not None:
+            r.update({"bound": "alu", "achieved": r["fp64_counted"]["achieved"],
+                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                      "frac": r["fp64_counted"]["frac"],
+                      "per_unit": "%.1f FLOP per %s" % (
+                          flops / ncell, "cell" if key == "predictor" else "face")})
+        else:
+            r.update({"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                      "frac": gbs / PEAK_HBM_GBS, "per_unit": r["hbm_design"]["per_unit"]})
         out[key] = r
     return out
+
+
+def step_roofline(rl, value, ncell, design_bytes):
+    """Whole-step HBM figures: algorithmic (128 B per cell update), design and
+    counted bytes per cell update, each as a fraction of the HBM peak at the
+    measured cell-update rate; and the counted FP64 VALU work per cell."""
+    out = {"bytes_per_cell_min": STEP_MIN_BYTES_PER_CELL,
+           "achieved_min": STEP_MIN_BYTES_PER_CELL * value / 1e9, "unit": "GB/s",
+           "frac_min": STEP_MIN_BYTES_PER_CELL * value / (PEAK_HBM_GBS * 1e9),
+           "bytes_per_cell_design": design_bytes,
+           "frac_design": design_bytes * value / (PEAK_HBM_GBS * 1e9)}
+    if all(r.get("traffic") is not None for k, r in rl.items() if k != "dt_final"):
+        tb = sum(r["traffic"] * r["launches_per_step"] for k, r in rl.items()
+                 if k != "dt_final") / ncell
+        out.update({"bytes_per_cell_counters": tb,
+                    "frac_counters": tb * value / (PEAK_HBM_GBS * 1e9)})
+    flops = [r["fp64_counted"]["flops_per_launch"] * r["launches_per_step"]
+             for r in rl.values() if "fp64_counted" in r]
+    if flops:
+        out["fp64_counted_flops_per_cell"] = sum(flops) / ncell
+        out["fp64_counted_frac"] = sum(flops) / ncell * value / (PEAK_FP64_TFLOPS * 1e12)
+    return out
+
+
+def summarize_valu(insts_csv, busy_csv, workload, commands, out_dir):
+    """rocprofv3 --pmc runs of FP64 VALU instruction counts (SQ_INSTS_VALU_*_F64,
+    SQ_INSTS_VALU, SQ_WAVES) and of VALU busy / utilisation / occupancy
+    (VALUBusy, VALUUtilization, MeanOccupancyPerActiveCU) -> per-family means
+    per launch (profiles/fp64_valu_<workload>.{json,md}), with the kernels'
+    VGPR, LDS and scratch sizes from the same records."""
+    import collections
+    import csv
+
+    def per_family(path):
+        vals = collections.defaultdict(lambda: collections.defaultdict(list))
+        res = {}
+        for r in csv.DictReader(open(path)):
+            k = kernel_family(r["Kernel_Name"])
+            if not k or k == "copy":
+                continue
+            vals[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+            res.setdefault(k, set()).add((r["Kernel_Name"].split("(")[0].replace("void ", ""),
+                                          int(r.get("VGPR_Count") or 0),
+                                          int(r.get("Accum_VGPR_Count") or 0),
+                                          int(r.get("LDS_Block_Size") or 0),
+                                          int(r.get("Scratch_Size") or 0),
+                                          int(r.get("Workgroup_Size") or 0)))
+        return vals, res
+    ins, kres = per_family(insts_csv)
+    busy, _ = per_family(busy_csv)
+    fams = {}
+    for k in ins:
+        m = {c: sum(v) / len(v) for c, v in ins[k].items()}
+        b = {c: sum(v) / len(v) for c, v in busy.get(k, {}).items()}
+        f64 = m.get("SQ_INSTS_VALU_FMA_F64", 0) + m.get("SQ_INSTS_VALU_ADD_F64", 0) + \
+            m.get("SQ_INSTS_VALU_MUL_F64", 0) + m.get("SQ_INSTS_VALU_TRANS_F64", 0)
+        fams[k] = {"valu_insts_per_launch": m.get("SQ_INSTS_VALU"),
+                   "fp64_insts_per_launch": f64,
+                   "fp64_fma_per_launch": m.get("SQ_INSTS_VALU_FMA_F64"),
+                   "fp64_trans_per_launch": m.get("SQ_INSTS_VALU_TRANS_F64"),
+                   "fp64_flops_per_launch": 64 * (2 * m.get("SQ_INSTS_VALU_FMA_F64", 0) +
+                                                  m.get("SQ_INSTS_VALU_ADD_F64", 0) +
+                                                  m.get("SQ_INSTS_VALU_MUL_F64", 0)),
+                   "fp64_share_of_valu": f64 / m["SQ_INSTS_VALU"] if m.get("SQ_INSTS_VALU") else None,
+                   "waves_per_launch": m.get("SQ_WAVES"),
+                   "valu_busy": b.get("VALUBusy", 0.0) / 100.0,
+                   "valu_lane_utilization": b.get("VALUUtilization", 0.0) / 100.0,
+                   "mean_occupancy_waves_per_cu": b.get("MeanOccupancyPerActiveCU"),
+                   "kernels": [{"name": n, "vgpr": v, "agpr": a, "lds_bytes": lds,
+                                "scratch_bytes": sc, "workgroup": wg}
+                               for n, v, a, lds, sc, wg in sorted(kres[k])]}
+    res = {"workload": workload, "source_sha256": source_hash(), "commands": commands,
+           "families": fams}
+    base = os.path.join(out_dir, "fp64_valu_%s" % workload)
+    with open(base + ".json", "w") as f:
+        json.dump(res, f, indent=1)
+    lines = ["# FP64 VALU counters per launch, %s" % workload, "",
+             "rocprofv3 --pmc runs (one per counter set):", ""] + \
+        ["    " + c for c in commands] + [
+        "", "Kernel sources sha256: `%s`" % res["source_sha256"], "",
+        "VALU busy: share of the kernel's time the CUs' vector ALUs issue (VALUBusy); "
+        "lane utilisation: active lanes per VALU instruction (VALUUtilization); FP64 FLOP "
+        "= 64 x (2 FMA + ADD + MUL) wave instructions.", "",
+        "| family | VALU insts | FP64 insts | FP64 share | FP64 GFLOP | VALU busy | lanes | "
+        "waves/CU | VGPR | LDS B | scratch B |", "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for k, v in sorted(fams.items()):
+        ks = v["kernels"][0] if v["kernels"] else {}
+        lines.append("| %s | %.3g | %.3g | %.2f | %.2f | %.2f | %.2f | %.1f | %s | %s | %s |" % (
+            k, v["valu_insts_per_launch"] or 0, v["fp64_insts_per_launch"],
+            v["fp64_share_of_valu"] or 0, v["fp64_flops_per_launch"] / 1e9, v["valu_busy"],
+            v["valu_lane_utilization"], v["mean_occupancy_waves_per_cu"] or 0,
+            ks.get("vgpr", "?"), ks.get("lds_bytes", "?"), ks.get("scratch_bytes", "?")))
+    lines += ["", "Kernels of each family (VGPRs, LDS and scratch per work-group from the "
+              "dispatch records):", ""]
+    for k, v in sorted(fams.items()):
+        for ks in v["kernels"]:
+            lines.append("- %s: `%s` VGPR %d, AGPR %d, LDS %d B, scratch %d B, work-group %d" % (
+                k, ks["name"], ks["vgpr"], ks["agpr"], ks["lds_bytes"], ks["scratch_bytes"],
+                ks["workgroup"]))
+    with open(base + ".md", "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return res
 
 
 def kernel_family(name):
@@ -264,6 +442,8 @@ def kernel_family(name):
                         else "adj_faces_pcm"
                 return fam
         return "adj_other"
+    if "k_pred" in name:
+        return "predictor"
     if "k_prims" in name:
         return "prims"
     if "k_ct_update" in name:
@@ -412,6 +592,57 @@ def ensemble_bench(count, steps, warmup):
     for _ in range(warmup):
         tbs.step()
     ms_tuned = timed(tbs.step, steps)
+    # config 4 proper: every instance to its own period, batched with
+    # per-instance retirement (vlct_step_batch_until) against the instances
+    # run one after another with the same clipped last step
+    periods = [T for _, _, T in ens]
+    ub = BatchStepper(grids, inplace=True).upload(states)
+    ub.compute_dt()
+    torch.cuda.synchronize()
+    ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ea.record()
+    nbatch = ub.run_until(periods)
+    eb.record()
+    torch.cuda.synchronize()
+    ms_until = ea.elapsed_time(eb)
+    until_out = ub.download()
+    del ub
+    seq = [Stepper(g, inplace=True) for g in grids]
+
+    def seq_run(counts=None):
+        found = []
+        for q, (st, s0, T) in enumerate(zip(seq, states, periods)):
+            st.upload(s0)
+            st.compute_dt()
+            t = torch.zeros(1, dtype=torch.float64, device="cuda")
+            te = torch.tensor([T], dtype=torch.float64, device="cuda")
+            n = 0
+            while (counts is None and float(t.item()) < T) or (counts is not None and n < counts[q]):
+                dte = torch.minimum(st.dt, te - t)
+                st.dt.copy_(dte)
+                st.step()
+                t += dte
+                n += 1
+            found.append(n)
+        return found
+    counts = seq_run()          # untimed: each instance's step count
+    torch.cuda.synchronize()
+    ea.record()
+    seq_run(counts)             # timed: the same steps with no host round trip
+    eb.record()
+    torch.cuda.synchronize()
+    ms_seq_until = ea.elapsed_time(eb)
+    same_until = all(np.array_equal(o[f], st.download()[f]) for o, st in zip(until_out, seq)
+                     for f in I.FIELDS)
+    cell_steps = sum(g.ncells * n for g, n in zip(grids, counts))
+    to_period = {"batched_until": {"ms": ms_until, "batched_steps": nbatch,
+                                   "cell_updates_per_s": cell_steps / (ms_until * 1e-3)},
+                 "sequential": {"ms": ms_seq_until,
+                                "cell_updates_per_s": cell_steps / (ms_seq_until * 1e-3)},
+                 "steps_per_instance": {"min": min(counts), "max": max(counts),
+                                        "total": sum(counts)},
+                 "speedup": ms_seq_until / ms_until, "bitwise_equal": bool(same_until)}
+    del seq
     hist = {}
     for p in plan:
         key = "ct%dx%d_march%d" % ((64, 32, 16)[p & 15], (8, 16, 32)[p & 15], (16, 32, 8)[p >> 4])
@@ -431,7 +662,7 @@ def ensemble_bench(count, steps, warmup):
             "batched_tuned": {"ms_per_step": ms_tuned,
                               "cell_updates_per_s": ncell / (ms_tuned * 1e-3), "plan": hist},
             "speedup": ms_seq / ms_batch, "speedup_tuned": ms_seq / ms_tuned,
-            "bitwise_equal": bool(same)}
+            "bitwise_equal": bool(same), "to_one_period": to_period}
 
 
 RECON_NAMES = {1: "PCM", 2: "PLMC", 3: "PPMC", 4: "PLMP", 5: "PPMP"}
@@ -577,6 +808,9 @@ def main():
     ap.add_argument("--adjoint-recon", default="plmc",
                     choices=["pcm", "plmc", "ppmc", "plmp", "ppmp"],
                     help="corrector reconstruction of the adjoint cost measurement")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the other workloads (PPMC turbulence 256^3, blast 512^3, linear "
+                         "wave 32^3)")
     ap.add_argument("--cpu-planes", type=int, default=256)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--cpu-threads", type=int, default=0)
@@ -586,6 +820,9 @@ def main():
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/hbm_counters_<workload>.{json,md} from the two "
                          "rocprofv3 --pmc runs (no GPU needed)")
+    ap.add_argument("--summarize-valu", nargs=2, metavar=("INSTS_CSV", "BUSY_CSV"),
+                    help="write profiles/fp64_valu_<workload>.{json,md} from the two rocprofv3 "
+                         "--pmc runs of FP64 VALU counters (no GPU needed)")
     ap.add_argument("--summarize-trace", metavar="KERNEL_STATS_CSV",
                     help="write profiles/kernel_trace_<workload>.md (no GPU needed)")
     ap.add_argument("--trace-name", default=None,
@@ -593,13 +830,16 @@ def main():
     ap.add_argument("--commands", nargs="*", default=[],
                     help="the rocprofv3 command lines the summarised files came from")
     args = ap.parse_args()
-    if args.summarize_counters or args.summarize_trace:
+    if args.summarize_counters or args.summarize_trace or args.summarize_valu:
         out_dir = os.path.join(ROOT, "profiles")
         os.makedirs(out_dir, exist_ok=True)
         if args.summarize_counters:
             summarize_counters(args.summarize_counters[0], args.summarize_counters[1],
                                int(args.copy_calibration_gib * (1 << 30)) or (1 << 30),
                                args.workload, args.commands[:2], out_dir)
+        if args.summarize_valu:
+            summarize_valu(args.summarize_valu[0], args.summarize_valu[1], args.workload,
+                           args.commands[:2], out_dir)
         if args.summarize_trace:
             summarize_trace(args.summarize_trace, args.trace_name or args.workload,
                             args.commands[-1] if args.commands else "", out_dir)
@@ -680,16 +920,14 @@ def main():
                    "reconstruction": recon_name, "riemann": "HLLD", "integrator": "VL+CT",
                    "bc": ["periodic" if b == 0 else "outflow" for b in g.bc], "cfl": g.cfl,
                    "gamma": g.gamma},
+        # the dominant kernel family (most time per step) against the roof
+        # its counters say binds it
         "roofline": rl[dom],
         "rooflines": rl,
-        # whole step against the HBM roofline: as a fused step would move it
-        # (state in and out once) and as this design's kernels move it
-        "step_hbm": {"bytes_per_cell_min": STEP_MIN_BYTES_PER_CELL,
-                     "frac_min": STEP_MIN_BYTES_PER_CELL * value / (PEAK_HBM_GBS * 1e9),
-                     "bytes_per_cell_design": design_bytes,
-                     "frac_design_lower_bound": design_bytes * value / (PEAK_HBM_GBS * 1e9),
-                     "note": "design bytes count the compute-bound flux kernels' reads and "
-                             "writes as well"},
+        # the whole step against the HBM roofline: the scope's algorithmic
+        # bytes (state in and out once, 128 B per cell update), the bytes this
+        # design's kernels are written to move, and what the HBM counters saw
+        "step_roofline": step_roofline(rl, value, ncell, design_bytes),
         "adjoint_forward_cost": None,
         "kernels_ms_per_step": {k: v["total_ms"] / args.steps for k, v in kern.items()},
         "wall_ms_per_step": (w1 - w0) * 1e3 / args.steps,
@@ -708,10 +946,20 @@ def main():
     if not args.no_ensemble:
         torch.cuda.empty_cache()
         out["ensemble"] = ensemble_bench(64, args.ensemble_steps, 2)
+    if not args.no_workloads:
+        torch.cuda.empty_cache()
+        out["workloads"] = {}
+        for name in ("turbulence_ppmc_256", "blast_ppmc_512", "linear_fast_32"):
+            if name != args.workload:
+                out["workloads"][name] = workload_bench(name)
+                torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         torch.cuda.empty_cache()
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(g, s0, args.cpu_planes, args.cpu_steps, threads)
+        # the same oracle on one host thread, on a thinner slab of the same state
+        one = cpu_baseline(g, s0, max(1, args.cpu_planes // 16), args.cpu_steps, 1)
+        out["cpu_baseline"]["one_thread"] = one
     print(json.dumps(out), flush=True)
 
 

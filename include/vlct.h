@@ -173,6 +173,25 @@ int vlct_step_batch_plan(int count, const vlct_grid *grids, const vlct_state *in
                          uint32_t *status_dev, const uint8_t *plan, void *ws, size_t ws_bytes,
                          void *stream);
 
+/* Ensembles with per-instance end times (each run to its own t_end): one step
+ * of vlct_step_batch_plan for every instance still running, in place
+ * (states[i] is both input and output).  Instance i is running while
+ * t_dev[i] < t_end_dev[i]; it then advances by min(dt_dev[i],
+ * t_end_dev[i] - t_dev[i]) (its last step clipped to land on t_end), writes
+ * its next CFL step to next_dt_dev[i] and adds the step to t_dev[i].  A
+ * finished instance's blocks return at once in every kernel, so it costs
+ * almost nothing while the others continue, and its state, time and dt stay
+ * as they are.  t_dev (device, read and written), t_end_dev (device, read),
+ * next_dt_dev (device, required: VLCT_EINVAL if NULL); the other arguments
+ * as for vlct_step_batch_plan.  Everything happens on the device, so a loop of
+ * these calls needs no host synchronisation (check t_dev now and then).  An
+ * instance's result is bitwise that of vlct_step applied with the same clip
+ * (dt = min(dt, t_end - t), t += dt). */
+int vlct_step_batch_until(int count, const vlct_grid *grids, const vlct_state *states,
+                          const double *dt_dev, double *next_dt_dev, uint32_t *status_dev,
+                          double *t_dev, const double *t_end_dev, const uint8_t *plan, void *ws,
+                          size_t ws_bytes, void *stream);
+
 /* Autotuner for a batch: writes into plan[count] (host) the tiles that make
  * the batched step fastest, found by timing it on this batch: instances are
  * grouped by nx (<= 24, <= 48, <= 96, larger) and each group's CT tile, then

@@ -136,6 +136,13 @@ int main()
                 double(hlld_r) / N);
     std::printf("adj_march_fused_plmc_per_cell %.1f\n",
                 double(plmc_f + hlld_r + plmc_r) / N);
+    // fused predictor, per cell: three PCM HLLD solves (its low x-, y- and
+    // z-faces) and, counted by hand from the kernel's source, 195 more:
+    // primitives 27 (B_cc 6, one division, v 3, kinetic 7, magnetic 6,
+    // pressure 4), reference field 9, three edge fields 3 x 17 (mean 4, four
+    // upwind terms 8, sum 5), cell update 5 x 9, face update 3 x 6, and the
+    // half-step primitives 45 (three high faces 18, B_cc 6, the rest 21)
+    std::printf("predictor_per_cell %.1f\n", 3.0 * double(hlld_f) / N + 195.0);
     std::printf("ppmc_rev_per_call %.1f\nppmp_rev_per_call %.1f\n", double(ppmc_r) / N,
                 double(ppmp_r) / N);
     std::printf("adj_faces_ppmc_per_face %.1f (cell-parallel: %.1f)\n",

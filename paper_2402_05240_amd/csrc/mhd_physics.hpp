@@ -118,18 +118,17 @@ VLCT_DEV void hlld(const W7 &L, const W7 &R, double bn, double gam, double gm1i,
     const double sM = (qR * R.u - qL * L.u - ptR + ptL) * iq;
     const double pts = (qR * ptL - qL * ptR + qL * qR * (R.u - L.u)) * iq;
 
-    // single-star states of both sides
-    double ds[2], vs[2], ws[2], bys[2], bzs[2], vbs[2], es[2];
+    // single-star states of both sides (the energy only where it is used,
+    // on the side whose fan contains x/t = 0)
+    double ds[2], vs[2], ws[2], bys[2], bzs[2], issm[2];
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
         const W7 &X = a == 0 ? L : R;
         const double S = a == 0 ? sL : sR;
-        const double pt = a == 0 ? ptL : ptR;
-        const double e = a == 0 ? eL : eR;
         const double su = S - X.u;
         const double ssm = S - sM;
-        const double issm = 1.0 / ssm;
-        ds[a] = X.d * su * issm;
+        issm[a] = 1.0 / ssm;
+        ds[a] = X.d * su * issm[a];
         const double den = X.d * su * ssm - bn2;
         const bool degen = fabs(den) < kHlldDegen * pts;
         const double iden = 1.0 / den;
@@ -139,9 +138,6 @@ VLCT_DEV void hlld(const W7 &L, const W7 &R, double bn, double gam, double gm1i,
         ws[a] = X.w - X.bz * t1;
         bys[a] = X.by * t2;
         bzs[a] = X.bz * t2;
-        vbs[a] = sM * bn + vs[a] * bys[a] + ws[a] * bzs[a];
-        const double vb = X.u * bn + X.v * X.by + X.w * X.bz;
-        es[a] = (su * e - pt * X.u + pts * sM + bn * (vb - vbs[a])) * issm;
     }
     // double-star states (shared by both sides)
     const double sg = bn >= 0.0 ? 1.0 : -1.0;
@@ -161,14 +157,19 @@ VLCT_DEV void hlld(const W7 &L, const W7 &R, double bn, double gam, double gm1i,
     const double pt = left ? ptL : ptR;
     const double e = left ? eL : eR;
     const double r = left ? rL : rR;
-    const double ss = left ? sM - fabs(bn) / rL : sM + fabs(bn) / rR;
+    const double car = fabs(bn) / r;
+    const double ss = left ? sM - car : sM + car;
     const bool star_only = left ? (ss >= 0.0) : (ss <= 0.0);
-    const double ess = left ? es[0] - r * sg * (vbs[0] - vbss) : es[1] + r * sg * (vbs[1] - vbss);
+    // its single-star energy and the double-star correction
+    const double vbs = sM * bn + vs[a] * bys[a] + ws[a] * bzs[a];
+    const double vbx = X.u * bn + X.v * X.by + X.w * X.bz;
+    const double esa = ((S - X.u) * e - pt * X.u + pts * sM + bn * (vbx - vbs)) * issm[a];
+    const double ess = left ? esa - r * sg * (vbs - vbss) : esa + r * sg * (vbs - vbss);
     const bool outer = left ? (sL > 0.0) : (sR < 0.0);
     const double cS = outer ? 0.0 : S;
     const double cSS = (outer || star_only) ? 0.0 : ss;
 
-    const double vb = X.u * bn + X.v * X.by + X.w * X.bz;
+    const double vb = vbx;
     const double mu = X.d * X.u;
     // physical flux F(W) of the chosen side (Sec. 2.1, sweep frame)
     const double F0 = mu;
@@ -184,12 +185,12 @@ VLCT_DEV void hlld(const W7 &L, const W7 &R, double bn, double gam, double gm1i,
     const double dU1 = dsa * sM - mu;
     const double dU2 = dsa * vs[a] - X.d * X.v;
     const double dU3 = dsa * ws[a] - X.d * X.w;
-    const double dU4 = es[a] - e;
+    const double dU4 = esa - e;
     const double dU5 = bys[a] - X.by;
     const double dU6 = bzs[a] - X.bz;
     const double dV2 = dsa * (vss - vs[a]);
     const double dV3 = dsa * (wss - ws[a]);
-    const double dV4 = ess - es[a];
+    const double dV4 = ess - esa;
     const double dV5 = byss - bys[a];
     const double dV6 = bzss - bzs[a];
     f[0] = F0 + cS * dU0;

@@ -81,17 +81,38 @@ __host__ __device__ __forceinline__ idx_t nblk_dt(const Geom &g)
 // primitive variables on the ghost-padded grid (Sec. 2.1; B_cc = face average,
 // Step 1); the boundary conditions are applied here by index mapping
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void prims_body(const Geom &g, const StateP &s, const Prims &P,
-                                           uint32_t *status, idx_t b)
+// primitives of one cell from its conserved variables u and cell-centred
+// field, floored (the conserved state is never changed), stored at padded
+// index o; returns the floor status bits
+__device__ __forceinline__ uint32_t prims_store(const Geom &g, const Prims &P, idx_t o,
+                                                const double u[5], double bcx, double bcy,
+                                                double bcz)
 {
-    const idx_t tot = (idx_t)g.p[0] * g.p[1] * g.p[2];
-    const idx_t t = b * kBlock + threadIdx.x;
-    if (t >= tot) return;
-    const int pi = (int)(t % g.p[0]);
-    const idx_t r = t / g.p[0];
-    const int pj = (int)(r % g.p[1]);
-    const int pk = (int)(r / g.p[1]);
-    const int i = pi - kGhost, j = pj - kGhost, k = pk - kGhost;
+    double d = u[0];
+    uint32_t st = 0;
+    if (!(d >= kFloorRho)) { d = kFloorRho; st |= kStatusDensityFloor; }
+    const double id = 1.0 / d;
+    const double vx = u[1] * id, vy = u[2] * id, vz = u[3] * id;
+    const double ke = 0.5 * d * (vx * vx + vy * vy + vz * vz);
+    const double me = 0.5 * (bcx * bcx + bcy * bcy + bcz * bcz);
+    double pr = (g.gamma - 1.0) * (u[4] - ke - me);
+    if (!(pr >= kFloorP)) { pr = kFloorP; st |= kStatusPressureFloor; }
+    P.w[0][o] = d;
+    P.w[1][o] = vx;
+    P.w[2][o] = vy;
+    P.w[3][o] = vz;
+    P.w[4][o] = pr;
+    P.w[5][o] = bcx;
+    P.w[6][o] = bcy;
+    P.w[7][o] = bcz;
+    return st;
+}
+
+// primitives of padded cell (i, j, k), i, j, k in [-G, n + G - 1], with the
+// boundary conditions applied by index mapping
+__device__ __forceinline__ uint32_t prims_cell(const Geom &g, const StateP &s, const Prims &P,
+                                               int i, int j, int k)
+{
     const int mi = map_cell(i, g.n[0], g.bc[0]);
     const int mj = map_cell(j, g.n[1], g.bc[1]);
     const int mk = map_cell(k, g.n[2], g.bc[2]);
@@ -102,28 +123,62 @@ __device__ __forceinline__ void prims_body(const Geom &g, const StateP &s, const
     const double by1 = s.b[1][face_store(g, 1, mi, map_face(j + 1, g.n[1], g.bc[1]), mk)];
     const double bz0 = s.b[2][face_store(g, 2, mi, mj, map_face(k, g.n[2], g.bc[2]))];
     const double bz1 = s.b[2][face_store(g, 2, mi, mj, map_face(k + 1, g.n[2], g.bc[2]))];
-    const double bcx = 0.5 * (bx0 + bx1);
-    const double bcy = 0.5 * (by0 + by1);
-    const double bcz = 0.5 * (bz0 + bz1);
-    double d = s.u[0][c];
-    uint32_t st = 0;
-    if (!(d >= kFloorRho)) { d = kFloorRho; st |= kStatusDensityFloor; }
-    const double id = 1.0 / d;
-    const double vx = s.u[1][c] * id, vy = s.u[2][c] * id, vz = s.u[3][c] * id;
-    const double ke = 0.5 * d * (vx * vx + vy * vy + vz * vz);
-    const double me = 0.5 * (bcx * bcx + bcy * bcy + bcz * bcz);
-    double pr = (g.gamma - 1.0) * (s.u[4][c] - ke - me);
-    if (!(pr >= kFloorP)) { pr = kFloorP; st |= kStatusPressureFloor; }
+    const double u[5] = {s.u[0][c], s.u[1][c], s.u[2][c], s.u[3][c], s.u[4][c]};
+    return prims_store(g, P, pidx(g, i, j, k), u, 0.5 * (bx0 + bx1), 0.5 * (by0 + by1),
+                       0.5 * (bz0 + bz1));
+}
+
+__device__ __forceinline__ void prims_body(const Geom &g, const StateP &s, const Prims &P,
+                                           uint32_t *status, idx_t b)
+{
+    const idx_t tot = (idx_t)g.p[0] * g.p[1] * g.p[2];
+    const idx_t t = b * kBlock + threadIdx.x;
+    if (t >= tot) return;
+    const int pi = (int)(t % g.p[0]);
+    const idx_t r = t / g.p[0];
+    const int pj = (int)(r % g.p[1]);
+    const int pk = (int)(r / g.p[1]);
+    const uint32_t st = prims_cell(g, s, P, pi - kGhost, pj - kGhost, pk - kGhost);
     if (st && status) atomicOr(status, st);
-    const idx_t o = t;
-    P.w[0][o] = d;
-    P.w[1][o] = vx;
-    P.w[2][o] = vy;
-    P.w[3][o] = vz;
-    P.w[4][o] = pr;
-    P.w[5][o] = bcx;
-    P.w[6][o] = bcy;
-    P.w[7][o] = bcz;
+}
+
+// ghost layers only: the padded cells outside the grid, enumerated as the
+// z-ghost planes, then the y-ghost rows of interior planes, then the x-ghost
+// cells of interior rows
+__host__ __device__ __forceinline__ idx_t ghost_cells(const Geom &g)
+{
+    return (idx_t)g.p[0] * g.p[1] * g.p[2] - (idx_t)g.n[0] * g.n[1] * g.n[2];
+}
+
+__device__ __forceinline__ void prims_ghost_body(const Geom &g, const StateP &s, const Prims &P,
+                                                 uint32_t *status, idx_t b)
+{
+    const idx_t t = b * kBlock + threadIdx.x;
+    if (t >= ghost_cells(g)) return;
+    const int px = g.p[0], py = g.p[1], G2 = 2 * kGhost;
+    const idx_t n1 = (idx_t)G2 * px * py, n2 = (idx_t)g.n[2] * G2 * px;
+    int i, j, k;
+    if (t < n1) {
+        const int q = (int)(t / ((idx_t)px * py));
+        const idx_t r = t % ((idx_t)px * py);
+        k = q < kGhost ? q - kGhost : g.n[2] + q - kGhost;
+        j = (int)(r / px) - kGhost;
+        i = (int)(r % px) - kGhost;
+    } else if (t < n1 + n2) {
+        const idx_t r = t - n1;
+        k = (int)(r / ((idx_t)G2 * px));
+        const int q = (int)((r / px) % G2);
+        j = q < kGhost ? q - kGhost : g.n[1] + q - kGhost;
+        i = (int)(r % px) - kGhost;
+    } else {
+        const idx_t r = t - n1 - n2;
+        k = (int)(r / ((idx_t)g.n[1] * G2));
+        j = (int)((r / G2) % g.n[1]);
+        const int q = (int)(r % G2);
+        i = q < kGhost ? q - kGhost : g.n[0] + q - kGhost;
+    }
+    const uint32_t st = prims_cell(g, s, P, i, j, k);
+    if (st && status) atomicOr(status, st);
 }
 
 // sweep-frame state of a padded cell for axis D
@@ -171,7 +226,7 @@ __device__ __forceinline__ void flux_pcm_body(const Geom &g, const StateP &s, co
     if (st && status) atomicOr(status, st);
 #pragma unroll
     for (int c = 0; c < 7; ++c) F.f[D][c][t] = f[c];
-    F.f[D][7][t] = upw;
+    F.sg[D][t] = (int8_t)upw;
 }
 
 // ---------------------------------------------------------------------------
@@ -249,7 +304,7 @@ __device__ __forceinline__ void recon_x_body(const Geom &g, const StateP &s, con
         const idx_t o = fidx(g, 0, c, j, k);
 #pragma unroll
         for (int v = 0; v < 7; ++v) F.f[0][v][o] = f[v];
-        F.f[0][7][o] = upw;
+        F.sg[0][o] = (int8_t)upw;
     }
     if (st && status) atomicOr(status, st);
 }
@@ -319,7 +374,7 @@ __device__ __forceinline__ void march_body(const Geom &g, const StateP &s, const
             const idx_t o = fidx(g, D, q[0], q[1], q[2]);
 #pragma unroll
             for (int v = 0; v < 7; ++v) F.f[D][v][o] = f[v];
-            F.f[D][7][o] = upw;
+            F.sg[D][o] = (int8_t)upw;
         }
         prev = fp;
         if (c + 1 < s1) {
@@ -394,8 +449,8 @@ __device__ __forceinline__ double edge_emf(const Geom &g, const Flux &F, int i, 
     // B-face EMF component A = -F_B[B_t1]; C-face EMF component A = +F_C[B_t2]
     const double eb_c = -F.f[B][5][fb_c], eb_cm = -F.f[B][5][fb_cm];
     const double ec_b = F.f[C][6][fc_b], ec_bm = F.f[C][6][fc_bm];
-    const double sb_c = F.f[B][7][fb_c], sb_cm = F.f[B][7][fb_cm];
-    const double sc_b = F.f[C][7][fc_b], sc_bm = F.f[C][7][fc_bm];
+    const double sb_c = F.sg[B][fb_c], sb_cm = F.sg[B][fb_cm];
+    const double sc_b = F.sg[C][fc_b], sc_bm = F.sg[C][fc_bm];
     const double avg = 0.25 * (eb_c + eb_cm + ec_b + ec_bm);
     const double t1 = upwind(sb_c, ec_bm - r10, ec_b - r00);
     const double t2 = upwind(sb_cm, ec_bm - r11, ec_b - r01);
@@ -663,11 +718,15 @@ __device__ __forceinline__ double edge_value(double eb_c, double eb_cm, double e
     return avg + 0.25 * (t1 + t2 + t3 + t4);
 }
 
-// TAPE: also writes the upwind side of every interior face (tape layout)
-template <int TX, int TY, bool TAPE>
+// side0..2 (optional): the upwind side of every interior face, tape layout;
+// P (optional, P.w[0] == NULL skips it): the half-step primitives of the
+// interior cells are written there as k_prims would derive them from
+// U^{n+1/2}; its ghost layers are left to k_prims_ghost.  Both are run-time
+// choices of one kernel, so a taped step runs the very code of a plain one.
+template <int TX, int TY>
 __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const StateW &out,
-                                          const double *dt_dev, uint32_t *status, idx_t b,
-                                          uint8_t *side0, uint8_t *side1, uint8_t *side2)
+                                          const Prims &P, const double *dt_dev, uint32_t *status,
+                                          idx_t b, uint8_t *side0, uint8_t *side1, uint8_t *side2)
 {
     using S = PredShape<TX, TY>;
     constexpr int CX = S::CX, CY = S::CY, NC = S::NC;
@@ -721,30 +780,44 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
     double hx[5] = {}, hy[5] = {};  // own x-, y-face hydro fluxes of the previous plane
     double hz_lo[5] = {};           // own z-face hydro flux below the previous plane
 
+    // U^n of this thread's cell in a plane: 5 conserved values and the six faces
+    double pf[11];
+    auto load_plane = [&](int m) {
+        const int mk = map_cell(m, nz, g.bc[2]);
+        const idx_t cc = cell_store(g, mi, mj, mk);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) pf[q] = s.u[q][cc];
+        pf[5] = s.b[0][face_store(g, 0, fi0, mj, mk)];
+        pf[6] = s.b[0][face_store(g, 0, fi1, mj, mk)];
+        pf[7] = s.b[1][face_store(g, 1, mi, fj0, mk)];
+        pf[8] = s.b[1][face_store(g, 1, mi, fj1, mk)];
+        pf[9] = s.b[2][face_store(g, 2, mi, mj, map_face(m, nz, g.bc[2]))];
+        pf[10] = s.b[2][face_store(g, 2, mi, mj, map_face(m + 1, nz, g.bc[2]))];
+    };
+
     for (int m = k0 - 1; m <= k1; ++m) {
         const int sm = m & 1, sp = sm ^ 1;
         // (A) primitives and reference field of plane m; the cell's low faces
         // are also the normal fields of the faces this thread solves in (B)
         double bx0 = 0.0, by0 = 0.0, bz0 = 0.0;
         if (live) {
-            const int mk = map_cell(m, nz, g.bc[2]);
-            const idx_t cc = cell_store(g, mi, mj, mk);
-            bx0 = s.b[0][face_store(g, 0, fi0, mj, mk)];
-            const double bx1 = s.b[0][face_store(g, 0, fi1, mj, mk)];
-            by0 = s.b[1][face_store(g, 1, mi, fj0, mk)];
-            const double by1 = s.b[1][face_store(g, 1, mi, fj1, mk)];
-            bz0 = s.b[2][face_store(g, 2, mi, mj, map_face(m, nz, g.bc[2]))];
-            const double bz1 = s.b[2][face_store(g, 2, mi, mj, map_face(m + 1, nz, g.bc[2]))];
+            load_plane(m);
+            bx0 = pf[5];
+            const double bx1 = pf[6];
+            by0 = pf[7];
+            const double by1 = pf[8];
+            bz0 = pf[9];
+            const double bz1 = pf[10];
             const double bcx = 0.5 * (bx0 + bx1);
             const double bcy = 0.5 * (by0 + by1);
             const double bcz = 0.5 * (bz0 + bz1);
-            double d = s.u[0][cc];
+            double d = pf[0];
             if (!(d >= kFloorRho)) { d = kFloorRho; st |= kStatusDensityFloor; }
             const double id = 1.0 / d;
-            const double vx = s.u[1][cc] * id, vy = s.u[2][cc] * id, vz = s.u[3][cc] * id;
+            const double vx = pf[1] * id, vy = pf[2] * id, vz = pf[3] * id;
             const double ke = 0.5 * d * (vx * vx + vy * vy + vz * vz);
             const double me = 0.5 * (bcx * bcx + bcy * bcy + bcz * bcz);
-            double pr = (g.gamma - 1.0) * (s.u[4][cc] - ke - me);
+            double pr = (g.gamma - 1.0) * (pf[4] - ke - me);
             if (!(pr >= kFloorP)) { pr = kFloorP; st |= kStatusPressureFloor; }
             s_wh[0][t] = d;
             s_wh[1][t] = vx;
@@ -775,7 +848,6 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
                 s_em[sm][0][t] = -f[5];
                 s_em[sm][1][t] = f[6];
                 s_sg[sm][0][t] = (int8_t)upw;
-                if (TAPE && interior && m >= k0 && m < k1) side0[cell_store(g, ii, jj, m)] = side_code(upw);
             }
             if (do_y) {
                 const int l = t - CX;
@@ -787,7 +859,6 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
                 s_em[sm][2][t] = -f[5];
                 s_em[sm][3][t] = f[6];
                 s_sg[sm][1][t] = (int8_t)upw;
-                if (TAPE && interior && m >= k0 && m < k1) side1[cell_store(g, ii, jj, m)] = side_code(upw);
             }
             if (do_z && m >= k0) {
                 hlld(wz_prev, wz, bz0, g.gamma, g.gm1i, f, upw);
@@ -796,12 +867,31 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
                 s_zem[0][t] = -f[5];
                 s_zem[1][t] = f[6];
                 s_zsg[t] = (int8_t)upw;
-                if (TAPE && interior && m < k1) side2[cell_store(g, ii, jj, m)] = side_code(upw);
             }
         }
         __syncthreads();
         // (C) E_z of plane m, E_x / E_y of the half plane m - 1/2; the hydro
-        // fluxes of plane m - 1 go to LDS for the neighbours' updates
+        // fluxes of plane m - 1 go to LDS for the neighbours' updates.  The
+        // U^n values the update of plane m - 1 in (D) starts from are loaded
+        // first, so that their latency hides behind the edge computations.
+        const bool upd = m - 1 >= k0 && m - 1 < k1;
+        double u0[5] = {}, bxb = 0.0, byb = 0.0, bzb = 0.0, bxh = 0.0, byh = 0.0, bzh = 0.0;
+        if (upd && own) {
+            const int k = m - 1;
+            if (interior) {
+                const idx_t cc = cell_store(g, ii, jj, k);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) u0[q] = s.u[q][cc];
+                bzb = s.b[2][face_store(g, 2, ii, jj, k)];
+                if (P.w[0]) {
+                    bxh = s.b[0][face_store(g, 0, map_face(ii + 1, nx, g.bc[0]), jj, k)];
+                    byh = s.b[1][face_store(g, 1, ii, map_face(jj + 1, ny, g.bc[1]), k)];
+                    bzh = s.b[2][face_store(g, 2, ii, jj, map_face(k + 1, nz, g.bc[2]))];
+                }
+            }
+            if (jj < ny) bxb = s.b[0][face_store(g, 0, ii, jj, k)];
+            if (ii < nx) byb = s.b[1][face_store(g, 1, ii, jj, k)];
+        }
         if (m >= k0) {
             const int nez = m < k1 ? NEZ : 0;
             for (int q = threadIdx.x; q < nez + NEX + NEY; q += S::NT) {
@@ -840,7 +930,6 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
                 }
             }
         }
-        const bool upd = m - 1 >= k0 && m - 1 < k1;
         if (upd && live) {
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
@@ -848,11 +937,23 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
                 s_wh[5 + q][t] = hy[q];
             }
         }
+        // the tape: upwind sides of the interior cell's low faces in plane m
+        if (side0 && interior && m >= k0 && m < k1) {
+            const idx_t cc = cell_store(g, ii, jj, m);
+            side0[cc] = side_code(s_sg[sm][0][t]);
+            side1[cc] = side_code(s_sg[sm][1][t]);
+            side2[cc] = side_code(s_zsg[t]);
+        }
         __syncthreads();
-        // (D) half-step update of plane k = m - 1 (Step 5)
+        // (D) half-step update of plane k = m - 1 (Step 5); an interior cell
+        // also derives its half-step primitives (for the corrector), with its
+        // high faces recomputed from the same edge fields and in the same
+        // arithmetic as the threads or blocks that own them
         if (upd && own) {
             const int k = m - 1;
             const int lo = sp, hi = sm;  // half planes k - 1/2 and k + 1/2
+            const int ke = k & 1;        // E_z slot of plane k
+            double u[5] = {}, bxl = 0.0, byl = 0.0, bzl = 0.0;
             if (interior) {
                 const idx_t cc = cell_store(g, ii, jj, k);
                 const double dxr = s_wh[0][t + 1] - hx[0];
@@ -870,33 +971,45 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
                 const double dzmz = hzn[1] - hz_lo[1];
                 const double dzmx = hzn[2] - hz_lo[2];
                 const double dzmy = hzn[3] - hz_lo[3];
-                out.u[0][cc] = s.u[0][cc] - cx * dxr - cy * dyr - cz * dzr;
-                out.u[1][cc] = s.u[1][cc] - cx * dxmx - cy * dymx - cz * dzmx;
-                out.u[2][cc] = s.u[2][cc] - cx * dxmy - cy * dymy - cz * dzmy;
-                out.u[3][cc] = s.u[3][cc] - cx * dxmz - cy * dymz - cz * dzmz;
-                out.u[4][cc] = s.u[4][cc] - cx * dxe - cy * dye - cz * dze;
+                u[0] = u0[0] - cx * dxr - cy * dyr - cz * dzr;
+                u[1] = u0[1] - cx * dxmx - cy * dymx - cz * dzmx;
+                u[2] = u0[2] - cx * dxmy - cy * dymy - cz * dzmy;
+                u[3] = u0[3] - cx * dxmz - cy * dymz - cz * dzmz;
+                u[4] = u0[4] - cx * dxe - cy * dye - cz * dze;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) out.u[q][cc] = u[q];
             }
-            const int ke = k & 1;  // E_z slot of plane k
             if (jj < ny) {  // face x (ii - 1/2, jj, k)
-                const double b0 = s.b[0][face_store(g, 0, ii, jj, k)];
-                const double v = b0 - cy * (s_ez[ke][ty + 1][tx] - s_ez[ke][ty][tx])
+                const double v = bxb - cy * (s_ez[ke][ty + 1][tx] - s_ez[ke][ty][tx])
                                  + cz * (s_ey[hi][ty][tx] - s_ey[lo][ty][tx]);
                 out.b[0][face_store(g, 0, ii, jj, k)] = v;
                 if (g.bc[0] == VLCT_BC_PERIODIC && ii == 0) out.b[0][face_store(g, 0, nx, jj, k)] = v;
+                bxl = v;
             }
             if (ii < nx) {  // face y (ii, jj - 1/2, k)
-                const double b0 = s.b[1][face_store(g, 1, ii, jj, k)];
-                const double v = b0 - cz * (s_ex[hi][ty][tx] - s_ex[lo][ty][tx])
+                const double v = byb - cz * (s_ex[hi][ty][tx] - s_ex[lo][ty][tx])
                                  + cx * (s_ez[ke][ty][tx + 1] - s_ez[ke][ty][tx]);
                 out.b[1][face_store(g, 1, ii, jj, k)] = v;
                 if (g.bc[1] == VLCT_BC_PERIODIC && jj == 0) out.b[1][face_store(g, 1, ii, ny, k)] = v;
+                byl = v;
             }
             if (interior) {  // face z (ii, jj, k - 1/2)
-                const double b0 = s.b[2][face_store(g, 2, ii, jj, k)];
-                const double v = b0 - cx * (s_ey[lo][ty][tx + 1] - s_ey[lo][ty][tx])
+                const double v = bzb - cx * (s_ey[lo][ty][tx + 1] - s_ey[lo][ty][tx])
                                  + cy * (s_ex[lo][ty + 1][tx] - s_ex[lo][ty][tx]);
                 out.b[2][face_store(g, 2, ii, jj, k)] = v;
                 if (g.bc[2] == VLCT_BC_PERIODIC && k == 0) out.b[2][face_store(g, 2, ii, jj, nz)] = v;
+                bzl = v;
+            }
+            if (interior && P.w[0]) {
+                // high faces (a periodic one through the face map, as its owner computes it)
+                const double bxu = bxh - cy * (s_ez[ke][ty + 1][tx + 1] - s_ez[ke][ty][tx + 1])
+                                   + cz * (s_ey[hi][ty][tx + 1] - s_ey[lo][ty][tx + 1]);
+                const double byu = byh - cz * (s_ex[hi][ty + 1][tx] - s_ex[lo][ty + 1][tx])
+                                   + cx * (s_ez[ke][ty + 1][tx + 1] - s_ez[ke][ty + 1][tx]);
+                const double bzu = bzh - cx * (s_ey[hi][ty][tx + 1] - s_ey[hi][ty][tx])
+                                   + cy * (s_ex[hi][ty + 1][tx] - s_ex[hi][ty][tx]);
+                st |= prims_store(g, P, pidx(g, ii, jj, k), u, 0.5 * (bxl + bxu), 0.5 * (byl + byu),
+                                  0.5 * (bzl + bzu));
             }
         }
         // the top z faces of an outflow axis, from the edges of the half plane nz - 1/2
@@ -1032,14 +1145,19 @@ __host__ __device__ __forceinline__ idx_t nblk_pred(const Geom &g)
     return (idx_t)ntx * nty * ntz;
 }
 
-template <bool TAPE>
-__global__ void __launch_bounds__(kPredThreads) k_pred(Geom g, StateP s, StateW out,
+__global__ void __launch_bounds__(kPredThreads) k_pred(Geom g, StateP s, StateW out, Prims P,
                                                         const double *dt_dev, uint32_t *status,
                                                         uint8_t *side0, uint8_t *side1,
                                                         uint8_t *side2)
 {
-    pred_body<kPredTx, kPredTy, TAPE>(g, s, out, dt_dev, status, xcd_block(nblk_pred(g)), side0,
-                                      side1, side2);
+    pred_body<kPredTx, kPredTy>(g, s, out, P, dt_dev, status, xcd_block(nblk_pred(g)), side0,
+                                side1, side2);
+}
+
+__global__ void __launch_bounds__(kBlock) k_prims_ghost(Geom g, StateP s, Prims P,
+                                                        uint32_t *status)
+{
+    prims_ghost_body(g, s, P, status, xcd_block((ghost_cells(g) + kBlock - 1) / kBlock));
 }
 
 __global__ void __launch_bounds__(kBlock) k_dt_partial(Geom g, StateP s, double *partial,
@@ -1060,6 +1178,7 @@ __global__ void __launch_bounds__(kBlock) k_dt_partial(Geom g, StateP s, double 
 // variant (an instance has blocks only in the slot of its own variant)
 enum Slot {
     kSlotPred,
+    kSlotGhost,
     kSlotPrims,
     kSlotFlux0,
     kSlotFlux1,
@@ -1083,8 +1202,15 @@ struct Inst {
     const double *dt;
     double *next_dt;
     uint32_t *status;
+    // per-instance end times (vlct_step_batch_until; NULL otherwise): the
+    // instance steps only while *active, by *dt = min(caller dt, t_end - t),
+    // and its time *t advances at the end of the step
+    const int *active;
+    double *t;
     idx_t start[kSlots];  // first flattened block of this instance in each launch
 };
+
+__device__ __forceinline__ bool retired(const Inst &I) { return I.active && !I.active[0]; }
 
 constexpr int kPackChunk = 4;  // records per pack launch (kernel-argument size)
 struct PackArgs {
@@ -1128,10 +1254,26 @@ __global__ void __launch_bounds__(kPredThreads) kb_pred(const Inst *tab, int cou
     if (gb >= total) return;
     idx_t lb;
     const Inst &I = find_inst(tab, count, kSlotPred, gb, lb);
+    if (retired(I)) return;
     const Geom g = I.g;
     const StateP in = I.in;
     const StateW half = I.half;
-    pred_body<kPredTx, kPredTy, false>(g, in, half, I.dt, I.status, lb, nullptr, nullptr, nullptr);
+    const Prims P = I.P;
+    pred_body<kPredTx, kPredTy>(g, in, half, P, I.dt, I.status, lb, nullptr, nullptr, nullptr);
+}
+
+// ghost-layer primitives of the half-step state of every instance
+__global__ void __launch_bounds__(kBlock) kb_prims_ghost(const Inst *tab, int count, idx_t total)
+{
+    const idx_t gb = xcd_block(total);
+    if (gb >= total) return;
+    idx_t lb;
+    const Inst &I = find_inst(tab, count, kSlotGhost, gb, lb);
+    if (retired(I)) return;
+    const Geom g = I.g;
+    const StateP st = const_view(I.half);
+    const Prims P = I.P;
+    prims_ghost_body(g, st, P, I.status, lb);
 }
 
 // half = 0: primitives of U^n, 1: of U^{n+1/2}
@@ -1142,6 +1284,7 @@ __global__ void __launch_bounds__(kBlock) kb_prims(const Inst *tab, int count, i
     if (gb >= total) return;
     idx_t lb;
     const Inst &I = find_inst(tab, count, kSlotPrims, gb, lb);
+    if (retired(I)) return;
     const Geom g = I.g;
     const StateP st = half ? const_view(I.half) : I.in;
     const Prims P = I.P;
@@ -1157,6 +1300,7 @@ __global__ void __launch_bounds__(kBlock) kb_flux_pcm(const Inst *tab, int count
     if (gb >= total) return;
     idx_t lb;
     const Inst &I = find_inst(tab, count, kSlotFlux0 + D, gb, lb);
+    if (retired(I)) return;
     const Geom g = I.g;
     const StateP st = half ? const_view(I.half) : I.in;
     const Prims P = I.P;
@@ -1171,6 +1315,7 @@ __global__ void __launch_bounds__(kBlock) kb_recon_x(const Inst *tab, int count,
     if (gb >= total) return;
     idx_t lb;
     const Inst &I = find_inst(tab, count, kSlotRow, gb, lb);
+    if (retired(I)) return;
     const Geom g = I.g;
     const StateP st = const_view(I.half);
     const Prims P = I.P;
@@ -1185,6 +1330,7 @@ __global__ void __launch_bounds__(kBlock) kb_march(const Inst *tab, int count, i
     if (gb >= total) return;
     idx_t lb;
     const Inst &I = find_inst(tab, count, (D == 1 ? kSlotMarch1 : kSlotMarch2) + V, gb, lb);
+    if (retired(I)) return;
     const Geom g = I.g;
     const StateP st = const_view(I.half);
     const Prims P = I.P;
@@ -1199,6 +1345,7 @@ __global__ void __launch_bounds__(kCt) kb_ct(const Inst *tab, int count, idx_t t
     if (gb >= total) return;
     idx_t lb;
     const Inst &I = find_inst(tab, count, kSlotCt + V, gb, lb);
+    if (retired(I)) return;
     const Geom g = I.g;
     const Prims P = I.P;
     const Flux F = I.F;
@@ -1214,14 +1361,17 @@ __global__ void __launch_bounds__(kBlock) kb_dt_partial(const Inst *tab, int cou
     if (gb >= total) return;
     idx_t lb;
     const Inst &I = find_inst(tab, count, kSlotDt, gb, lb);
+    if (retired(I)) return;
     const Geom g = I.g;
     dt_partial_body(g, const_view(I.out), I.partial, I.status, lb);
 }
 
-// one block per instance: dt = cfl / max over that instance's partials
+// one block per instance: dt = cfl / max over that instance's partials; an
+// instance with an end time also advances its time by the step it took
 __global__ void __launch_bounds__(1024) kb_dt_final(const Inst *tab)
 {
     const Inst &I = tab[blockIdx.x];
+    if (retired(I)) return;
     const int n = (int)nblk_dt(I.g);
     __shared__ double red[1024 / 64];
     double m = 0.0;
@@ -1234,7 +1384,20 @@ __global__ void __launch_bounds__(1024) kb_dt_final(const Inst *tab)
         double b = red[0];
         for (int q = 1; q < (int)(blockDim.x / 64); ++q) b = fmax(b, red[q]);
         I.next_dt[0] = I.g.cfl / b;
+        if (I.t) I.t[0] += I.dt[0];
     }
+}
+
+// per-instance end times: instance i is active while t[i] < t_end[i] and then
+// steps by min(dt[i], t_end[i] - t[i]) (the caller's clip of the last step)
+__global__ void kb_clip(int count, const double *dt, const double *t, const double *t_end,
+                        double *dt_eff, int *active)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const bool a = t[i] < t_end[i];
+    active[i] = a ? 1 : 0;
+    dt_eff[i] = a ? fmin(dt[i], t_end[i] - t[i]) : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1263,7 +1426,7 @@ static Layout layout(const Geom &g)
     for (int d = 0; d < 3; ++d) {
         L.flux_len[d] = (size_t)flux_dim(g.n, d, 0) * flux_dim(g.n, d, 1) * flux_dim(g.n, d, 2);
         L.flux[d] = off;
-        off += 8 * align_up(L.flux_len[d] * sizeof(double));
+        off += flux_axis_bytes(L.flux_len[d]);
     }
     const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
     L.npartial = (N + kBlock - 1) / kBlock;  // partials of the CFL kernel
@@ -1314,10 +1477,7 @@ static Bound bind(const Layout &L, void *ws)
     }
     for (int f = 0; f < 8; ++f)
         B.P.w[f] = reinterpret_cast<double *>(b + L.prims + f * align_up(L.prims_len * sizeof(double)));
-    for (int d = 0; d < 3; ++d)
-        for (int c = 0; c < 8; ++c)
-            B.F.f[d][c] = reinterpret_cast<double *>(
-                b + L.flux[d] + c * align_up(L.flux_len[d] * sizeof(double)));
+    B.F = bind_flux(b, L.flux, L.flux_len);
     B.partial = reinterpret_cast<double *>(b + L.partial);
     return B;
 }
@@ -1390,16 +1550,20 @@ int launch_ct(const Geom &g, bool full, const Prims &P, const Flux &F, const Sta
 
 // the whole predictor (Steps 2-5) in one kernel: U^n -> U^{n+1/2}; with
 // `side` (3 arrays, tape layout) it also records the faces' upwind sides
-static int launch_pred(const Geom &g, const StateP &st, const StateW &half, const double *dt_dev,
-                       uint32_t *status, uint8_t *const *side, hipStream_t s)
+static int launch_pred(const Geom &g, const StateP &st, const StateW &half, const Prims &P,
+                       const double *dt_dev, uint32_t *status, uint8_t *const *side,
+                       hipStream_t s)
 {
-    Observe o(VLCT_KERNEL_PREDICTOR, s);
-    if (side)
-        k_pred<true><<<xcd_grid(nblk_pred(g)), kPredThreads, 0, s>>>(g, st, half, dt_dev, status,
-                                                                     side[0], side[1], side[2]);
-    else
-        k_pred<false><<<xcd_grid(nblk_pred(g)), kPredThreads, 0, s>>>(g, st, half, dt_dev, status,
-                                                                      nullptr, nullptr, nullptr);
+    {
+        Observe o(VLCT_KERNEL_PREDICTOR, s);
+        k_pred<<<xcd_grid(nblk_pred(g)), kPredThreads, 0, s>>>(
+            g, st, half, P, dt_dev, status, side ? side[0] : nullptr, side ? side[1] : nullptr,
+            side ? side[2] : nullptr);
+    }
+    // ghost layers of the half-step primitives
+    Observe o(VLCT_KERNEL_PRIMS, s);
+    k_prims_ghost<<<xcd_grid((ghost_cells(g) + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+        g, as_const(half), P, status);
     return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
 }
 
@@ -1426,9 +1590,9 @@ __global__ void k_pack_sides(Geom g, Flux F, uint8_t *s0, uint8_t *s1, uint8_t *
     if (t >= N) return;
     const int i = (int)(t % g.n[0]), j = (int)((t / g.n[0]) % g.n[1]),
               k = (int)(t / ((idx_t)g.n[0] * g.n[1]));
-    s0[t] = side_code(F.f[0][7][fidx(g, 0, i, j, k)]);
-    s1[t] = side_code(F.f[1][7][fidx(g, 1, i, j, k)]);
-    s2[t] = side_code(F.f[2][7][fidx(g, 2, i, j, k)]);
+    s0[t] = side_code(F.sg[0][fidx(g, 0, i, j, k)]);
+    s1[t] = side_code(F.sg[1][fidx(g, 1, i, j, k)]);
+    s2[t] = side_code(F.sg[2][fidx(g, 2, i, j, k)]);
 }
 
 int launch_pack_sides(const Geom &g, const Flux &F, uint8_t *const side[3], hipStream_t s)
@@ -1450,7 +1614,23 @@ static int launch_dt(const Geom &g, const StateP &st, const Bound &B, const Layo
 
 constexpr int kMaxBatch = 1 << 16;
 
-static size_t batch_table_bytes(int count) { return align_up((size_t)count * sizeof(Inst)); }
+// the instance table, then the clipped dt and active flag of every instance
+// (used by vlct_step_batch_until)
+static size_t batch_table_bytes(int count)
+{
+    return align_up((size_t)count * sizeof(Inst)) + align_up((size_t)count * sizeof(double)) +
+           align_up((size_t)count * sizeof(int));
+}
+static double *batch_dt_eff(void *ws, int count)
+{
+    return reinterpret_cast<double *>(static_cast<char *>(ws) +
+                                      align_up((size_t)count * sizeof(Inst)));
+}
+static int *batch_active(void *ws, int count)
+{
+    return reinterpret_cast<int *>(reinterpret_cast<char *>(batch_dt_eff(ws, count)) +
+                                   align_up((size_t)count * sizeof(double)));
+}
 
 // instance records with workspace regions and flattened block offsets;
 // returns the per-slot block totals through `total`
@@ -1478,9 +1658,12 @@ static void batch_records(int count, const vlct_grid *grids, const vlct_state *i
         r.dt = dt_dev + i;
         r.next_dt = next_dt_dev ? next_dt_dev + i : nullptr;
         r.status = status_dev ? status_dev + i : nullptr;
+        r.active = nullptr;
+        r.t = nullptr;
         const int cv = plan ? (plan[i] & 15) : 0, mv = plan ? (plan[i] >> 4) : 0;
         idx_t nb[kSlots] = {};
         nb[kSlotPred] = nblk_pred(g);
+        nb[kSlotGhost] = (ghost_cells(g) + kBlock - 1) / kBlock;
         nb[kSlotPrims] = nblk_prims(g);
         for (int d = 0; d < 3; ++d) nb[kSlotFlux0 + d] = nblk_flux(g, d);
         nb[kSlotRow] = nblk_row(g);
@@ -1618,10 +1801,9 @@ int vlct_step(const vlct_grid *vg, const vlct_state *in, const vlct_state *out,
     hipStream_t s = static_cast<hipStream_t>(stream);
     const StateP sin = as_const(in);
     // predictor (Steps 2-5)
-    int rc = launch_pred(g, sin, B.half, dt_dev, status_dev, nullptr, s);
-    // corrector (Steps 6-9)
+    int rc = launch_pred(g, sin, B.half, B.P, dt_dev, status_dev, nullptr, s);
+    // corrector (Steps 6-9) on the half-step primitives the predictor left in B.P
     const StateP half = as_const(B.half);
-    if (!rc) rc = launch_prims(g, half, B.P, status_dev, s);
     if (!rc) rc = launch_fluxes(g, half, B.P, B.F, vg->recon, status_dev, s);
     if (rc) return rc;
     // the CFL reduction rides on the full update unless the step is in place
@@ -1679,9 +1861,8 @@ int vlct_step_taped(const vlct_grid *vg, const vlct_state *in, const vlct_state 
     const StateP sin = as_const(in);
     // the steps of vlct_step with the half-step state and both stages' upwind
     // sides kept in the tape
-    int rc = launch_pred(g, sin, half, dt_dev, status_dev, side[0], s);
+    int rc = launch_pred(g, sin, half, B.P, dt_dev, status_dev, side[0], s);
     const StateP hc = as_const(half);
-    if (!rc) rc = launch_prims(g, hc, B.P, status_dev, s);
     if (!rc) rc = launch_fluxes(g, hc, B.P, B.F, vg->recon, status_dev, s);
     if (!rc) rc = launch_pack_sides(g, B.F, side[1], s);
     if (rc) return rc;
@@ -1760,10 +1941,12 @@ static int batch_args(int count, const vlct_grid *grids, const vlct_state *in,
     return VLCT_OK;
 }
 
-int vlct_step_batch_plan(int count, const vlct_grid *grids, const vlct_state *in,
-                         const vlct_state *out, const double *dt_dev, double *next_dt_dev,
-                         uint32_t *status_dev, const uint8_t *plan, void *ws, size_t ws_bytes,
-                         void *stream)
+// the batched step; with t_dev / t_end_dev (device, count each) every
+// instance runs only while t < t_end, by min(dt, t_end - t), and advances t
+static int batch_step(int count, const vlct_grid *grids, const vlct_state *in,
+                      const vlct_state *out, const double *dt_dev, double *next_dt_dev,
+                      uint32_t *status_dev, const uint8_t *plan, void *ws, size_t ws_bytes,
+                      void *stream, double *t_dev, const double *t_end_dev)
 {
     const int arc = batch_args(count, grids, in, out, dt_dev, plan);
     if (arc) return arc;
@@ -1773,6 +1956,17 @@ int vlct_step_batch_plan(int count, const vlct_grid *grids, const vlct_state *in
     std::vector<Inst> rec;
     idx_t tot[kSlots];
     batch_records(count, grids, in, out, dt_dev, next_dt_dev, status_dev, plan, ws, rec, tot);
+    if (t_dev) {
+        double *dt_eff = batch_dt_eff(ws, count);
+        int *active = batch_active(ws, count);
+        kb_clip<<<(count + 255) / 256, 256, 0, s>>>(count, dt_dev, t_dev, t_end_dev, dt_eff,
+                                                    active);
+        for (int i = 0; i < count; ++i) {
+            rec[i].dt = dt_eff + i;
+            rec[i].active = active + i;
+            rec[i].t = t_dev + i;
+        }
+    }
     Inst *tab = static_cast<Inst *>(ws);
     for (int first = 0; first < count; first += kPackChunk) {
         PackArgs a;
@@ -1788,16 +1982,16 @@ int vlct_step_batch_plan(int count, const vlct_grid *grids, const vlct_state *in
         Observe o(VLCT_KERNEL_PREDICTOR, s);
         kb_pred<<<xcd_grid(tot[kSlotPred]), kPredThreads, 0, s>>>(tab, count, tot[kSlotPred]);
     }
+    {
+        Observe o(VLCT_KERNEL_PRIMS, s);
+        kb_prims_ghost<<<xcd_grid(tot[kSlotGhost]), kBlock, 0, s>>>(tab, count, tot[kSlotGhost]);
+    }
 #define VLCT_BCT(FULL, V)                                                                 \
     if (tot[kSlotCt + V]) {                                                                   \
         Observe o(FULL ? VLCT_KERNEL_UPDATE_FULL : VLCT_KERNEL_UPDATE_HALF, s);                \
         kb_ct<FULL, V><<<xcd_grid(tot[kSlotCt + V]), kCt, 0, s>>>(tab, count, tot[kSlotCt + V]); \
     }
-    // corrector (Steps 6-9)
-    {
-        Observe o(VLCT_KERNEL_PRIMS, s);
-        kb_prims<<<xcd_grid(tot[kSlotPrims]), kBlock, 0, s>>>(tab, count, tot[kSlotPrims], 1);
-    }
+    // corrector (Steps 6-9); the predictor wrote the interior primitives
 #define VLCT_BMARCH(D, R, V)                                                                  \
     if (tot[(D == 1 ? kSlotMarch1 : kSlotMarch2) + V]) {                                      \
         const idx_t n = tot[(D == 1 ? kSlotMarch1 : kSlotMarch2) + V];                        \
@@ -1836,6 +2030,25 @@ int vlct_step_batch_plan(int count, const vlct_grid *grids, const vlct_state *in
         kb_dt_final<<<count, 1024, 0, s>>>(tab);
     }
     return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
+}
+
+int vlct_step_batch_plan(int count, const vlct_grid *grids, const vlct_state *in,
+                         const vlct_state *out, const double *dt_dev, double *next_dt_dev,
+                         uint32_t *status_dev, const uint8_t *plan, void *ws, size_t ws_bytes,
+                         void *stream)
+{
+    return batch_step(count, grids, in, out, dt_dev, next_dt_dev, status_dev, plan, ws, ws_bytes,
+                      stream, nullptr, nullptr);
+}
+
+int vlct_step_batch_until(int count, const vlct_grid *grids, const vlct_state *states,
+                          const double *dt_dev, double *next_dt_dev, uint32_t *status_dev,
+                          double *t_dev, const double *t_end_dev, const uint8_t *plan, void *ws,
+                          size_t ws_bytes, void *stream)
+{
+    if (!t_dev || !t_end_dev || !next_dt_dev) return VLCT_EINVAL;
+    return batch_step(count, grids, states, states, dt_dev, next_dt_dev, status_dev, plan, ws,
+                      ws_bytes, stream, t_dev, t_end_dev);
 }
 
 int vlct_batch_tune(int count, const vlct_grid *grids, const vlct_state *in,

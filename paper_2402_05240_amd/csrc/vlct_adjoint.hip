@@ -911,7 +911,7 @@ static AdLayout ad_layout(const Geom &g, bool taped)
         for (int h = 0; h < 2; ++h)
             for (int d = 0; d < 3; ++d) {
                 L.flux[h][d] = off;
-                off += 8 * align_up(L.flux_len[d] * 8);
+                off += flux_axis_bytes(L.flux_len[d]);
             }
         for (int h = 0; h < 2; ++h)
             for (int d = 0; d < 3; ++d) {
@@ -1144,9 +1144,8 @@ int vlct_step_adjoint(const vlct_grid *vg, const vlct_state *in, const vlct_stat
     uint8_t *side[2][3];
     Sides sides[2];
     for (int h = 0; h < 2; ++h) {
+        F[h] = bind_flux(b, L.flux[h], L.flux_len);
         for (int d = 0; d < 3; ++d) {
-            for (int c = 0; c < 8; ++c)
-                F[h].f[d][c] = arr(L.flux[h][d] + c * align_up(L.flux_len[d] * 8));
             side[h][d] = reinterpret_cast<uint8_t *>(b + L.side[h][d]);
             sides[h].s[d] = side[h][d];
         }

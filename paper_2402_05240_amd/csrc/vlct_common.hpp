@@ -103,9 +103,29 @@ struct StateW {
 struct Prims {
     double *w[8];  // rho, vx, vy, vz, P, Bcx, Bcy, Bcz on padded cells
 };
+inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
 struct Flux {
-    double *f[3][8];  // per axis: 7 sweep-frame components + upwind indicator
+    double *f[3][7];  // per axis: 7 sweep-frame flux components
+    int8_t *sg[3];    // per axis: CT upwind indicator (+1, -1, 0), the sign of S_M
 };
+
+// bytes of one axis' flux arrays (7 doubles and the indicator per face)
+inline size_t flux_axis_bytes(size_t len)
+{
+    return 7 * align_up(len * sizeof(double)) + align_up(len);
+}
+
+inline Flux bind_flux(char *base, const size_t off[3], const size_t len[3])
+{
+    Flux F;
+    for (int d = 0; d < 3; ++d) {
+        for (int c = 0; c < 7; ++c)
+            F.f[d][c] = reinterpret_cast<double *>(base + off[d] + c * align_up(len[d] * sizeof(double)));
+        F.sg[d] = reinterpret_cast<int8_t *>(base + off[d] + 7 * align_up(len[d] * sizeof(double)));
+    }
+    return F;
+}
 
 // ---------------------------------------------------------------------------
 // host helpers
@@ -233,7 +253,6 @@ inline StateW as_mut(const vlct_state *s)
     return p;
 }
 
-inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 inline unsigned nblocks(size_t work) { return (unsigned)((work + kBlock - 1) / kBlock); }
 

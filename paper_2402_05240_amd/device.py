@@ -161,6 +161,35 @@ class BatchStepper:
         self.cur, self.nxt = self.nxt, self.cur
         self.dt, self.next_dt = self.next_dt, self.dt
 
+    def run_until(self, t_end, check_every: int = 8, max_steps: int = 100000):
+        """Advance every instance in place to its own end time t_end[i]
+        (vlct_step_batch_until: the last step of each is clipped to land on
+        it, finished instances drop out of the kernels); returns the number
+        of batched steps.  The host looks at the times every `check_every`
+        steps only."""
+        torch = _torch()
+        if self.nxt is not self.cur:
+            raise ValueError("run_until steps in place")
+        n = len(self.grids)
+        self.t = torch.zeros(n, dtype=torch.float64, device=self.device)
+        tend = torch.tensor([float(x) for x in t_end], dtype=torch.float64, device=self.device)
+        steps = 0
+        while steps < max_steps:
+            for _ in range(check_every):
+                rc = vlct.vlct_step_batch_until(self.cgs, [d.c_state() for d in self.cur],
+                                                self.dt.data_ptr(), self.next_dt.data_ptr(),
+                                                self.status.data_ptr(), self.t.data_ptr(),
+                                                tend.data_ptr(), self.plan, self.ws.data_ptr(),
+                                                self.ws_bytes, self.stream())
+                if rc:
+                    raise vlct.VlctError(rc, "vlct_step_batch_until")
+                # a finished instance keeps its dt; a running one takes its next CFL step
+                self.dt.copy_(torch.where(self.t < tend, self.next_dt, self.dt))
+                steps += 1
+            if bool((self.t >= tend).all()):
+                break
+        return steps
+
     def tune(self, reps: int = 3):
         """Per-instance tiles from the library's autotuner (vlct_batch_tune),
         timed on the current states with the current dt; needs out-of-place

@@ -36,7 +36,7 @@ EXPORTED = ("vlct_workspace_bytes", "vlct_cfl_dt", "vlct_step", "vlct_strerror",
             "vlct_step_adjoint", "vlct_curl_potential", "vlct_curl_potential_adjoint",
             "vlct_tape_bytes", "vlct_step_taped", "vlct_adjoint_taped_workspace_bytes",
             "vlct_step_adjoint_taped", "vlct_step_batch_plan", "vlct_batch_tune",
-            "vlct_step_noalloc")
+            "vlct_step_noalloc", "vlct_step_batch_until")
 
 VLCT_KERNEL_PRIMS = 0
 VLCT_KERNEL_FLUX_PCM = 1
@@ -74,12 +74,21 @@ _lib = None
 
 
 def load(path: str = LIB_PATH):
-    """Load libvlct.so; raises if it has not been built."""
+    """Load libvlct.so; raises if it has not been built.
+
+    torch is imported first when it is installed: it ships its own HIP
+    runtime under the same soname, and the library must bind to that one
+    copy, or the streams and device memory torch hands over would belong to a
+    second runtime in the same process."""
     global _lib
     if _lib is None:
         if not os.path.exists(path):
             raise RuntimeError("libvlct.so not found at %s: build it with "
                                "`python -m paper_2402_05240_amd.build`" % path)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(path)
         lib.vlct_workspace_bytes.argtypes = [ctypes.POINTER(vlct_grid)]
         lib.vlct_workspace_bytes.restype = ctypes.c_size_t
@@ -109,6 +118,12 @@ def load(path: str = LIB_PATH):
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                              ctypes.c_void_p]
         lib.vlct_step_batch_plan.restype = ctypes.c_int
+        lib.vlct_step_batch_until.argtypes = [ctypes.c_int, ctypes.POINTER(vlct_grid),
+                                              ctypes.POINTER(vlct_state), ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_size_t, ctypes.c_void_p]
+        lib.vlct_step_batch_until.restype = ctypes.c_int
         lib.vlct_batch_tune.argtypes = [ctypes.c_int, ctypes.POINTER(vlct_grid),
                                         ctypes.POINTER(vlct_state), ctypes.POINTER(vlct_state),
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
@@ -273,6 +288,20 @@ def vlct_step_batch_plan(grids, states_in, states_out, dt_dev: int, next_dt_dev:
     return int(load().vlct_step_batch_plan(n, g, a, b, dt_dev, next_dt_dev, status_dev,
                                            ctypes.cast(p, ctypes.c_void_p) if p is not None else None,
                                            ws, ws_bytes, stream))
+
+
+def vlct_step_batch_until(grids, states, dt_dev: int, next_dt_dev: int, status_dev: int,
+                          t_dev: int, t_end_dev: int, plan, ws: int, ws_bytes: int,
+                          stream: int) -> int:
+    """In-place batched step of the instances with t < t_end (device arrays)."""
+    n = len(grids)
+    g = (vlct_grid * n)(*grids)
+    a = (vlct_state * n)(*states)
+    p = (ctypes.c_uint8 * n)(*plan) if plan is not None else None
+    return int(load().vlct_step_batch_until(n, g, a, dt_dev, next_dt_dev, status_dev, t_dev,
+                                            t_end_dev,
+                                            ctypes.cast(p, ctypes.c_void_p) if p is not None
+                                            else None, ws, ws_bytes, stream))
 
 
 def vlct_batch_tune(grids, states_in, states_out, dt_dev: int, ws: int, ws_bytes: int,

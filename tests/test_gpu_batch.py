@@ -201,3 +201,43 @@ def test_batch_autotuner_plan_is_valid_and_exact():
     for q in range(len(inst)):
         for f in FIELDS:
             assert np.array_equal(tuned[q][f], base[q][f]), (q, f)
+
+
+def test_batch_until_each_instance_to_its_own_end_time():
+    """vlct_step_batch_until: instances with different periods each run to
+    their own end time (the last step clipped onto it) and then drop out;
+    every instance ends bit for bit where vlct_step gets it with the same
+    clip, and the times land on the end times."""
+    _need_gpu()
+    import torch
+    from paper_2402_05240_amd.device import BatchStepper, Stepper
+    ens = I.ensemble(5, seed=11, nmin=12, nmax=24)
+    grids = [g for g, _, _ in ens]
+    ends = [0.25 * T * (1 + q) / 5 for q, (_, _, T) in enumerate(ens)]
+    _say("ensemble of %d, end times %s" % (len(ens), ["%.3g" % x for x in ends]))
+    bs = BatchStepper(grids, inplace=True).upload([s for _, s, _ in ens])
+    bs.compute_dt()
+    nb = bs.run_until(ends, check_every=4)
+    got = bs.download()
+    t_b = bs.t.cpu().numpy()
+    counts = []
+    for q, ((g, s, _), tend) in enumerate(zip(ens, ends)):
+        st = Stepper(g, inplace=True).upload(s)
+        st.compute_dt()
+        t = torch.zeros(1, dtype=torch.float64, device="cuda")
+        te = torch.tensor([tend], dtype=torch.float64, device="cuda")
+        n = 0
+        while float(t.item()) < tend:
+            dte = torch.minimum(st.dt, te - t)
+            st.dt.copy_(dte)
+            st.step()
+            t += dte
+            n += 1
+        counts.append(n)
+        ref_state = st.download()
+        assert float(t.item()) == t_b[q], q
+        for f in FIELDS:
+            assert np.array_equal(got[q][f], ref_state[f]), (q, f)
+    _say("steps per instance %s, batched steps %d" % (counts, nb))
+    assert len(set(counts)) > 1 and nb >= max(counts)
+    assert np.allclose(t_b, ends, rtol=1e-14, atol=0)
