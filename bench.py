@@ -390,7 +390,7 @@ def summarize_valu(insts_csv, busy_csv, workload, commands, out_dir):
                    "waves_per_launch": m.get("SQ_WAVES"),
                    "valu_busy": b.get("VALUBusy", 0.0) / 100.0,
                    "valu_lane_utilization": b.get("VALUUtilization", 0.0) / 100.0,
-                   "mean_occupancy_waves_per_cu": b.get("MeanOccupancyPerActiveCU"),
+                   "mean_occupancy_waves_per_simd": b.get("MeanOccupancyPerActiveCU"),
                    "kernels": [{"name": n, "vgpr": v, "agpr": a, "lds_bytes": lds,
                                 "scratch_bytes": sc, "workgroup": wg}
                                for n, v, a, lds, sc, wg in sorted(kres[k])]}
@@ -407,15 +407,19 @@ def summarize_valu(insts_csv, busy_csv, workload, commands, out_dir):
         "lane utilisation: active lanes per VALU instruction (VALUUtilization); FP64 FLOP "
         "= 64 x (2 FMA + ADD + MUL) wave instructions.", "",
         "| family | VALU insts | FP64 insts | FP64 share | FP64 GFLOP | VALU busy | lanes | "
-        "waves/CU | VGPR | LDS B | scratch B |", "|---|---|---|---|---|---|---|---|---|---|---|"]
+        "waves/SIMD | VGPR (record) | LDS B | scratch B |", "|---|---|---|---|---|---|---|---|---|---|---|"]
     for k, v in sorted(fams.items()):
         ks = v["kernels"][0] if v["kernels"] else {}
         lines.append("| %s | %.3g | %.3g | %.2f | %.2f | %.2f | %.2f | %.1f | %s | %s | %s |" % (
             k, v["valu_insts_per_launch"] or 0, v["fp64_insts_per_launch"],
             v["fp64_share_of_valu"] or 0, v["fp64_flops_per_launch"] / 1e9, v["valu_busy"],
-            v["valu_lane_utilization"], v["mean_occupancy_waves_per_cu"] or 0,
+            v["valu_lane_utilization"], v["mean_occupancy_waves_per_simd"] or 0,
             ks.get("vgpr", "?"), ks.get("lds_bytes", "?"), ks.get("scratch_bytes", "?")))
-    lines += ["", "Kernels of each family (VGPRs, LDS and scratch per work-group from the "
+    lines += ["", "waves/SIMD: MeanOccupancyPerActiveCU as rocprofv3 reports it (it reads 2.0 for "
+              "a kernel the compiler limits to 2 waves per SIMD). VGPR (record): the dispatch "
+              "record's VGPR_Count, which on gfx950 is half the compiler's per-lane count "
+              "(the kernel-resource-usage remark).", "",
+              "Kernels of each family (VGPRs, LDS and scratch per work-group from the "
               "dispatch records):", ""]
     for k, v in sorted(fams.items()):
         for ks in v["kernels"]:

@@ -164,8 +164,9 @@ int vlct_step_batch(int count, const vlct_grid *grids, const vlct_state *in,
 /* Per-instance tile plan: vlct_step_batch with plan[i] (HOST array of `count`
  * bytes, NULL = all zero) choosing instance i's tiles: low nibble the CT
  * column tile (0: 64 x 8, 1: 32 x 16, 2: 16 x 32), high nibble the corrector
- * march segment along y and z (0: 16 faces, 1: 32, 2: 8).  Plan 0 is the
- * tiling of vlct_step.  Every plan gives the
+ * march segment along y and z (0: 16 faces, 1: 32, 2: 8).  Plan 0 takes
+ * 64 x 8 CT tiles with vlct_step's planes per CT block and 16-face marches
+ * (vlct_step itself marches 8 faces on small grids).  Every plan gives the
  * same results bit for bit (the tiles only regroup the same per-cell and
  * per-face arithmetic); VLCT_EINVAL for an unknown variant. */
 int vlct_step_batch_plan(int count, const vlct_grid *grids, const vlct_state *in,

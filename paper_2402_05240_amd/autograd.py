@@ -59,6 +59,18 @@ class Simulator:
     def _stream(self) -> int:
         return _torch().cuda.current_stream().cuda_stream
 
+    def raise_on_status(self, where: str) -> None:
+        """One host read of the status word the steps accumulate: a floor or a
+        non-finite value makes the loss and its gradient those of the floored
+        branch (or meaningless), so a rollout reports it instead of returning
+        them silently."""
+        bits = int(self.status.item())
+        if bits:
+            names = [n for b, n in ((vlct.VLCT_STATUS_PRESSURE_FLOOR, "pressure floor"),
+                                    (vlct.VLCT_STATUS_DENSITY_FLOOR, "density floor"),
+                                    (vlct.VLCT_STATUS_NONFINITE, "non-finite state")) if bits & b]
+            raise FloatingPointError("%s: %s (status %d)" % (where, ", ".join(names), bits))
+
     def ws_adj(self):
         if self._ws_adj is None:
             torch = _torch()
@@ -218,6 +230,7 @@ def _make_functions():
         def forward(ctx, sim, dts, segment, record, taped, *fields):
             cur = sim._check(fields)
             nsteps = len(dts)
+            sim.status.zero_()
             if record:
                 dts[0].copy_(sim.cfl_dt(cur))
             ckpts = [cur]
@@ -229,6 +242,7 @@ def _make_functions():
             ctx.sim, ctx.dts, ctx.segment, ctx.nck = sim, list(dts), segment, len(ckpts)
             ctx.taped = taped
             ctx.save_for_backward(*[t for c in ckpts for t in c])
+            sim.raise_on_status("rollout forward pass")
             return cur
 
         @staticmethod
@@ -238,6 +252,7 @@ def _make_functions():
             ckpts = [tuple(flat[8 * c:8 * c + 8]) for c in range(ctx.nck)]
             lam = _grads_or_zeros(grads, ckpts[0])
             nsteps = len(dts)
+            sim.status.zero_()
             for s in reversed(range(len(ckpts))):
                 start, stop = s * seg, min((s + 1) * seg, nsteps)
                 states = [ckpts[s]]
@@ -257,6 +272,7 @@ def _make_functions():
                     for i in reversed(range(start, stop)):
                         lam = sim.adjoint(states[i - start], lam, dts[i])
                 del states
+            sim.raise_on_status("rollout backward pass (recomputed segments)")
             return (None, None, None, None, None) + tuple(lam)
 
     class CurlFn(torch.autograd.Function):

@@ -38,8 +38,22 @@ VLCT_DEV double msqrt(double x)
     g = fma(d, h, g);
     return x == 0.0 ? x : g;  // rsq(0) is infinite
 }
+// Reciprocal square root of a finite argument > 0 in the normal range: the
+// hardware estimate refined by two Newton steps y <- y + y (1 - x y^2) / 2
+// (each doubles the correct bits of the estimate), within about an ulp.
+// One of these replaces a square root and a division where both the root and
+// its reciprocal are needed.
+VLCT_DEV double mrsqrt(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double r = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, r, y);
+    r = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, r, y);
+}
 #else
 VLCT_DEV double msqrt(double x) { return sqrt(x); }
+VLCT_DEV double mrsqrt(double x) { return 1.0 / sqrt(x); }
 #endif
 
 // Floors on derived and reconstructed rho, P (the conserved state is never changed).
@@ -105,9 +119,18 @@ VLCT_DEV void hlld(const W7 &L, const W7 &R, double bn, double gam, double gm1i,
     const double ptR = R.p + pbR;
     const double eL = L.p * gm1i + 0.5 * L.d * (L.u * L.u + L.v * L.v + L.w * L.w) + pbL;
     const double eR = R.p * gm1i + 0.5 * R.d * (R.u * R.u + R.v * R.v + R.w * R.w) + pbR;
-    double discL, discR;
-    const double cfL = msqrt(fast_sq(L.d, L.p, bn, L.by, L.bz, gam, discL));
-    const double cfR = msqrt(fast_sq(R.d, R.p, bn, R.by, R.bz, gam, discR));
+    // c_f = sqrt(num / (2 rho)) = num / sqrt(2 rho num), num = gP + B^2 + disc
+    // (the fast-speed formula of fast_sq with one reciprocal root per side)
+    auto fast = [&](const W7 &X) {
+        const double gp = gam * X.p;
+        const double bp2 = X.by * X.by + X.bz * X.bz;
+        const double b2 = bn2 + bp2;
+        const double t = gp - b2;
+        const double num = gp + b2 + msqrt(t * t + 4.0 * gp * bp2);
+        return num * mrsqrt(2.0 * X.d * num);
+    };
+    const double cfL = fast(L);
+    const double cfR = fast(R);
     const double cmax = fmax(cfL, cfR);
     const double sL = fmin(L.u, R.u) - cmax;
     const double sR = fmax(L.u, R.u) + cmax;
@@ -141,7 +164,8 @@ VLCT_DEV void hlld(const W7 &L, const W7 &R, double bn, double gam, double gm1i,
     }
     // double-star states (shared by both sides)
     const double sg = bn >= 0.0 ? 1.0 : -1.0;
-    const double rL = msqrt(ds[0]), rR = msqrt(ds[1]);
+    const double irL = mrsqrt(ds[0]), irR = mrsqrt(ds[1]);
+    const double rL = ds[0] * irL, rR = ds[1] * irR;
     const double isum = 1.0 / (rL + rR);
     const double vss = (rL * vs[0] + rR * vs[1] + sg * (bys[1] - bys[0])) * isum;
     const double wss = (rL * ws[0] + rR * ws[1] + sg * (bzs[1] - bzs[0])) * isum;
@@ -157,7 +181,7 @@ VLCT_DEV void hlld(const W7 &L, const W7 &R, double bn, double gam, double gm1i,
     const double pt = left ? ptL : ptR;
     const double e = left ? eL : eR;
     const double r = left ? rL : rR;
-    const double car = fabs(bn) / r;
+    const double car = fabs(bn) * (left ? irL : irR);
     const double ss = left ? sM - car : sM + car;
     const bool star_only = left ? (ss >= 0.0) : (ss <= 0.0);
     // its single-star energy and the double-star correction
@@ -222,30 +246,36 @@ struct Eigen {
 
 VLCT_DEV void eigen_setup(const W7 &c, double bn_in, double gam, Eigen &E)
 {
-    // field components below kBperpTiny of the magnetosonic scale are rounding
-    // noise and are zero here, so noise cannot turn the B_perp direction
-    const double bscale = msqrt(gam * c.p + bn_in * bn_in + c.by * c.by + c.bz * c.bz);
-    const double bn = fabs(bn_in) <= kBperpTiny * bscale ? 0.0 : bn_in;
-    const double bt1 = fabs(c.by) <= kBperpTiny * bscale ? 0.0 : c.by;
-    const double bt2 = fabs(c.bz) <= kBperpTiny * bscale ? 0.0 : c.bz;
-    const double id = 1.0 / c.d;
+    // field components below kBperpTiny of the magnetosonic scale
+    // sqrt(gP + B^2) are rounding noise and are zero here, so noise cannot
+    // turn the B_perp direction (compared in squares)
     const double gp = gam * c.p;
+    const double tiny2 =
+        kBperpTiny * kBperpTiny * (gp + bn_in * bn_in + c.by * c.by + c.bz * c.bz);
+    const double bn = bn_in * bn_in <= tiny2 ? 0.0 : bn_in;
+    const double bt1 = c.by * c.by <= tiny2 ? 0.0 : c.by;
+    const double bt2 = c.bz * c.bz <= tiny2 ? 0.0 : c.bz;
+    // r = 1/sqrt(rho), q = 1/sqrt(gP): every root and reciprocal of rho and gP
+    // below follows from these two
+    const double r = mrsqrt(c.d), q = mrsqrt(gp);
+    const double id = r * r;
     E.d = c.d;
-    E.sqd = msqrt(c.d);
+    E.sqd = c.d * r;
     E.asq = gp * id;
-    E.a = msqrt(E.asq);
-    E.ia2 = c.d / gp;
-    double disc;
-    const double cf2 = fast_sq(c.d, c.p, bn, bt1, bt2, gam, disc);
-    const double cs2 = E.asq * bn * bn * id / cf2;
+    E.a = gp * q * r;          // sqrt(gP / rho)
+    E.ia2 = c.d * q * q;       // rho / (gP)
+    const double bp2 = bt1 * bt1 + bt2 * bt2;
+    const double t = gp - (bn * bn + bp2);
+    const double disc = msqrt(t * t + 4.0 * gp * bp2);
+    const double cf2 = (gp + bn * bn + bp2 + disc) * (0.5 * id);
     E.cf = msqrt(cf2);
-    E.cs = msqrt(cs2);
-    const double bp = msqrt(bt1 * bt1 + bt2 * bt2);
-    const bool haveperp = bp > kBperpTiny * bscale;
-    const double ibp = 1.0 / bp;
+    // c_s = a |B_n| / (sqrt(rho) c_f), the root of gP B_n^2 / (rho^2 c_f^2)
+    E.cs = E.a * fabs(bn) * r / E.cf;
+    const bool haveperp = bp2 > tiny2;
+    const double ibp = mrsqrt(haveperp ? bp2 : 1.0);
     E.by = haveperp ? bt1 * ibp : 0.70710678118654752440;
     E.bz = haveperp ? bt2 * ibp : 0.70710678118654752440;
-    const double tdiff = gam * c.p - (bn * bn + bt1 * bt1 + bt2 * bt2);
+    const double tdiff = t;
     const bool split = disc > kCfCsTiny * c.d * cf2;
     const double idisc = 0.5 / disc;
     const double af2 = fmin(fmax((disc + tdiff) * idisc, 0.0), 1.0);
@@ -260,11 +290,9 @@ VLCT_DEV void eigen_setup(const W7 &c, double bn_in, double gam, Eigen &E)
     E.qs = 0.5 * E.s * E.af * E.cf * ia2;
     E.pf = 0.5 * E.af * ia2 * id;
     E.ps = 0.5 * E.as * ia2 * id;
-    const double isqd = 1.0 / E.sqd;
-    const double iasq = isqd / E.a;      // 1 / (a sqrt(rho))
-    E.bf = 0.5 * E.as * iasq;
-    E.bs = -0.5 * E.af * iasq;
-    E.sr = 0.5 * E.s * isqd;
+    E.bf = 0.5 * E.as * q;     // q = 1 / (a sqrt(rho))
+    E.bs = -0.5 * E.af * q;
+    E.sr = 0.5 * E.s * r;
 }
 
 // characteristic amplitudes a = L dW of a primitive increment dW

@@ -35,7 +35,8 @@ constexpr int kCt = kTx * kTy;  // threads of a CT block: one per column of the 
 
 // tile variants a batched step can give each instance (its plan byte: CT
 // variant in the low nibble, march variant in the high nibble); variant 0 is
-// the single-instance kernels' shape
+// the single-instance CT tile and the 16-face march (single steps on small
+// grids march 8 faces; every variant computes the same bits)
 constexpr int kCtVariants = 3;     // CT column tiles 64 x 8, 32 x 16, 16 x 32 (kCt threads)
 constexpr int kMarchVariants = 3;  // march segments of 16, 32 and 8 faces
 __host__ __device__ constexpr int ct_tx(int v) { return v == 0 ? 64 : (v == 1 ? 32 : 16); }

@@ -160,6 +160,28 @@ def test_checkpointed_rollout_gradient_independent_of_segment():
             assert np.abs(a - b).max() <= ROLLOUT_ORDER_TOL * np.abs(a).max(), name
 
 
+def test_rollout_reports_floors():
+    """A rollout whose forward pass reaches the pressure floor raises instead
+    of returning the floored branch's loss and gradient silently."""
+    _need_gpu()
+    import torch
+    from paper_2402_05240_amd import autograd as AG
+    g = _grid((10, 9, 11))
+    rho, v, p, A = _params(g, 5)
+    s = _state_from(g, rho, v, p, A)
+    s["E"] = s["E"].copy()
+    s["E"][3, 4, 5] -= 10.0 * float(np.max(p))  # a negative pressure in one cell
+    sim = AG.Simulator(g)
+    fields = [torch.from_numpy(s[f]).cuda().requires_grad_(True) for f in FIELDS]
+    with pytest.raises(FloatingPointError):
+        AG.rollout(sim, fields, nsteps=2, segment=1)
+    # a clean state passes, and the status word was reset for it
+    s = _state_from(g, rho, v, p, A)
+    fields = [torch.from_numpy(s[f]).cuda().requires_grad_(True) for f in FIELDS]
+    out, _ = AG.rollout(sim, fields, nsteps=2, segment=1)
+    torch.autograd.backward(out, [torch.ones_like(o) for o in out])
+
+
 def test_taped_step_and_adjoint_equal_untaped():
     """vlct_step_taped writes exactly what vlct_step writes (state and next
     dt); the adjoint from its tape equals the self-contained adjoint up to the
