@@ -182,6 +182,12 @@ def workload_bench(name, warmup=3):
             "status": st.status_bits()}
 
 
+def progress(msg):
+    """One line on stderr per finished part of the run (the JSON result goes
+    to stdout alone)."""
+    print("bench: %s" % msg, file=sys.stderr, flush=True)
+
+
 def make_workload(name):
     from paper_2402_05240_amd import inputs as I
     w = WORKLOADS[name]
@@ -629,6 +635,7 @@ def ensemble_bench(count, steps, warmup):
                 n += 1
             found.append(n)
         return found
+    progress("ensemble: batched to one period each, %d batched steps" % nbatch)
     counts = seq_run()          # untimed: each instance's step count
     torch.cuda.synchronize()
     ea.record()
@@ -939,17 +946,21 @@ def main():
     }
     del st
     torch.cuda.empty_cache()
+    progress("headline %s: %.3f ms per step" % (args.workload, ms_step))
     if not args.no_adjoint:
         recon = {v.lower(): k for k, v in RECON_NAMES.items()}[args.adjoint_recon]
         costs = [adjoint_bench(n, args.adjoint_steps, 2, recon) for n in args.adjoint_n]
         out["adjoint_forward_cost"] = costs[0] if len(costs) == 1 else costs
         torch.cuda.empty_cache()
+        progress("adjoint cost")
     if not args.no_inverse:
         out["inverse_problem"] = inverse_bench(args.inverse_n, args.inverse_steps)
         torch.cuda.empty_cache()
+        progress("inverse problem")
     if not args.no_ensemble:
         torch.cuda.empty_cache()
         out["ensemble"] = ensemble_bench(64, args.ensemble_steps, 2)
+        progress("ensemble")
     if not args.no_workloads:
         torch.cuda.empty_cache()
         out["workloads"] = {}
@@ -957,6 +968,7 @@ def main():
             if name != args.workload:
                 out["workloads"][name] = workload_bench(name)
                 torch.cuda.empty_cache()
+                progress("workload %s" % name)
     if not args.no_cpu_baseline:
         torch.cuda.empty_cache()
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
@@ -964,6 +976,7 @@ def main():
         # the same oracle on one host thread, on a thinner slab of the same state
         one = cpu_baseline(g, s0, max(1, args.cpu_planes // 16), args.cpu_steps, 1)
         out["cpu_baseline"]["one_thread"] = one
+        progress("cpu baseline")
     print(json.dumps(out), flush=True)
 
 

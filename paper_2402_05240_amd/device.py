@@ -164,30 +164,43 @@ class BatchStepper:
     def run_until(self, t_end, check_every: int = 8, max_steps: int = 100000):
         """Advance every instance in place to its own end time t_end[i]
         (vlct_step_batch_until: the last step of each is clipped to land on
-        it, finished instances drop out of the kernels); returns the number
-        of batched steps.  The host looks at the times every `check_every`
-        steps only."""
+        it, finished instances drop out of the kernels on the device).  Every
+        `check_every` steps the host reads the times and launches only the
+        instances still running from then on (their dt, next dt, status and
+        time gathered into compact device arrays), so a long-running few no
+        longer carry the empty blocks of the rest.  Returns the number of
+        batched steps."""
         torch = _torch()
         if self.nxt is not self.cur:
             raise ValueError("run_until steps in place")
         n = len(self.grids)
         self.t = torch.zeros(n, dtype=torch.float64, device=self.device)
         tend = torch.tensor([float(x) for x in t_end], dtype=torch.float64, device=self.device)
+        active = list(range(n))
         steps = 0
-        while steps < max_steps:
+        while active and steps < max_steps:
+            idx = torch.tensor(active, dtype=torch.long, device=self.device)
+            t_a, te_a = self.t[idx].contiguous(), tend[idx].contiguous()
+            dt_a, st_a = self.dt[idx].contiguous(), self.status[idx].contiguous()
+            nd_a = torch.empty_like(dt_a)
+            grids = [self.cgs[i] for i in active]
+            states = [self.cur[i].c_state() for i in active]
+            plan = [self.plan[i] for i in active] if self.plan is not None else None
             for _ in range(check_every):
-                rc = vlct.vlct_step_batch_until(self.cgs, [d.c_state() for d in self.cur],
-                                                self.dt.data_ptr(), self.next_dt.data_ptr(),
-                                                self.status.data_ptr(), self.t.data_ptr(),
-                                                tend.data_ptr(), self.plan, self.ws.data_ptr(),
-                                                self.ws_bytes, self.stream())
+                rc = vlct.vlct_step_batch_until(grids, states, dt_a.data_ptr(), nd_a.data_ptr(),
+                                                st_a.data_ptr(), t_a.data_ptr(), te_a.data_ptr(),
+                                                plan, self.ws.data_ptr(), self.ws_bytes,
+                                                self.stream())
                 if rc:
                     raise vlct.VlctError(rc, "vlct_step_batch_until")
                 # a finished instance keeps its dt; a running one takes its next CFL step
-                self.dt.copy_(torch.where(self.t < tend, self.next_dt, self.dt))
+                dt_a.copy_(torch.where(t_a < te_a, nd_a, dt_a))
                 steps += 1
-            if bool((self.t >= tend).all()):
-                break
+            self.t[idx] = t_a
+            self.dt[idx] = dt_a
+            self.status[idx] = st_a
+            running = (t_a < te_a).cpu().tolist()
+            active = [i for i, r in zip(active, running) if r]
         return steps
 
     def tune(self, reps: int = 3):
