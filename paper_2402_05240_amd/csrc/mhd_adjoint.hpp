@@ -26,31 +26,31 @@ struct FastSq {
     double gp, bp2, b2, t, disc, cf2;
 };
 
-VLCT_DEV FastSq fast_sq_fwd(double d, double p, double bn, double bt1, double bt2, double gam)
+// the terms of cf2 up to the numerator gP + B^2 + disc
+VLCT_DEV FastSq fast_sq_terms(double p, double bn2, double bt1, double bt2, double gam)
 {
     FastSq q;
     q.gp = gam * p;
     q.bp2 = bt1 * bt1 + bt2 * bt2;
-    q.b2 = bn * bn + q.bp2;
+    q.b2 = bn2 + q.bp2;
     q.t = q.gp - q.b2;
     q.disc = msqrt(q.t * q.t + 4.0 * q.gp * q.bp2);
-    q.cf2 = (q.gp + q.b2 + q.disc) / (2.0 * d);
+    q.cf2 = 0.0;
     return q;
 }
 
-// adds the cotangents of (d, p, bn, bt1, bt2) given those of cf2 and disc
-VLCT_DEV void fast_sq_rev(const FastSq &q, double d, double bn, double bt1, double bt2, double gam,
-                          double a_cf2, double a_disc, double &a_d, double &a_p, double &a_bn,
-                          double &a_bt1, double &a_bt2)
+// adds the cotangents of (d, p, bn, bt1, bt2) given those of cf2 and disc;
+// i2d = 1 / (2 rho), idc = 1 / disc (read only where disc > 0)
+VLCT_DEV void fast_sq_rev(const FastSq &q, double i2d, double idc, double bn, double bt1,
+                          double bt2, double gam, double a_cf2, double a_disc, double &a_d,
+                          double &a_p, double &a_bn, double &a_bt1, double &a_bt2)
 {
-    const double i2d = 1.0 / (2.0 * d);
     double a_gp = a_cf2 * i2d;
     double a_b2 = a_cf2 * i2d;
     a_disc = a_disc + a_cf2 * i2d;
-    a_d = a_d - a_cf2 * q.cf2 / d;
+    a_d = a_d - a_cf2 * q.cf2 * (2.0 * i2d);  // d cf2 / d rho = -cf2 / rho
     double a_bp2 = 0.0;
     if (q.disc > 0.0) {
-        const double idc = 1.0 / q.disc;
         const double a_t = a_disc * q.t * idc;
         a_gp = a_gp + a_disc * 2.0 * q.bp2 * idc + a_t;
         a_bp2 = a_disc * 2.0 * q.gp * idc;
@@ -79,9 +79,16 @@ VLCT_DEV void hlld_rev(const W7 &L, const W7 &R, double bn, double gam, double g
     const double u2R = R.u * R.u + R.v * R.v + R.w * R.w;
     const double eL = L.p * gm1i + 0.5 * L.d * u2L + pbL;
     const double eR = R.p * gm1i + 0.5 * R.d * u2R + pbR;
-    const FastSq qfL = fast_sq_fwd(L.d, L.p, bn, L.by, L.bz, gam);
-    const FastSq qfR = fast_sq_fwd(R.d, R.p, bn, R.by, R.bz, gam);
-    const double cfL = msqrt(qfL.cf2), cfR = msqrt(qfR.cf2);
+    // c_f = num rq, rq = 1 / sqrt(2 rho num), num = gP + B^2 + disc; then
+    // 1 / c_f = 2 rho rq and 1 / (2 rho) = num rq^2
+    FastSq qfL = fast_sq_terms(L.p, bn2, L.by, L.bz, gam);
+    FastSq qfR = fast_sq_terms(R.p, bn2, R.by, R.bz, gam);
+    const double numL = qfL.gp + qfL.b2 + qfL.disc, numR = qfR.gp + qfR.b2 + qfR.disc;
+    const double rqL = mrsqrt(2.0 * L.d * numL), rqR = mrsqrt(2.0 * R.d * numR);
+    const double cfL = numL * rqL, cfR = numR * rqR;
+    const double i2dL = numL * rqL * rqL, i2dR = numR * rqR * rqR;
+    qfL.cf2 = numL * i2dL;
+    qfR.cf2 = numR * i2dR;
     const bool cmaxR = takes_second_max(cfL, cfR);
     const double cmax = cmaxR ? cfR : cfL;
     const bool uminR = takes_second_min(L.u, R.u);
@@ -124,7 +131,8 @@ VLCT_DEV void hlld_rev(const W7 &L, const W7 &R, double bn, double gam, double g
         es[a] = num_e[a] * issm[a];
     }
     const double sg = bn >= 0.0 ? 1.0 : -1.0;
-    const double rL = msqrt(ds[0]), rR = msqrt(ds[1]);
+    const double irL = mrsqrt(ds[0]), irR = mrsqrt(ds[1]);
+    const double rL = ds[0] * irL, rR = ds[1] * irR;
     const double isum = 1.0 / (rL + rR);
     const double nv = rL * vs[0] + rR * vs[1] + sg * (bys[1] - bys[0]);
     const double nw = rL * ws[0] + rR * ws[1] + sg * (bzs[1] - bzs[0]);
@@ -139,7 +147,8 @@ VLCT_DEV void hlld_rev(const W7 &L, const W7 &R, double bn, double gam, double g
     const double pt = left ? ptL : ptR;
     const double e = left ? eL : eR;
     const double r = left ? rL : rR;
-    const double ss = left ? sM - fabs(bn) / rL : sM + fabs(bn) / rR;
+    const double car = fabs(bn) * (left ? irL : irR);
+    const double ss = left ? sM - car : sM + car;
     const bool star_only = left ? (ss >= 0.0) : (ss <= 0.0);
     const double vbs_a = left ? vbs[0] : vbs[1];
     const double ess = left ? es[0] - r * sg * (vbs[0] - vbss) : es[1] + r * sg * (vbs[1] - vbss);
@@ -259,11 +268,11 @@ VLCT_DEV void hlld_rev(const W7 &L, const W7 &R, double bn, double gam, double g
     // ss
     a_sM = a_sM + a_ss;
     if (left) {
-        a_bn = a_bn - a_ss * abs_slope(bn) / rL;
-        a_rL = a_rL + a_ss * fabs(bn) / (rL * rL);
+        a_bn = a_bn - a_ss * abs_slope(bn) * irL;
+        a_rL = a_rL + a_ss * fabs(bn) * (irL * irL);
     } else {
-        a_bn = a_bn + a_ss * abs_slope(bn) / rR;
-        a_rR = a_rR - a_ss * fabs(bn) / (rR * rR);
+        a_bn = a_bn + a_ss * abs_slope(bn) * irR;
+        a_rR = a_rR - a_ss * fabs(bn) * (irR * irR);
     }
     // vbss
     a_sM = a_sM + a_vbss * bn;
@@ -293,8 +302,8 @@ VLCT_DEV void hlld_rev(const W7 &L, const W7 &R, double bn, double gam, double g
         const double a_rsum = -a_isum * isum * isum;
         a_rL = a_rL + a_rsum;
         a_rR = a_rR + a_rsum;
-        a_ds[0] = a_ds[0] + a_rL * sqrt_slope(rL);
-        a_ds[1] = a_ds[1] + a_rR * sqrt_slope(rR);
+        a_ds[0] = a_ds[0] + a_rL * (0.5 * irL);
+        a_ds[1] = a_ds[1] + a_rR * (0.5 * irR);
     }
     // single-star states of both sides
     double aLs[7] = {0, 0, 0, 0, 0, 0, 0}, aRs[7] = {0, 0, 0, 0, 0, 0, 0};  // d u v w (p unused) by bz
@@ -405,9 +414,12 @@ VLCT_DEV void hlld_rev(const W7 &L, const W7 &R, double bn, double gam, double g
     double a_byR = R.by * a_pbR, a_bzR = R.bz * a_pbR;
     a_bn2 = a_bn2 + 0.5 * (a_pbL + a_pbR);
     // fast speeds
-    fast_sq_rev(qfL, L.d, bn, L.by, L.bz, gam, a_cfL * sqrt_slope(cfL), 0.0, a_dL, a_pL, a_bn,
+    // d c_f / d cf2 = 1 / (2 c_f) = rho rq
+    const double idcL = qfL.disc > 0.0 ? 1.0 / qfL.disc : 0.0;
+    const double idcR = qfR.disc > 0.0 ? 1.0 / qfR.disc : 0.0;
+    fast_sq_rev(qfL, i2dL, idcL, bn, L.by, L.bz, gam, a_cfL * (L.d * rqL), 0.0, a_dL, a_pL, a_bn,
                 a_byL, a_bzL);
-    fast_sq_rev(qfR, R.d, bn, R.by, R.bz, gam, a_cfR * sqrt_slope(cfR), 0.0, a_dR, a_pR, a_bn,
+    fast_sq_rev(qfR, i2dR, idcR, bn, R.by, R.bz, gam, a_cfR * (R.d * rqR), 0.0, a_dR, a_pR, a_bn,
                 a_byR, a_bzR);
     a_bn = a_bn + 2.0 * bn * a_bn2;
 
@@ -448,28 +460,35 @@ VLCT_DEV void eigen_zero(EigenA &A)
 VLCT_DEV void eigen_rev(const W7 &c, double bn_in, double gam, const EigenA &A, W7 &a_c,
                         double &a_bn_in)
 {
-    // forward
-    const double bscale = msqrt(gam * c.p + bn_in * bn_in + c.by * c.by + c.bz * c.bz);
-    const bool snap_n = fabs(bn_in) <= kBperpTiny * bscale;
-    const bool snap_1 = fabs(c.by) <= kBperpTiny * bscale;
-    const bool snap_2 = fabs(c.bz) <= kBperpTiny * bscale;
+    // forward (the formulas of eigen_setup)
+    const double gp = gam * c.p;
+    const double tiny2 =
+        kBperpTiny * kBperpTiny * (gp + bn_in * bn_in + c.by * c.by + c.bz * c.bz);
+    const bool snap_n = bn_in * bn_in <= tiny2;
+    const bool snap_1 = c.by * c.by <= tiny2;
+    const bool snap_2 = c.bz * c.bz <= tiny2;
     const double bn = snap_n ? 0.0 : bn_in;
     const double bt1 = snap_1 ? 0.0 : c.by;
     const double bt2 = snap_2 ? 0.0 : c.bz;
-    const double id = 1.0 / c.d;
-    const double gp = gam * c.p;
-    const double sqd = msqrt(c.d);
+    // r = 1/sqrt(rho), q = 1/sqrt(gP)
+    const double r = mrsqrt(c.d), q = mrsqrt(gp);
+    const double id = r * r;
+    const double sqd = c.d * r;
     const double asq = gp * id;
-    const double a = msqrt(asq);
-    const double ia2 = c.d / gp;
-    const FastSq q = fast_sq_fwd(c.d, c.p, bn, bt1, bt2, gam);
-    const double cf2 = q.cf2, disc = q.disc;
-    const double cs2 = asq * bn * bn * id / cf2;
-    const double cf = msqrt(cf2), cs = msqrt(cs2);
-    const double bp = msqrt(bt1 * bt1 + bt2 * bt2);
-    const bool haveperp = bp > kBperpTiny * bscale;
-    const double ibp = 1.0 / bp;
-    const double tdiff = gam * c.p - (bn * bn + bt1 * bt1 + bt2 * bt2);
+    const double a = gp * q * r;
+    const double ia = sqd * q;  // 1 / a
+    const double ia2 = c.d * q * q;
+    FastSq fq = fast_sq_terms(c.p, bn * bn, bt1, bt2, gam);
+    const double bp2 = fq.bp2, disc = fq.disc;
+    const double cf2 = (gp + bn * bn + bp2 + disc) * (0.5 * id);
+    fq.cf2 = cf2;
+    const double cf = msqrt(cf2);
+    const double icf = 1.0 / cf;
+    const double kcs = a * r * icf;  // c_s / |B_n|
+    const double cs = kcs * fabs(bn);
+    const bool haveperp = bp2 > tiny2;
+    const double ibp = mrsqrt(haveperp ? bp2 : 1.0);
+    const double tdiff = fq.t;
     const bool split = disc > kCfCsTiny * c.d * cf2;
     const double idisc = 0.5 / disc;
     const double qfv = (disc + tdiff) * idisc, qsv = (disc - tdiff) * idisc;
@@ -478,17 +497,16 @@ VLCT_DEV void eigen_rev(const W7 &c, double bn_in, double gam, const EigenA &A, 
     const double af = split ? msqrt(af2) : 1.0;
     const double as = split ? msqrt(as2) : 0.0;
     const double s = bn >= 0.0 ? 1.0 : -1.0;
-    const double isqd = 1.0 / sqd;
-    const double iasq = isqd / a;
+    // 1 / sqrt(rho) = r and 1 / (a sqrt(rho)) = q
 
     // reverse
     double a_isqd = 0.5 * s * A.sr;
-    double a_af = A.af - 0.5 * iasq * A.bs;
-    double a_as = A.as + 0.5 * iasq * A.bf;
+    double a_af = A.af - 0.5 * q * A.bs;
+    double a_as = A.as + 0.5 * q * A.bf;
     const double a_iasq = -0.5 * af * A.bs + 0.5 * as * A.bf;
-    a_isqd = a_isqd + a_iasq / a;
-    double a_a = A.a - a_iasq * iasq / a;
-    double a_sqd = A.sqd - a_isqd * isqd * isqd;
+    a_isqd = a_isqd + a_iasq * ia;
+    double a_a = A.a - a_iasq * q * ia;
+    double a_sqd = A.sqd - a_isqd * id;
     double a_ia2 = A.ia2;
     double a_id = 0.0;
     a_as = a_as + 0.5 * ia2 * id * A.ps;
@@ -513,37 +531,38 @@ VLCT_DEV void eigen_rev(const W7 &c, double bn_in, double gam, const EigenA &A, 
         const double a_qf = (qfv >= 0.0 && qfv <= 1.0) ? a_af2 : 0.0;
         const double a_qs = (qsv >= 0.0 && qsv <= 1.0) ? a_as2 : 0.0;
         const double a_idisc = (disc + tdiff) * a_qf + (disc - tdiff) * a_qs;
-        a_disc = idisc * (a_qf + a_qs) - a_idisc * idisc / disc;
+        a_disc = idisc * (a_qf + a_qs) - a_idisc * (2.0 * idisc * idisc);
         a_tdiff = idisc * (a_qf - a_qs);
     }
     double a_d = A.d, a_p = gam * a_tdiff, a_bn = -2.0 * bn * a_tdiff;
     double a_bt1 = -2.0 * bt1 * a_tdiff, a_bt2 = -2.0 * bt2 * a_tdiff;
-    // beta_t1, beta_t2
+    // beta_t1, beta_t2 = bt / sqrt(bp2)
     if (haveperp) {
         a_bt1 = a_bt1 + ibp * A.by;
         a_bt2 = a_bt2 + ibp * A.bz;
         const double a_ibp = bt1 * A.by + bt2 * A.bz;
         const double a_bp = -a_ibp * ibp * ibp;
-        if (bp > 0.0) {
-            a_bt1 = a_bt1 + bt1 / bp * a_bp;
-            a_bt2 = a_bt2 + bt2 / bp * a_bp;
-        }
+        a_bt1 = a_bt1 + bt1 * ibp * a_bp;
+        a_bt2 = a_bt2 + bt2 * ibp * a_bp;
     }
-    // slow and fast speeds
-    const double a_cs2 = a_cs * sqrt_slope(cs);
-    double a_cf2 = a_cf * sqrt_slope(cf);
-    double a_asq = a_cs2 * bn * bn * id / cf2;
-    a_bn = a_bn + a_cs2 * 2.0 * asq * bn * id / cf2;
-    a_id = a_id + a_cs2 * asq * bn * bn / cf2;
-    a_cf2 = a_cf2 - a_cs2 * cs2 / cf2;
-    fast_sq_rev(q, c.d, bn, bt1, bt2, gam, a_cf2, a_disc, a_d, a_p, a_bn, a_bt1, a_bt2);
-    // sound speed, rho^(1/2), 1/a^2
-    a_d = a_d + a_ia2 / gp;
-    double a_gp = -a_ia2 * ia2 / gp;
-    a_asq = a_asq + A.asq + a_a * sqrt_slope(a);
+    // slow and fast speeds: c_s^2 = a^2 B_n^2 / (rho c_f^2), so with
+    // h = c_s a_cs / 2 the slow speed sends h / a^2 to a^2, h rho to 1/rho and
+    // -h / c_f^2 to c_f^2, and c_s / B_n to B_n
+    const double h = 0.5 * a_cs * cs;
+    double a_cf2 = a_cf * (0.5 * icf);
+    double a_asq = h * ia2;
+    a_bn = a_bn + a_cs * kcs * s;
+    a_id = a_id + h * c.d;
+    a_cf2 = a_cf2 - h * (icf * icf);
+    fast_sq_rev(fq, 0.5 * id, 2.0 * idisc, bn, bt1, bt2, gam, a_cf2, a_disc, a_d, a_p, a_bn,
+                a_bt1, a_bt2);
+    // sound speed, rho^(1/2), 1/a^2 = rho / (gP)
+    a_d = a_d + a_ia2 * (q * q);
+    double a_gp = -a_ia2 * ia2 * (q * q);
+    a_asq = a_asq + A.asq + a_a * (0.5 * ia);
     a_gp = a_gp + id * a_asq;
     a_id = a_id + gp * a_asq;
-    a_d = a_d + a_sqd * sqrt_slope(sqd);
+    a_d = a_d + a_sqd * (0.5 * r);
     a_p = a_p + gam * a_gp;
     a_d = a_d - a_id * id * id;
     a_c.d = a_c.d + a_d;

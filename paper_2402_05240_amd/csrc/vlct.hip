@@ -431,6 +431,22 @@ __device__ __forceinline__ double upwind(double s, double lo, double hi)
     return s > 0.0 ? lo : (s < 0.0 ? hi : 0.5 * (lo + hi));
 }
 
+// the edge field from the EMFs and upwind indicators of its four faces and the
+// reference fields of its four cells: B-faces at x0 and x0 - e_C, C-faces at
+// x0 and x0 - e_B
+__device__ __forceinline__ double edge_combine(double eb_c, double eb_cm, double ec_b,
+                                               double ec_bm, double sb_c, double sb_cm,
+                                               double sc_b, double sc_bm, double r00, double r10,
+                                               double r01, double r11)
+{
+    const double avg = 0.25 * (eb_c + eb_cm + ec_b + ec_bm);
+    const double t1 = upwind(sb_c, ec_bm - r10, ec_b - r00);
+    const double t2 = upwind(sb_cm, ec_bm - r11, ec_b - r01);
+    const double t3 = upwind(sc_b, eb_cm - r01, eb_c - r00);
+    const double t4 = upwind(sc_bm, eb_cm - r11, eb_c - r10);
+    return avg + 0.25 * (t1 + t2 + t3 + t4);
+}
+
 template <int A>
 __device__ __forceinline__ double edge_emf(const Geom &g, const Flux &F, int i, int j, int k,
                                            double r00, double r10, double r01, double r11)
@@ -448,16 +464,54 @@ __device__ __forceinline__ double edge_emf(const Geom &g, const Flux &F, int i, 
     const idx_t fc_b = fidx(g, C, x0[0], x0[1], x0[2]);
     const idx_t fc_bm = fidx(g, C, xb[0], xb[1], xb[2]);
     // B-face EMF component A = -F_B[B_t1]; C-face EMF component A = +F_C[B_t2]
-    const double eb_c = -F.f[B][5][fb_c], eb_cm = -F.f[B][5][fb_cm];
-    const double ec_b = F.f[C][6][fc_b], ec_bm = F.f[C][6][fc_bm];
-    const double sb_c = F.sg[B][fb_c], sb_cm = F.sg[B][fb_cm];
-    const double sc_b = F.sg[C][fc_b], sc_bm = F.sg[C][fc_bm];
-    const double avg = 0.25 * (eb_c + eb_cm + ec_b + ec_bm);
-    const double t1 = upwind(sb_c, ec_bm - r10, ec_b - r00);
-    const double t2 = upwind(sb_cm, ec_bm - r11, ec_b - r01);
-    const double t3 = upwind(sc_b, eb_cm - r01, eb_c - r00);
-    const double t4 = upwind(sc_bm, eb_cm - r11, eb_c - r10);
-    return avg + 0.25 * (t1 + t2 + t3 + t4);
+    return edge_combine(-F.f[B][5][fb_c], -F.f[B][5][fb_cm], F.f[C][6][fc_b], F.f[C][6][fc_bm],
+                        F.sg[B][fb_c], F.sg[B][fb_cm], F.sg[C][fc_b], F.sg[C][fc_bm], r00, r10,
+                        r01, r11);
+}
+
+// E_x (A = 0) or E_y (A = 1) at the half plane k - 1/2 for a block marching up
+// in z: of its four faces, the one at x0 - e_z (the B-face for E_x, the
+// C-face for E_y) is the face at x0 of the half plane below, so its EMF and
+// upwind indicator come in through (ez, sz) and those at x0 go out through
+// them for the next half plane.  FIRST: the lower face is read, as edge_emf
+// reads it.
+template <int A, bool FIRST>
+__device__ __forceinline__ double edge_emf_zcarry(const Geom &g, const Flux &F, int i, int j,
+                                                  int k, double r00, double r10, double r01,
+                                                  double r11, double &ez, int8_t &sz)
+{
+    static_assert(A == 0 || A == 1, "the z-marching carry serves E_x and E_y");
+    constexpr int B = (A + 1) % 3, C = (A + 2) % 3;
+    constexpr int Z = A == 0 ? B : C;  // the face axis whose faces stack along z
+    constexpr int T = A == 0 ? C : B;  // the face axis whose two faces share the plane
+    const idx_t fz_hi = fidx(g, Z, i, j, k);
+    int xt[3] = {i, j, k};
+    xt[A == 0 ? B : C] -= 1;  // the in-plane neighbour of the T-faces
+    const idx_t ft_0 = fidx(g, T, i, j, k), ft_1 = fidx(g, T, xt[0], xt[1], xt[2]);
+    // EMF component A: -F_B[B_t1] on a B-face, +F_C[B_t2] on a C-face
+    constexpr int zcomp = Z == B ? 5 : 6, tcomp = T == B ? 5 : 6;
+    double e_lo, s_lo;
+    if (FIRST) {
+        const idx_t fz_lo = fidx(g, Z, i, j, k - 1);
+        e_lo = Z == B ? -F.f[Z][zcomp][fz_lo] : F.f[Z][zcomp][fz_lo];
+        s_lo = F.sg[Z][fz_lo];
+    } else {
+        e_lo = ez;
+        s_lo = sz;
+    }
+    const double e_hi = Z == B ? -F.f[Z][zcomp][fz_hi] : F.f[Z][zcomp][fz_hi];
+    const int8_t s_hi = F.sg[Z][fz_hi];
+    const double et0 = T == B ? -F.f[T][tcomp][ft_0] : F.f[T][tcomp][ft_0];
+    const double et1 = T == B ? -F.f[T][tcomp][ft_1] : F.f[T][tcomp][ft_1];
+    const double st0 = F.sg[T][ft_0], st1 = F.sg[T][ft_1];
+    ez = e_hi;
+    sz = s_hi;
+    if (A == 0)  // B = y stacked along z (x0 - e_C = lower), C = z faces at x0 and x0 - e_y
+        return edge_combine(e_hi, e_lo, et0, et1, (double)s_hi, s_lo, st0, st1, r00, r10, r01,
+                            r11);
+    else  // B = z faces at x0 and x0 - e_x, C = x stacked along z (x0 - e_B = lower)
+        return edge_combine(et0, et1, e_hi, e_lo, st0, st1, (double)s_hi, s_lo, r00, r10, r01,
+                            r11);
 }
 
 // ---------------------------------------------------------------------------
@@ -486,6 +540,9 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
     // cell-centred -(v x B) of the tile plus a one-cell halo below in x and y,
     // two planes in flight: plane kk lives in slot (kk - k0 + 1) & 1
     __shared__ double sref[2][3][TY + 2][TX + 2];
+    // EMF and upwind indicator of each horizontal edge's face stacked along z
+    __shared__ double szc_e[(TY + 1) * TX + TY * (TX + 1)];
+    __shared__ int8_t szc_s[(TY + 1) * TX + TY * (TX + 1)];
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     // positions owned by threads: cells/faces i in [0, ex), j in [0, ey)
     const int ex = nx + (g.bc[0] == VLCT_BC_OUTFLOW), ey = ny + (g.bc[1] == VLCT_BC_OUTFLOW);
@@ -519,24 +576,35 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
     };
     // LDS coordinates of cell (ii, jj): [jj - j0 + 1][ii - i0 + 1]
     // edge q of the plane kk - 1/2 (E_x for q < NEX, else E_y, at edge index
-    // kk) into slot h
-    auto horizontal_edge = [&](int q, int kk, int h) {
+    // kk) into slot h; szc_e / szc_s[q] carry the EMF and upwind indicator of
+    // its face stacked along z from one half plane to the next (first: read
+    // them).  Only the thread working on edge q touches entry q within a plane.
+    auto horizontal_edge = [&](int q, int kk, int h, bool first) {
         const int up = slot(kk), dn = slot(kk - 1);
+        const int qe = q;
         if (q < NEX) {
             const int a = q % TX, c = q / TX, ii = i0 + a, jj = j0 + c;
             // E_x at (ii, jj - 1/2, kk - 1/2): B = y, C = z
-            if (ii < nx && jj <= ny)
-                sex[h][c][a] = edge_emf<0>(g, F, ii, jj, kk, sref[up][0][c + 1][a + 1],
-                                           sref[up][0][c][a + 1], sref[dn][0][c + 1][a + 1],
-                                           sref[dn][0][c][a + 1]);
+            if (ii < nx && jj <= ny) {
+                const double r00 = sref[up][0][c + 1][a + 1], r10 = sref[up][0][c][a + 1];
+                const double r01 = sref[dn][0][c + 1][a + 1], r11 = sref[dn][0][c][a + 1];
+                sex[h][c][a] = first ? edge_emf_zcarry<0, true>(g, F, ii, jj, kk, r00, r10, r01, r11,
+                                                                szc_e[qe], szc_s[qe])
+                                     : edge_emf_zcarry<0, false>(g, F, ii, jj, kk, r00, r10, r01, r11,
+                                                                 szc_e[qe], szc_s[qe]);
+            }
         } else {
             q -= NEX;
             const int a = q % (TX + 1), c = q / (TX + 1), ii = i0 + a, jj = j0 + c;
             // E_y at (ii - 1/2, jj, kk - 1/2): B = z, C = x
-            if (ii <= nx && jj < ny)
-                sey[h][c][a] = edge_emf<1>(g, F, ii, jj, kk, sref[up][1][c + 1][a + 1],
-                                           sref[dn][1][c + 1][a + 1], sref[up][1][c + 1][a],
-                                           sref[dn][1][c + 1][a]);
+            if (ii <= nx && jj < ny) {
+                const double r00 = sref[up][1][c + 1][a + 1], r10 = sref[dn][1][c + 1][a + 1];
+                const double r01 = sref[up][1][c + 1][a], r11 = sref[dn][1][c + 1][a];
+                sey[h][c][a] = first ? edge_emf_zcarry<1, true>(g, F, ii, jj, kk, r00, r10, r01, r11,
+                                                                szc_e[qe], szc_s[qe])
+                                     : edge_emf_zcarry<1, false>(g, F, ii, jj, kk, r00, r10, r01, r11,
+                                                                 szc_e[qe], szc_s[qe]);
+            }
         }
     };
     // two barriers per plane: (1) E_z of plane k and E_x / E_y of plane
@@ -547,13 +615,24 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
     stage_ref(k0 - 1);
     stage_ref(k0);
     __syncthreads();
-    for (int q = threadIdx.x; q < NEX + NEY; q += (TX * TY)) horizontal_edge(q, k0, lo);
+    for (int q = threadIdx.x; q < NEX + NEY; q += (TX * TY)) horizontal_edge(q, k0, lo, true);
     __syncthreads();
     stage_ref(k0 + 1);  // into the slot of plane k0 - 1, no longer read
     __syncthreads();
     bool bad = false;
     double mcfl = 0.0;
     uint32_t stcfl = 0;
+    // the cell's z-face fluxes and (DT) base B_z at its low face k, read at k0
+    // and carried up from the high face of the plane below
+    const bool owner = i < ex && j < ey && i < nx && j < ny;
+    double fzc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double bzc = 0.0;
+    if (owner) {
+        const idx_t fz0 = fidx(g, 2, i, j, k0);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) fzc[q] = F.f[2][q][fz0];
+        if (DT) bzc = base.b[2][face_store(g, 2, i, j, k0)];
+    }
     for (int k = k0; k < k1; ++k) {
         const int sk = slot(k);
         for (int q = threadIdx.x; q < NEZ + NEX + NEY; q += (TX * TY)) {
@@ -565,32 +644,38 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
                                             sref[sk][2][c + 1][a], sref[sk][2][c][a + 1],
                                             sref[sk][2][c][a]);
             } else {
-                horizontal_edge(q - NEZ, k + 1, 1 - lo);
+                horizontal_edge(q - NEZ, k + 1, 1 - lo, false);
             }
         }
         __syncthreads();
         const int hi = 1 - lo;
+        double bzn = 0.0;
         if (i < ex && j < ey) {
             if (i < nx && j < ny) {
                 const idx_t c = cell_store(g, i, j, k);
                 const idx_t fx0 = fidx(g, 0, i, j, k), fx1 = fidx(g, 0, i + 1, j, k);
                 const idx_t fy0 = fidx(g, 1, i, j, k), fy1 = fidx(g, 1, i, j + 1, k);
-                const idx_t fz0 = fidx(g, 2, i, j, k), fz1 = fidx(g, 2, i, j, k + 1);
+                const idx_t fz1 = fidx(g, 2, i, j, k + 1);
+                double fzn[5];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) fzn[q] = F.f[2][q][fz1];
                 const double dxr = F.f[0][0][fx1] - F.f[0][0][fx0];
                 const double dyr = F.f[1][0][fy1] - F.f[1][0][fy0];
-                const double dzr = F.f[2][0][fz1] - F.f[2][0][fz0];
+                const double dzr = fzn[0] - fzc[0];
                 const double dxe = F.f[0][4][fx1] - F.f[0][4][fx0];
                 const double dye = F.f[1][4][fy1] - F.f[1][4][fy0];
-                const double dze = F.f[2][4][fz1] - F.f[2][4][fz0];
+                const double dze = fzn[4] - fzc[4];
                 const double dxmx = F.f[0][1][fx1] - F.f[0][1][fx0];
                 const double dxmy = F.f[0][2][fx1] - F.f[0][2][fx0];
                 const double dxmz = F.f[0][3][fx1] - F.f[0][3][fx0];
                 const double dymy = F.f[1][1][fy1] - F.f[1][1][fy0];
                 const double dymz = F.f[1][2][fy1] - F.f[1][2][fy0];
                 const double dymx = F.f[1][3][fy1] - F.f[1][3][fy0];
-                const double dzmz = F.f[2][1][fz1] - F.f[2][1][fz0];
-                const double dzmx = F.f[2][2][fz1] - F.f[2][2][fz0];
-                const double dzmy = F.f[2][3][fz1] - F.f[2][3][fz0];
+                const double dzmz = fzn[1] - fzc[1];
+                const double dzmx = fzn[2] - fzc[2];
+                const double dzmy = fzn[3] - fzc[3];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) fzc[q] = fzn[q];
                 const double u0 = base.u[0][c] - cx * dxr - cy * dyr - cz * dzr;
                 const double u1 = base.u[1][c] - cx * dxmx - cy * dymx - cz * dzmx;
                 const double u2 = base.u[2][c] - cx * dxmy - cy * dymy - cz * dzmy;
@@ -618,10 +703,11 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
                     const double by1 = base.b[1][face_store(g, 1, i, map_face(j + 1, ny, g.bc[1]), k)]
                                        - cz * (sex[hi][ty + 1][tx] - sex[lo][ty + 1][tx])
                                        + cx * (sez[ty + 1][tx + 1] - sez[ty + 1][tx]);
-                    const double bz0 = base.b[2][face_store(g, 2, i, j, k)]
+                    const double bz0 = bzc
                                        - cx * (sey[lo][ty][tx + 1] - sey[lo][ty][tx])
                                        + cy * (sex[lo][ty + 1][tx] - sex[lo][ty][tx]);
-                    const double bz1 = base.b[2][face_store(g, 2, i, j, map_face(k + 1, nz, g.bc[2]))]
+                    bzn = base.b[2][face_store(g, 2, i, j, map_face(k + 1, nz, g.bc[2]))];
+                    const double bz1 = bzn
                                        - cx * (sey[hi][ty][tx + 1] - sey[hi][ty][tx])
                                        + cy * (sex[hi][ty + 1][tx] - sex[hi][ty][tx]);
                     const double bcc[3] = {0.5 * (bx0 + bx1), 0.5 * (by0 + by1), 0.5 * (bz0 + bz1)};
@@ -645,12 +731,13 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
                 if (FULL) bad |= !isfinite(v);
             }
             if (i < nx && j < ny) {  // face z (i, j, k-1/2)
-                const double b0 = base.b[2][face_store(g, 2, i, j, k)];
+                const double b0 = DT ? bzc : base.b[2][face_store(g, 2, i, j, k)];
                 const double v = b0 - cx * (sey[lo][ty][tx + 1] - sey[lo][ty][tx])
                                  + cy * (sex[lo][ty + 1][tx] - sex[lo][ty][tx]);
                 out.b[2][face_store(g, 2, i, j, k)] = v;
                 if (g.bc[2] == VLCT_BC_PERIODIC && k == 0) out.b[2][face_store(g, 2, i, j, nz)] = v;
                 if (FULL) bad |= !isfinite(v);
+                if (DT) bzc = bzn;
             }
         }
         if (k + 2 <= k1) stage_ref(k + 2);
@@ -1127,7 +1214,7 @@ static int march_segment(const Geom &g, int d)
 }
 
 template <bool FULL, bool DT = false>
-__global__ void __launch_bounds__(kCt) k_ct_update(Geom g, Prims P, Flux F, StateP base,
+__global__ void __launch_bounds__(kCt, 4) k_ct_update(Geom g, Prims P, Flux F, StateP base,
                                                        StateW out, const double *dt_dev,
                                                        uint32_t *status, double *partial)
 {
@@ -1340,7 +1427,7 @@ __global__ void __launch_bounds__(kBlock) kb_march(const Inst *tab, int count, i
 }
 
 template <bool FULL, int V>
-__global__ void __launch_bounds__(kCt) kb_ct(const Inst *tab, int count, idx_t total)
+__global__ void __launch_bounds__(kCt, 4) kb_ct(const Inst *tab, int count, idx_t total)
 {
     const idx_t gb = xcd_block(total);
     if (gb >= total) return;

@@ -503,6 +503,18 @@ __global__ __launch_bounds__(kBlock) void k_ad_march_fused(Geom g, Prims P, Stat
     W7 prev{};
     uint32_t fprev = 0;
     double alow[7];  // cotangent of the low-face state of the cell below the face
+    // the reversal of cell m adds to the cells m - 1, m and m + 1, after which
+    // cell m - 1 has all its terms from this segment: the cells m and m + 1
+    // wait in LDS (cell c in slot c & 1, each thread its own column) and a
+    // cell leaves with one atomic add per component (segments share the two
+    // cells at each end)
+    __shared__ double pend[2][7][kBlock];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        pend[0][k][tid] = 0.0;
+        pend[1][k][tid] = 0.0;
+    }
     for (int a = s0 - 1; a <= s1; ++a) {
         W7 fm, fp;
         plmc<kChar>(win[1], win[2], win[3], bnc[2], g.gamma, fm, fp);
@@ -529,18 +541,19 @@ __global__ __launch_bounds__(kBlock) void k_ad_march_fused(Geom g, Prims P, Stat
                 double abc = 0.0;
                 plmc_rev<kChar>(win[0], win[1], win[2], bnc[1], g.gamma, alow, ahigh, am, a0,
                                 ap, abc);
-                const W7 *outs[3] = {&am, &a0, &ap};
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    int e[3] = {x[0], x[1], x[2]};
-                    e[D] = a - 2 + q;
-                    const idx_t cc = cell_of(g, e);
-                    const W7 &v = *outs[q];
-                    const double av[7] = {v.d, v.u, v.v, v.w, v.p, v.by, v.bz};
-#pragma unroll
-                    for (int k = 0; k < 7; ++k) atomicAdd(&S.lw[lab_slot(D, k)][cc], av[k]);
-                }
+                const double vm[7] = {am.d, am.u, am.v, am.w, am.p, am.by, am.bz};
+                const double v0[7] = {a0.d, a0.u, a0.v, a0.w, a0.p, a0.by, a0.bz};
+                const double vp[7] = {ap.d, ap.u, ap.v, ap.w, ap.p, ap.by, ap.bz};
+                const int so = (a - 2) & 1, sn = (a - 1) & 1;  // slots of cells a - 2 (and a), a - 1
                 int e[3] = {x[0], x[1], x[2]};
+                e[D] = a - 2;
+                const idx_t cm = cell_of(g, e);
+#pragma unroll
+                for (int k = 0; k < 7; ++k) {
+                    atomicAdd(&S.lw[lab_slot(D, k)][cm], pend[so][k][tid] + vm[k]);
+                    pend[so][k][tid] = vp[k];
+                    pend[sn][k][tid] += v0[k];
+                }
                 e[D] = a - 1;
                 atomicAdd(&S.lw[5 + D][cell_of(g, e)], abc);
             }
@@ -562,6 +575,16 @@ __global__ __launch_bounds__(kBlock) void k_ad_march_fused(Geom g, Prims P, Stat
             win[3] = w7_at(P, D, o);
             bnc[3] = P.w[5 + D][o];
         }
+    }
+    // the cells s1 - 1 and s1 (the last reversal was that of cell s1 - 1)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        int e[3] = {x[0], x[1], x[2]};
+        e[D] = s1 - 1 + q;
+        const idx_t cc = cell_of(g, e);
+        const int sl = (s1 - 1 + q) & 1;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) atomicAdd(&S.lw[lab_slot(D, k)][cc], pend[sl][k][tid]);
     }
 }
 
@@ -589,7 +612,9 @@ __global__ __launch_bounds__(kBlock) void k_ad_row_fused(Geom g, Prims P, StateP
     static_assert(RECON == VLCT_RECON_PLMC || RECON == VLCT_RECON_PLMP, "linear reconstructions");
     constexpr bool kChar = RECON == VLCT_RECON_PLMC;
     __shared__ double lds[7][kBlock];
+    __shared__ double lds_p[7][kBlock];
     __shared__ uint32_t lfl[kBlock];
+    __shared__ uint32_t lrev[kBlock];
     const int nx = g.n[0];
     const idx_t per_row = nx + 2;
     const idx_t items = per_row * g.n[1] * g.n[2];
@@ -646,24 +671,53 @@ __global__ __launch_bounds__(kBlock) void k_ad_row_fused(Geom g, Prims P, StateP
 #pragma unroll
     for (int c = 0; c < 7; ++c) lds[c][t] = ahigh_left[c];
     __syncthreads();
-    if (!face || t > kBlock - 2 || x[0] >= nx) return;
-    double ahigh[7];
-#pragma unroll
-    for (int c = 0; c < 7; ++c) ahigh[c] = lds[c][t + 1];
+    const bool rev = face && t <= kBlock - 2 && x[0] < nx;
     W7 am{0, 0, 0, 0, 0, 0, 0}, a0{0, 0, 0, 0, 0, 0, 0}, ap{0, 0, 0, 0, 0, 0, 0};
     double abc = 0.0;
-    plmc_rev<kChar>(w7_at(P, 0, at(-1)), w7_at(P, 0, at(0)), w7_at(P, 0, at(1)), P.w[5][at(0)],
-                    g.gamma, alow, ahigh, am, a0, ap, abc);
-    const W7 *outs[3] = {&am, &a0, &ap};
+    if (rev) {
+        double ahigh[7];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const idx_t cc = cell_of(g, x[0] - 1 + k, x[1], x[2]);
-        const W7 &v = *outs[k];
-        const double av[7] = {v.d, v.u, v.v, v.w, v.p, v.by, v.bz};
-#pragma unroll
-        for (int c = 0; c < 7; ++c) atomicAdd(&S.lw[lab_slot(0, c)][cc], av[c]);
+        for (int c = 0; c < 7; ++c) ahigh[c] = lds[c][t + 1];
+        plmc_rev<kChar>(w7_at(P, 0, at(-1)), w7_at(P, 0, at(0)), w7_at(P, 0, at(1)),
+                        P.w[5][at(0)], g.gamma, alow, ahigh, am, a0, ap, abc);
     }
-    atomicAdd(&S.lw[5][cell_of(g, x)], abc);
+    __syncthreads();
+    // the reversal adds to the cells x - 1, x and x + 1: the neighbours' terms
+    // go through LDS to the item that owns the cell where it reversed too, so
+    // that each cell leaves with one atomic add per component
+    const double vm[7] = {am.d, am.u, am.v, am.w, am.p, am.by, am.bz};
+    const double vp[7] = {ap.d, ap.u, ap.v, ap.w, ap.p, ap.by, ap.bz};
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+        lds[c][t] = vm[c];
+        lds_p[c][t] = vp[c];
+    }
+    lrev[t] = rev ? 1u : 0u;
+    __syncthreads();
+    if (!rev) return;
+    // an item that reversed on the left (right) is the cell x - 1 (x + 1) of this row
+    const bool left_rev = t >= 1 && lrev[t - 1];
+    const bool right_rev = lrev[t + 1] != 0u;
+    const double v0[7] = {a0.d, a0.u, a0.v, a0.w, a0.p, a0.by, a0.bz};
+    const idx_t cc = cell_of(g, x);
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+        double v = v0[c];
+        if (left_rev) v += lds_p[c][t - 1];
+        if (right_rev) v += lds[c][t + 1];
+        atomicAdd(&S.lw[lab_slot(0, c)][cc], v);
+    }
+    if (!left_rev) {
+        const idx_t cl = cell_of(g, x[0] - 1, x[1], x[2]);
+#pragma unroll
+        for (int c = 0; c < 7; ++c) atomicAdd(&S.lw[lab_slot(0, c)][cl], vm[c]);
+    }
+    if (!right_rev) {
+        const idx_t cr = cell_of(g, x[0] + 1, x[1], x[2]);
+#pragma unroll
+        for (int c = 0; c < 7; ++c) atomicAdd(&S.lw[lab_slot(0, c)][cr], vp[c]);
+    }
+    atomicAdd(&S.lw[5][cc], abc);
 }
 
 // reconstruction of each cell along D reversed: cotangents of the stencil
