@@ -768,8 +768,11 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
 }
 
 // ---------------------------------------------------------------------------
-// fused predictor (Steps 2-5 in one kernel): a block owns a TX x TY column
-// tile and marches along z through its planes [k0, k1).  Per new plane m it
+// fused predictor (Steps 2-5 in one kernel): the (column tile, plane) pairs
+// of the grid, tile-major, are dealt out to the blocks in equal runs
+// (Geom::pred_chunk), one wave of resident blocks when the grid is large
+// enough; a block marches along z through each run [k0, k1) of planes of a
+// TX x TY column tile that its share holds.  Per new plane m it
 //   (A) derives the primitives of the tile plus a one-cell ring (Sec. 2.1,
 //       B_cc = face average, floors) and the reference field -(v x B),
 //   (B) solves PCM HLLD on the x- and y-faces of plane m and the z-face
@@ -781,9 +784,10 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
 //   (D) updates the cells and the owned faces of plane m - 1 to t + dt/2
 //       (Step 5).
 // Nothing but U^n is read and nothing but U^{n+1/2} is written: primitives,
-// fluxes and edge fields stay on chip.  The block also evaluates the faces of
-// the planes k0 - 1 and k1 (the edges of its first and last half planes need
-// them).  Arithmetic per quantity is that of k_prims, k_flux and k_ct_update.
+// fluxes and edge fields stay on chip.  For each run the block also
+// evaluates the faces of the planes k0 - 1 and k1 (the edges of its first and
+// last half planes need them).  Arithmetic per quantity is that of k_prims,
+// k_flux and k_ct_update, whatever the runs.
 // ---------------------------------------------------------------------------
 template <int TX, int TY>
 struct PredShape {
@@ -839,282 +843,293 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
 
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const int ex = nx + (g.bc[0] == VLCT_BC_OUTFLOW), ey = ny + (g.bc[1] == VLCT_BC_OUTFLOW);
-    const int tz = g.pred_planes;
-    const int ntx = (ex + TX - 1) / TX, nty = (ey + TY - 1) / TY, ntz = (nz + tz - 1) / tz;
-    if (b >= (idx_t)ntx * nty * ntz) return;
-    const int bx = (int)(b % ntx), by = (int)((b / ntx) % nty), bz = (int)(b / ((idx_t)ntx * nty));
-    const int i0 = bx * TX, j0 = by * TY, k0 = bz * tz, k1 = min(k0 + tz, nz);
+    // the block's share: positions [pos0, pos1) of the sequence (column tile,
+    // plane), tile-major, planes along z; it marches each tile's run of
+    // planes in turn
+    const int ntx = (ex + TX - 1) / TX, nty = (ey + TY - 1) / TY;
+    const int npos = ntx * nty * nz;  // below 2^31 for sides up to kMaxN
+    if (b * (idx_t)g.pred_chunk >= npos) return;
+    const int pos0 = (int)b * g.pred_chunk;
+    const int pos1 = min(pos0 + g.pred_chunk, npos);
     const double dt = 0.5 * dt_dev[0];
     const double cx = dt / g.dl[0], cy = dt / g.dl[1], cz = dt / g.dl[2];
 
-    // this thread's column: (a, c) in the tile with its ring, cell (ii, jj)
+    // this thread's column: (a, c) in the tile with its ring
     const int t = threadIdx.x;
     const bool col = t < NC;
     const int a = t % CX, c = t / CX;
-    const int ii = i0 - 1 + a, jj = j0 - 1 + c;
-    const bool live = col && ii <= nx && jj <= ny;
-    const bool do_x = live && a >= 1, do_y = live && c >= 1;
-    const bool do_z = live && !((a == 0 || a == CX - 1) && (c == 0 || c == CY - 1));
-    // owned positions: cells / faces of the tile proper
     const int tx = a - 1, ty = c - 1;
-    const bool own = live && a >= 1 && a <= TX && c >= 1 && c <= TY && ii < ex && jj < ey;
-    const bool interior = own && ii < nx && jj < ny;
-    const int mi = map_cell(ii, nx, g.bc[0]), mj = map_cell(jj, ny, g.bc[1]);
-    const int fi0 = map_face(ii, nx, g.bc[0]), fi1 = map_face(ii + 1, nx, g.bc[0]);
-    const int fj0 = map_face(jj, ny, g.bc[1]), fj1 = map_face(jj + 1, ny, g.bc[1]);
-
     uint32_t st = 0;
-    W7 wz_prev{};                   // own cell of the previous plane, z sweep frame
-    double hx[5] = {}, hy[5] = {};  // own x-, y-face hydro fluxes of the previous plane
-    double hz_lo[5] = {};           // own z-face hydro flux below the previous plane
+    for (int pos = pos0; pos < pos1;) {
+        const int tile = pos / nz;
+        const int k0 = pos - tile * nz;
+        const int k1 = min(nz, k0 + (pos1 - pos));
+        pos += k1 - k0;
+        const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
+        // cell (ii, jj) of the column
+        const int ii = i0 - 1 + a, jj = j0 - 1 + c;
+        const bool live = col && ii <= nx && jj <= ny;
+        const bool do_x = live && a >= 1, do_y = live && c >= 1;
+        const bool do_z = live && !((a == 0 || a == CX - 1) && (c == 0 || c == CY - 1));
+        // owned positions: cells / faces of the tile proper
+        const bool own = live && a >= 1 && a <= TX && c >= 1 && c <= TY && ii < ex && jj < ey;
+        const bool interior = own && ii < nx && jj < ny;
+        const int mi = map_cell(ii, nx, g.bc[0]), mj = map_cell(jj, ny, g.bc[1]);
+        const int fi0 = map_face(ii, nx, g.bc[0]), fi1 = map_face(ii + 1, nx, g.bc[0]);
+        const int fj0 = map_face(jj, ny, g.bc[1]), fj1 = map_face(jj + 1, ny, g.bc[1]);
 
-    // U^n of this thread's cell in a plane: 5 conserved values and the six faces
-    double pf[11];
-    auto load_plane = [&](int m) {
-        const int mk = map_cell(m, nz, g.bc[2]);
-        const idx_t cc = cell_store(g, mi, mj, mk);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) pf[q] = s.u[q][cc];
-        pf[5] = s.b[0][face_store(g, 0, fi0, mj, mk)];
-        pf[6] = s.b[0][face_store(g, 0, fi1, mj, mk)];
-        pf[7] = s.b[1][face_store(g, 1, mi, fj0, mk)];
-        pf[8] = s.b[1][face_store(g, 1, mi, fj1, mk)];
-        pf[9] = s.b[2][face_store(g, 2, mi, mj, map_face(m, nz, g.bc[2]))];
-        pf[10] = s.b[2][face_store(g, 2, mi, mj, map_face(m + 1, nz, g.bc[2]))];
-    };
+        W7 wz_prev{};                   // own cell of the previous plane, z sweep frame
+        double hx[5] = {}, hy[5] = {};  // own x-, y-face hydro fluxes of the previous plane
+        double hz_lo[5] = {};           // own z-face hydro flux below the previous plane
 
-    for (int m = k0 - 1; m <= k1; ++m) {
-        const int sm = m & 1, sp = sm ^ 1;
-        // (A) primitives and reference field of plane m; the cell's low faces
-        // are also the normal fields of the faces this thread solves in (B)
-        double bx0 = 0.0, by0 = 0.0, bz0 = 0.0;
-        if (live) {
-            load_plane(m);
-            bx0 = pf[5];
-            const double bx1 = pf[6];
-            by0 = pf[7];
-            const double by1 = pf[8];
-            bz0 = pf[9];
-            const double bz1 = pf[10];
-            const double bcx = 0.5 * (bx0 + bx1);
-            const double bcy = 0.5 * (by0 + by1);
-            const double bcz = 0.5 * (bz0 + bz1);
-            double d = pf[0];
-            if (!(d >= kFloorRho)) { d = kFloorRho; st |= kStatusDensityFloor; }
-            const double id = 1.0 / d;
-            const double vx = pf[1] * id, vy = pf[2] * id, vz = pf[3] * id;
-            const double ke = 0.5 * d * (vx * vx + vy * vy + vz * vz);
-            const double me = 0.5 * (bcx * bcx + bcy * bcy + bcz * bcz);
-            double pr = (g.gamma - 1.0) * (pf[4] - ke - me);
-            if (!(pr >= kFloorP)) { pr = kFloorP; st |= kStatusPressureFloor; }
-            s_wh[0][t] = d;
-            s_wh[1][t] = vx;
-            s_wh[2][t] = vy;
-            s_wh[3][t] = vz;
-            s_wh[4][t] = pr;
-            s_wh[5][t] = bcx;
-            s_wh[6][t] = bcy;
-            s_wh[7][t] = bcz;
-            s_rx[sm][t] = -(vy * bcz - vz * bcy);
-            s_ry[sm][t] = -(vz * bcx - vx * bcz);
-            s_rz[t] = -(vx * bcy - vy * bcx);
-        }
-        __syncthreads();
-        // (B) PCM HLLD on the x-, y-faces of plane m and the z-face m - 1/2
-        double hxn[5] = {}, hyn[5] = {}, hzn[5] = {};
-        W7 wz{};
-        if (live) {
-            const W7 wxr{s_wh[0][t], s_wh[1][t], s_wh[2][t], s_wh[3][t], s_wh[4][t], s_wh[6][t], s_wh[7][t]};
-            wz = W7{s_wh[0][t], s_wh[3][t], s_wh[1][t], s_wh[2][t], s_wh[4][t], s_wh[5][t], s_wh[6][t]};
-            double f[7], upw;
-            if (do_x) {
-                const int l = t - 1;
-                const W7 wl{s_wh[0][l], s_wh[1][l], s_wh[2][l], s_wh[3][l], s_wh[4][l], s_wh[6][l], s_wh[7][l]};
-                hlld(wl, wxr, bx0, g.gamma, g.gm1i, f, upw);
+        // U^n of this thread's cell in a plane: 5 conserved values and the six faces
+        double pf[11];
+        auto load_plane = [&](int m) {
+            const int mk = map_cell(m, nz, g.bc[2]);
+            const idx_t cc = cell_store(g, mi, mj, mk);
 #pragma unroll
-                for (int q = 0; q < 5; ++q) hxn[q] = f[q];
-                s_em[sm][0][t] = -f[5];
-                s_em[sm][1][t] = f[6];
-                s_sg[sm][0][t] = (int8_t)upw;
+            for (int q = 0; q < 5; ++q) pf[q] = s.u[q][cc];
+            pf[5] = s.b[0][face_store(g, 0, fi0, mj, mk)];
+            pf[6] = s.b[0][face_store(g, 0, fi1, mj, mk)];
+            pf[7] = s.b[1][face_store(g, 1, mi, fj0, mk)];
+            pf[8] = s.b[1][face_store(g, 1, mi, fj1, mk)];
+            pf[9] = s.b[2][face_store(g, 2, mi, mj, map_face(m, nz, g.bc[2]))];
+            pf[10] = s.b[2][face_store(g, 2, mi, mj, map_face(m + 1, nz, g.bc[2]))];
+        };
+
+        for (int m = k0 - 1; m <= k1; ++m) {
+            const int sm = m & 1, sp = sm ^ 1;
+            // (A) primitives and reference field of plane m; the cell's low faces
+            // are also the normal fields of the faces this thread solves in (B)
+            double bx0 = 0.0, by0 = 0.0, bz0 = 0.0;
+            if (live) {
+                load_plane(m);
+                bx0 = pf[5];
+                const double bx1 = pf[6];
+                by0 = pf[7];
+                const double by1 = pf[8];
+                bz0 = pf[9];
+                const double bz1 = pf[10];
+                const double bcx = 0.5 * (bx0 + bx1);
+                const double bcy = 0.5 * (by0 + by1);
+                const double bcz = 0.5 * (bz0 + bz1);
+                double d = pf[0];
+                if (!(d >= kFloorRho)) { d = kFloorRho; st |= kStatusDensityFloor; }
+                const double id = 1.0 / d;
+                const double vx = pf[1] * id, vy = pf[2] * id, vz = pf[3] * id;
+                const double ke = 0.5 * d * (vx * vx + vy * vy + vz * vz);
+                const double me = 0.5 * (bcx * bcx + bcy * bcy + bcz * bcz);
+                double pr = (g.gamma - 1.0) * (pf[4] - ke - me);
+                if (!(pr >= kFloorP)) { pr = kFloorP; st |= kStatusPressureFloor; }
+                s_wh[0][t] = d;
+                s_wh[1][t] = vx;
+                s_wh[2][t] = vy;
+                s_wh[3][t] = vz;
+                s_wh[4][t] = pr;
+                s_wh[5][t] = bcx;
+                s_wh[6][t] = bcy;
+                s_wh[7][t] = bcz;
+                s_rx[sm][t] = -(vy * bcz - vz * bcy);
+                s_ry[sm][t] = -(vz * bcx - vx * bcz);
+                s_rz[t] = -(vx * bcy - vy * bcx);
             }
-            if (do_y) {
-                const int l = t - CX;
-                const W7 wl{s_wh[0][l], s_wh[2][l], s_wh[3][l], s_wh[1][l], s_wh[4][l], s_wh[7][l], s_wh[5][l]};
-                const W7 wr{s_wh[0][t], s_wh[2][t], s_wh[3][t], s_wh[1][t], s_wh[4][t], s_wh[7][t], s_wh[5][t]};
-                hlld(wl, wr, by0, g.gamma, g.gm1i, f, upw);
-#pragma unroll
-                for (int q = 0; q < 5; ++q) hyn[q] = f[q];
-                s_em[sm][2][t] = -f[5];
-                s_em[sm][3][t] = f[6];
-                s_sg[sm][1][t] = (int8_t)upw;
-            }
-            if (do_z && m >= k0) {
-                hlld(wz_prev, wz, bz0, g.gamma, g.gm1i, f, upw);
-#pragma unroll
-                for (int q = 0; q < 5; ++q) hzn[q] = f[q];
-                s_zem[0][t] = -f[5];
-                s_zem[1][t] = f[6];
-                s_zsg[t] = (int8_t)upw;
-            }
-        }
-        __syncthreads();
-        // (C) E_z of plane m, E_x / E_y of the half plane m - 1/2; the hydro
-        // fluxes of plane m - 1 go to LDS for the neighbours' updates.  The
-        // U^n values the update of plane m - 1 in (D) starts from are loaded
-        // first, so that their latency hides behind the edge computations.
-        const bool upd = m - 1 >= k0 && m - 1 < k1;
-        double u0[5] = {}, bxb = 0.0, byb = 0.0, bzb = 0.0, bxh = 0.0, byh = 0.0, bzh = 0.0;
-        if (upd && own) {
-            const int k = m - 1;
-            if (interior) {
-                const idx_t cc = cell_store(g, ii, jj, k);
-#pragma unroll
-                for (int q = 0; q < 5; ++q) u0[q] = s.u[q][cc];
-                bzb = s.b[2][face_store(g, 2, ii, jj, k)];
-                if (P.w[0]) {
-                    bxh = s.b[0][face_store(g, 0, map_face(ii + 1, nx, g.bc[0]), jj, k)];
-                    byh = s.b[1][face_store(g, 1, ii, map_face(jj + 1, ny, g.bc[1]), k)];
-                    bzh = s.b[2][face_store(g, 2, ii, jj, map_face(k + 1, nz, g.bc[2]))];
+            __syncthreads();
+            // (B) PCM HLLD on the x-, y-faces of plane m and the z-face m - 1/2
+            double hxn[5] = {}, hyn[5] = {}, hzn[5] = {};
+            W7 wz{};
+            if (live) {
+                const W7 wxr{s_wh[0][t], s_wh[1][t], s_wh[2][t], s_wh[3][t], s_wh[4][t], s_wh[6][t], s_wh[7][t]};
+                wz = W7{s_wh[0][t], s_wh[3][t], s_wh[1][t], s_wh[2][t], s_wh[4][t], s_wh[5][t], s_wh[6][t]};
+                double f[7], upw;
+                if (do_x) {
+                    const int l = t - 1;
+                    const W7 wl{s_wh[0][l], s_wh[1][l], s_wh[2][l], s_wh[3][l], s_wh[4][l], s_wh[6][l], s_wh[7][l]};
+                    hlld(wl, wxr, bx0, g.gamma, g.gm1i, f, upw);
+    #pragma unroll
+                    for (int q = 0; q < 5; ++q) hxn[q] = f[q];
+                    s_em[sm][0][t] = -f[5];
+                    s_em[sm][1][t] = f[6];
+                    s_sg[sm][0][t] = (int8_t)upw;
+                }
+                if (do_y) {
+                    const int l = t - CX;
+                    const W7 wl{s_wh[0][l], s_wh[2][l], s_wh[3][l], s_wh[1][l], s_wh[4][l], s_wh[7][l], s_wh[5][l]};
+                    const W7 wr{s_wh[0][t], s_wh[2][t], s_wh[3][t], s_wh[1][t], s_wh[4][t], s_wh[7][t], s_wh[5][t]};
+                    hlld(wl, wr, by0, g.gamma, g.gm1i, f, upw);
+    #pragma unroll
+                    for (int q = 0; q < 5; ++q) hyn[q] = f[q];
+                    s_em[sm][2][t] = -f[5];
+                    s_em[sm][3][t] = f[6];
+                    s_sg[sm][1][t] = (int8_t)upw;
+                }
+                if (do_z && m >= k0) {
+                    hlld(wz_prev, wz, bz0, g.gamma, g.gm1i, f, upw);
+    #pragma unroll
+                    for (int q = 0; q < 5; ++q) hzn[q] = f[q];
+                    s_zem[0][t] = -f[5];
+                    s_zem[1][t] = f[6];
+                    s_zsg[t] = (int8_t)upw;
                 }
             }
-            if (jj < ny) bxb = s.b[0][face_store(g, 0, ii, jj, k)];
-            if (ii < nx) byb = s.b[1][face_store(g, 1, ii, jj, k)];
-        }
-        if (m >= k0) {
-            const int nez = m < k1 ? NEZ : 0;
-            for (int q = threadIdx.x; q < nez + NEX + NEY; q += S::NT) {
-                if (q < nez) {
-                    const int ea = q % (TX + 1), ec = q / (TX + 1), ie = i0 + ea, je = j0 + ec;
-                    // E_z at (ie - 1/2, je - 1/2, m): B = x-faces, C = y-faces
-                    if (ie <= nx && je <= ny) {
-                        const int o = (ec + 1) * CX + ea + 1;  // column (ie, je)
-                        s_ez[sm][ec][ea] = edge_value(
-                            s_em[sm][0][o], s_em[sm][0][o - CX], s_em[sm][3][o], s_em[sm][3][o - 1],
-                            s_sg[sm][0][o], s_sg[sm][0][o - CX], s_sg[sm][1][o], s_sg[sm][1][o - 1],
-                            s_rz[o], s_rz[o - 1], s_rz[o - CX], s_rz[o - CX - 1]);
+            __syncthreads();
+            // (C) E_z of plane m, E_x / E_y of the half plane m - 1/2; the hydro
+            // fluxes of plane m - 1 go to LDS for the neighbours' updates.  The
+            // U^n values the update of plane m - 1 in (D) starts from are loaded
+            // first, so that their latency hides behind the edge computations.
+            const bool upd = m - 1 >= k0 && m - 1 < k1;
+            double u0[5] = {}, bxb = 0.0, byb = 0.0, bzb = 0.0, bxh = 0.0, byh = 0.0, bzh = 0.0;
+            if (upd && own) {
+                const int k = m - 1;
+                if (interior) {
+                    const idx_t cc = cell_store(g, ii, jj, k);
+    #pragma unroll
+                    for (int q = 0; q < 5; ++q) u0[q] = s.u[q][cc];
+                    bzb = s.b[2][face_store(g, 2, ii, jj, k)];
+                    if (P.w[0]) {
+                        bxh = s.b[0][face_store(g, 0, map_face(ii + 1, nx, g.bc[0]), jj, k)];
+                        byh = s.b[1][face_store(g, 1, ii, map_face(jj + 1, ny, g.bc[1]), k)];
+                        bzh = s.b[2][face_store(g, 2, ii, jj, map_face(k + 1, nz, g.bc[2]))];
                     }
-                } else if (q < nez + NEX) {
-                    const int r = q - nez;
-                    const int ea = r % TX, ec = r / TX, ie = i0 + ea, je = j0 + ec;
-                    // E_x at (ie, je - 1/2, m - 1/2): B = y-faces (planes m, m - 1), C = z-faces
-                    if (ie < nx && je <= ny) {
-                        const int o = (ec + 1) * CX + ea + 1;
-                        s_ex[sm][ec][ea] = edge_value(
-                            s_em[sm][2][o], s_em[sp][2][o], s_zem[1][o], s_zem[1][o - CX],
-                            s_sg[sm][1][o], s_sg[sp][1][o], s_zsg[o], s_zsg[o - CX],
-                            s_rx[sm][o], s_rx[sm][o - CX], s_rx[sp][o], s_rx[sp][o - CX]);
-                    }
-                } else {
-                    const int r = q - nez - NEX;
-                    const int ea = r % (TX + 1), ec = r / (TX + 1), ie = i0 + ea, je = j0 + ec;
-                    // E_y at (ie - 1/2, je, m - 1/2): B = z-faces, C = x-faces (planes m, m - 1)
-                    if (ie <= nx && je < ny) {
-                        const int o = (ec + 1) * CX + ea + 1;
-                        s_ey[sm][ec][ea] = edge_value(
-                            s_zem[0][o], s_zem[0][o - 1], s_em[sm][1][o], s_em[sp][1][o],
-                            s_zsg[o], s_zsg[o - 1], s_sg[sm][0][o], s_sg[sp][0][o],
-                            s_ry[sm][o], s_ry[sp][o], s_ry[sm][o - 1], s_ry[sp][o - 1]);
+                }
+                if (jj < ny) bxb = s.b[0][face_store(g, 0, ii, jj, k)];
+                if (ii < nx) byb = s.b[1][face_store(g, 1, ii, jj, k)];
+            }
+            if (m >= k0) {
+                const int nez = m < k1 ? NEZ : 0;
+                for (int q = threadIdx.x; q < nez + NEX + NEY; q += S::NT) {
+                    if (q < nez) {
+                        const int ea = q % (TX + 1), ec = q / (TX + 1), ie = i0 + ea, je = j0 + ec;
+                        // E_z at (ie - 1/2, je - 1/2, m): B = x-faces, C = y-faces
+                        if (ie <= nx && je <= ny) {
+                            const int o = (ec + 1) * CX + ea + 1;  // column (ie, je)
+                            s_ez[sm][ec][ea] = edge_value(
+                                s_em[sm][0][o], s_em[sm][0][o - CX], s_em[sm][3][o], s_em[sm][3][o - 1],
+                                s_sg[sm][0][o], s_sg[sm][0][o - CX], s_sg[sm][1][o], s_sg[sm][1][o - 1],
+                                s_rz[o], s_rz[o - 1], s_rz[o - CX], s_rz[o - CX - 1]);
+                        }
+                    } else if (q < nez + NEX) {
+                        const int r = q - nez;
+                        const int ea = r % TX, ec = r / TX, ie = i0 + ea, je = j0 + ec;
+                        // E_x at (ie, je - 1/2, m - 1/2): B = y-faces (planes m, m - 1), C = z-faces
+                        if (ie < nx && je <= ny) {
+                            const int o = (ec + 1) * CX + ea + 1;
+                            s_ex[sm][ec][ea] = edge_value(
+                                s_em[sm][2][o], s_em[sp][2][o], s_zem[1][o], s_zem[1][o - CX],
+                                s_sg[sm][1][o], s_sg[sp][1][o], s_zsg[o], s_zsg[o - CX],
+                                s_rx[sm][o], s_rx[sm][o - CX], s_rx[sp][o], s_rx[sp][o - CX]);
+                        }
+                    } else {
+                        const int r = q - nez - NEX;
+                        const int ea = r % (TX + 1), ec = r / (TX + 1), ie = i0 + ea, je = j0 + ec;
+                        // E_y at (ie - 1/2, je, m - 1/2): B = z-faces, C = x-faces (planes m, m - 1)
+                        if (ie <= nx && je < ny) {
+                            const int o = (ec + 1) * CX + ea + 1;
+                            s_ey[sm][ec][ea] = edge_value(
+                                s_zem[0][o], s_zem[0][o - 1], s_em[sm][1][o], s_em[sp][1][o],
+                                s_zsg[o], s_zsg[o - 1], s_sg[sm][0][o], s_sg[sp][0][o],
+                                s_ry[sm][o], s_ry[sp][o], s_ry[sm][o - 1], s_ry[sp][o - 1]);
+                        }
                     }
                 }
             }
-        }
-        if (upd && live) {
-#pragma unroll
+            if (upd && live) {
+    #pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    s_wh[q][t] = hx[q];
+                    s_wh[5 + q][t] = hy[q];
+                }
+            }
+            // the tape: upwind sides of the interior cell's low faces in plane m
+            if (side0 && interior && m >= k0 && m < k1) {
+                const idx_t cc = cell_store(g, ii, jj, m);
+                side0[cc] = side_code(s_sg[sm][0][t]);
+                side1[cc] = side_code(s_sg[sm][1][t]);
+                side2[cc] = side_code(s_zsg[t]);
+            }
+            __syncthreads();
+            // (D) half-step update of plane k = m - 1 (Step 5); an interior cell
+            // also derives its half-step primitives (for the corrector), with its
+            // high faces recomputed from the same edge fields and in the same
+            // arithmetic as the threads or blocks that own them
+            if (upd && own) {
+                const int k = m - 1;
+                const int lo = sp, hi = sm;  // half planes k - 1/2 and k + 1/2
+                const int ke = k & 1;        // E_z slot of plane k
+                double u[5] = {}, bxl = 0.0, byl = 0.0, bzl = 0.0;
+                if (interior) {
+                    const idx_t cc = cell_store(g, ii, jj, k);
+                    const double dxr = s_wh[0][t + 1] - hx[0];
+                    const double dyr = s_wh[5][t + CX] - hy[0];
+                    const double dzr = hzn[0] - hz_lo[0];
+                    const double dxe = s_wh[4][t + 1] - hx[4];
+                    const double dye = s_wh[9][t + CX] - hy[4];
+                    const double dze = hzn[4] - hz_lo[4];
+                    const double dxmx = s_wh[1][t + 1] - hx[1];
+                    const double dxmy = s_wh[2][t + 1] - hx[2];
+                    const double dxmz = s_wh[3][t + 1] - hx[3];
+                    const double dymy = s_wh[6][t + CX] - hy[1];
+                    const double dymz = s_wh[7][t + CX] - hy[2];
+                    const double dymx = s_wh[8][t + CX] - hy[3];
+                    const double dzmz = hzn[1] - hz_lo[1];
+                    const double dzmx = hzn[2] - hz_lo[2];
+                    const double dzmy = hzn[3] - hz_lo[3];
+                    u[0] = u0[0] - cx * dxr - cy * dyr - cz * dzr;
+                    u[1] = u0[1] - cx * dxmx - cy * dymx - cz * dzmx;
+                    u[2] = u0[2] - cx * dxmy - cy * dymy - cz * dzmy;
+                    u[3] = u0[3] - cx * dxmz - cy * dymz - cz * dzmz;
+                    u[4] = u0[4] - cx * dxe - cy * dye - cz * dze;
+    #pragma unroll
+                    for (int q = 0; q < 5; ++q) out.u[q][cc] = u[q];
+                }
+                if (jj < ny) {  // face x (ii - 1/2, jj, k)
+                    const double v = bxb - cy * (s_ez[ke][ty + 1][tx] - s_ez[ke][ty][tx])
+                                     + cz * (s_ey[hi][ty][tx] - s_ey[lo][ty][tx]);
+                    out.b[0][face_store(g, 0, ii, jj, k)] = v;
+                    if (g.bc[0] == VLCT_BC_PERIODIC && ii == 0) out.b[0][face_store(g, 0, nx, jj, k)] = v;
+                    bxl = v;
+                }
+                if (ii < nx) {  // face y (ii, jj - 1/2, k)
+                    const double v = byb - cz * (s_ex[hi][ty][tx] - s_ex[lo][ty][tx])
+                                     + cx * (s_ez[ke][ty][tx + 1] - s_ez[ke][ty][tx]);
+                    out.b[1][face_store(g, 1, ii, jj, k)] = v;
+                    if (g.bc[1] == VLCT_BC_PERIODIC && jj == 0) out.b[1][face_store(g, 1, ii, ny, k)] = v;
+                    byl = v;
+                }
+                if (interior) {  // face z (ii, jj, k - 1/2)
+                    const double v = bzb - cx * (s_ey[lo][ty][tx + 1] - s_ey[lo][ty][tx])
+                                     + cy * (s_ex[lo][ty + 1][tx] - s_ex[lo][ty][tx]);
+                    out.b[2][face_store(g, 2, ii, jj, k)] = v;
+                    if (g.bc[2] == VLCT_BC_PERIODIC && k == 0) out.b[2][face_store(g, 2, ii, jj, nz)] = v;
+                    bzl = v;
+                }
+                if (interior && P.w[0]) {
+                    // high faces (a periodic one through the face map, as its owner computes it)
+                    const double bxu = bxh - cy * (s_ez[ke][ty + 1][tx + 1] - s_ez[ke][ty][tx + 1])
+                                       + cz * (s_ey[hi][ty][tx + 1] - s_ey[lo][ty][tx + 1]);
+                    const double byu = byh - cz * (s_ex[hi][ty + 1][tx] - s_ex[lo][ty + 1][tx])
+                                       + cx * (s_ez[ke][ty + 1][tx + 1] - s_ez[ke][ty + 1][tx]);
+                    const double bzu = bzh - cx * (s_ey[hi][ty][tx + 1] - s_ey[hi][ty][tx])
+                                       + cy * (s_ex[hi][ty + 1][tx] - s_ex[hi][ty][tx]);
+                    st |= prims_store(g, P, pidx(g, ii, jj, k), u, 0.5 * (bxl + bxu), 0.5 * (byl + byu),
+                                      0.5 * (bzl + bzu));
+                }
+            }
+            // the top z faces of an outflow axis, from the edges of the half plane nz - 1/2
+            if (m == k1 && k1 == nz && g.bc[2] == VLCT_BC_OUTFLOW && interior) {
+                const double b0 = s.b[2][face_store(g, 2, ii, jj, nz)];
+                const double v = b0 - cx * (s_ey[sm][ty][tx + 1] - s_ey[sm][ty][tx])
+                                 + cy * (s_ex[sm][ty + 1][tx] - s_ex[sm][ty][tx]);
+                out.b[2][face_store(g, 2, ii, jj, nz)] = v;
+            }
+    #pragma unroll
             for (int q = 0; q < 5; ++q) {
-                s_wh[q][t] = hx[q];
-                s_wh[5 + q][t] = hy[q];
+                hx[q] = hxn[q];
+                hy[q] = hyn[q];
+                hz_lo[q] = hzn[q];
             }
+            wz_prev = wz;
+            __syncthreads();
         }
-        // the tape: upwind sides of the interior cell's low faces in plane m
-        if (side0 && interior && m >= k0 && m < k1) {
-            const idx_t cc = cell_store(g, ii, jj, m);
-            side0[cc] = side_code(s_sg[sm][0][t]);
-            side1[cc] = side_code(s_sg[sm][1][t]);
-            side2[cc] = side_code(s_zsg[t]);
-        }
-        __syncthreads();
-        // (D) half-step update of plane k = m - 1 (Step 5); an interior cell
-        // also derives its half-step primitives (for the corrector), with its
-        // high faces recomputed from the same edge fields and in the same
-        // arithmetic as the threads or blocks that own them
-        if (upd && own) {
-            const int k = m - 1;
-            const int lo = sp, hi = sm;  // half planes k - 1/2 and k + 1/2
-            const int ke = k & 1;        // E_z slot of plane k
-            double u[5] = {}, bxl = 0.0, byl = 0.0, bzl = 0.0;
-            if (interior) {
-                const idx_t cc = cell_store(g, ii, jj, k);
-                const double dxr = s_wh[0][t + 1] - hx[0];
-                const double dyr = s_wh[5][t + CX] - hy[0];
-                const double dzr = hzn[0] - hz_lo[0];
-                const double dxe = s_wh[4][t + 1] - hx[4];
-                const double dye = s_wh[9][t + CX] - hy[4];
-                const double dze = hzn[4] - hz_lo[4];
-                const double dxmx = s_wh[1][t + 1] - hx[1];
-                const double dxmy = s_wh[2][t + 1] - hx[2];
-                const double dxmz = s_wh[3][t + 1] - hx[3];
-                const double dymy = s_wh[6][t + CX] - hy[1];
-                const double dymz = s_wh[7][t + CX] - hy[2];
-                const double dymx = s_wh[8][t + CX] - hy[3];
-                const double dzmz = hzn[1] - hz_lo[1];
-                const double dzmx = hzn[2] - hz_lo[2];
-                const double dzmy = hzn[3] - hz_lo[3];
-                u[0] = u0[0] - cx * dxr - cy * dyr - cz * dzr;
-                u[1] = u0[1] - cx * dxmx - cy * dymx - cz * dzmx;
-                u[2] = u0[2] - cx * dxmy - cy * dymy - cz * dzmy;
-                u[3] = u0[3] - cx * dxmz - cy * dymz - cz * dzmz;
-                u[4] = u0[4] - cx * dxe - cy * dye - cz * dze;
-#pragma unroll
-                for (int q = 0; q < 5; ++q) out.u[q][cc] = u[q];
-            }
-            if (jj < ny) {  // face x (ii - 1/2, jj, k)
-                const double v = bxb - cy * (s_ez[ke][ty + 1][tx] - s_ez[ke][ty][tx])
-                                 + cz * (s_ey[hi][ty][tx] - s_ey[lo][ty][tx]);
-                out.b[0][face_store(g, 0, ii, jj, k)] = v;
-                if (g.bc[0] == VLCT_BC_PERIODIC && ii == 0) out.b[0][face_store(g, 0, nx, jj, k)] = v;
-                bxl = v;
-            }
-            if (ii < nx) {  // face y (ii, jj - 1/2, k)
-                const double v = byb - cz * (s_ex[hi][ty][tx] - s_ex[lo][ty][tx])
-                                 + cx * (s_ez[ke][ty][tx + 1] - s_ez[ke][ty][tx]);
-                out.b[1][face_store(g, 1, ii, jj, k)] = v;
-                if (g.bc[1] == VLCT_BC_PERIODIC && jj == 0) out.b[1][face_store(g, 1, ii, ny, k)] = v;
-                byl = v;
-            }
-            if (interior) {  // face z (ii, jj, k - 1/2)
-                const double v = bzb - cx * (s_ey[lo][ty][tx + 1] - s_ey[lo][ty][tx])
-                                 + cy * (s_ex[lo][ty + 1][tx] - s_ex[lo][ty][tx]);
-                out.b[2][face_store(g, 2, ii, jj, k)] = v;
-                if (g.bc[2] == VLCT_BC_PERIODIC && k == 0) out.b[2][face_store(g, 2, ii, jj, nz)] = v;
-                bzl = v;
-            }
-            if (interior && P.w[0]) {
-                // high faces (a periodic one through the face map, as its owner computes it)
-                const double bxu = bxh - cy * (s_ez[ke][ty + 1][tx + 1] - s_ez[ke][ty][tx + 1])
-                                   + cz * (s_ey[hi][ty][tx + 1] - s_ey[lo][ty][tx + 1]);
-                const double byu = byh - cz * (s_ex[hi][ty + 1][tx] - s_ex[lo][ty + 1][tx])
-                                   + cx * (s_ez[ke][ty + 1][tx + 1] - s_ez[ke][ty + 1][tx]);
-                const double bzu = bzh - cx * (s_ey[hi][ty][tx + 1] - s_ey[hi][ty][tx])
-                                   + cy * (s_ex[hi][ty + 1][tx] - s_ex[hi][ty][tx]);
-                st |= prims_store(g, P, pidx(g, ii, jj, k), u, 0.5 * (bxl + bxu), 0.5 * (byl + byu),
-                                  0.5 * (bzl + bzu));
-            }
-        }
-        // the top z faces of an outflow axis, from the edges of the half plane nz - 1/2
-        if (m == k1 && k1 == nz && g.bc[2] == VLCT_BC_OUTFLOW && interior) {
-            const double b0 = s.b[2][face_store(g, 2, ii, jj, nz)];
-            const double v = b0 - cx * (s_ey[sm][ty][tx + 1] - s_ey[sm][ty][tx])
-                             + cy * (s_ex[sm][ty + 1][tx] - s_ex[sm][ty][tx]);
-            out.b[2][face_store(g, 2, ii, jj, nz)] = v;
-        }
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            hx[q] = hxn[q];
-            hy[q] = hyn[q];
-            hz_lo[q] = hzn[q];
-        }
-        wz_prev = wz;
-        __syncthreads();
     }
     if (st && status) atomicOr(status, st);
 }
@@ -1222,18 +1237,18 @@ __global__ void __launch_bounds__(kCt, 4) k_ct_update(Geom g, Prims P, Flux F, S
                                 partial);
 }
 
-constexpr int kPredTx = 32, kPredTy = 13;  // fused predictor column tile: 34 x 15 columns with the ring, 510 threads of 512
 constexpr int kPredThreads = PredShape<kPredTx, kPredTy>::NT;
+static_assert(kPredThreads * kPredBlocksPerCU <= 1024,
+              "the resident predictor blocks of a CU hold at most two waves per SIMD");
 
+// blocks of the fused predictor: Geom::pred_chunk (tile, plane) positions each
 __host__ __device__ __forceinline__ idx_t nblk_pred(const Geom &g)
 {
-    const int ntx = (g.n[0] + (g.bc[0] == VLCT_BC_OUTFLOW) + kPredTx - 1) / kPredTx;
-    const int nty = (g.n[1] + (g.bc[1] == VLCT_BC_OUTFLOW) + kPredTy - 1) / kPredTy;
-    const int ntz = (g.n[2] + g.pred_planes - 1) / g.pred_planes;
-    return (idx_t)ntx * nty * ntz;
+    const idx_t npos = pred_tiles(g) * g.n[2];
+    return (npos + g.pred_chunk - 1) / g.pred_chunk;
 }
 
-__global__ void __launch_bounds__(kPredThreads) k_pred(Geom g, StateP s, StateW out, Prims P,
+__global__ void __launch_bounds__(kPredThreads, kPredWavesPerSimd) k_pred(Geom g, StateP s, StateW out, Prims P,
                                                         const double *dt_dev, uint32_t *status,
                                                         uint8_t *side0, uint8_t *side1,
                                                         uint8_t *side2)
@@ -1336,7 +1351,7 @@ __device__ __forceinline__ StateP const_view(const StateW &w)
 }
 
 // the fused predictor of every instance: U^n -> U^{n+1/2}
-__global__ void __launch_bounds__(kPredThreads) kb_pred(const Inst *tab, int count, idx_t total)
+__global__ void __launch_bounds__(kPredThreads, kPredWavesPerSimd) kb_pred(const Inst *tab, int count, idx_t total)
 {
     const idx_t gb = xcd_block(total);
     if (gb >= total) return;

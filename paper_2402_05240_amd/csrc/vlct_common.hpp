@@ -41,7 +41,7 @@ struct Geom {
     double gamma, gm1i, cfl;
     int p[3];  // padded primitive dims n + 2G
     int ct_planes;    // z planes a CT block marches through
-    int pred_planes;  // z planes a fused predictor block marches through
+    int pred_chunk;   // (column tile, plane) positions of one fused predictor block
 };
 
 __host__ __device__ __forceinline__ int map_cell(int i, int n, int bc)
@@ -146,8 +146,8 @@ inline bool grid_ok(const vlct_grid *g)
 
 // Tile override for tests and tuning: the environment variable VLCT_TILES,
 // read at every call, holds comma-separated key=value pairs (ct=4|8|16 CT
-// planes per block, march=8|16 faces per corrector march segment, pred=4..64
-// fused predictor planes per block, admarch=8|16 cells per adjoint march
+// planes per block, march=8|16 faces per corrector march segment, pred=N
+// (column tile, plane) positions per fused predictor block, admarch=8|16 cells per adjoint march
 // segment) that replace the size-dependent choices.  Every choice computes the
 // same per-cell and per-face arithmetic; the forward results are bitwise the
 // same, the adjoint's equal to the summation order of its accumulations.
@@ -164,6 +164,21 @@ inline int tile_override(const char *key)
         p = c + 1;
     }
     return 0;
+}
+
+// fused predictor column tile: kPredTx x kPredTy cells, its threads also
+// covering a one-cell ring (34 x 15 columns, 510 threads of 512); one block
+// per CU (123 KB of LDS, 256 VGPRs: two waves per SIMD)
+constexpr int kPredTx = 32, kPredTy = 13;
+constexpr int kPredBlocksPerCU = 1;
+constexpr int kPredWavesPerSimd = 2;
+constexpr int kNumCUs = 256;  // gfx950 (MI355X)
+
+__host__ __device__ __forceinline__ long long pred_tiles(const Geom &g)
+{
+    const int ntx = (g.n[0] + (g.bc[0] == VLCT_BC_OUTFLOW) + kPredTx - 1) / kPredTx;
+    const int nty = (g.n[1] + (g.bc[1] == VLCT_BC_OUTFLOW) + kPredTy - 1) / kPredTy;
+    return (long long)ntx * nty;
 }
 
 inline Geom make_geom(const vlct_grid *vg)
@@ -191,23 +206,18 @@ inline Geom make_geom(const vlct_grid *vg)
     g.ct_planes = 16;
     if (cols * ((g.n[2] + 15) / 16) < 1024) g.ct_planes = 8;
     if (g.ct_planes == 8 && cols * ((g.n[2] + 7) / 8) < 256) g.ct_planes = 4;
-    // fused predictor: 32 x 13 column tiles, one block per CU (LDS-bound); a
-    // block marching p planes also solves the faces of two extra planes, so
-    // take the p that minimises (blocks per CU, rounded up) x (p + 2)
-    const long long pcols = (long long)((g.n[0] + (g.bc[0] == VLCT_BC_OUTFLOW) + 31) / 32) *
-                            ((g.n[1] + (g.bc[1] == VLCT_BC_OUTFLOW) + 12) / 13);
-    long long best = -1;
-    for (int p = 64; p >= 4; p /= 2) {
-        const long long blocks = pcols * ((g.n[2] + p - 1) / p);
-        const long long cost = ((blocks + 255) / 256) * (p + 2);
-        if (best < 0 || cost < best) {
-            best = cost;
-            g.pred_planes = p;
-        }
-    }
+    // fused predictor: the (column tile, plane) positions, tile-major, split
+    // evenly over one wave of resident blocks, at least 4 planes a block (a
+    // block solves the faces of one plane beyond each end of every run of
+    // planes it marches)
+    const long long npos = pred_tiles(g) * g.n[2];
+    const long long resident = (long long)kNumCUs * kPredBlocksPerCU;
+    long long chunk = (npos + resident - 1) / resident;
+    if (chunk < 4) chunk = 4;
+    g.pred_chunk = (int)chunk;
     const int oct = tile_override("ct"), opred = tile_override("pred");
     if (oct == 4 || oct == 8 || oct == 16) g.ct_planes = oct;
-    if (opred >= 1 && opred <= 64) g.pred_planes = opred;
+    if (opred >= 1) g.pred_chunk = opred;
     return g;
 }
 

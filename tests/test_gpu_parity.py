@@ -213,16 +213,18 @@ def test_turbulence_128_hundred_steps(recon, capsys):
 
 
 TILE_VARIANTS = ["ct=4", "ct=8", "ct=16", "march=8", "march=16", "pred=1", "pred=3", "pred=8",
-                 "pred=64", "ct=16,march=16,pred=32"]
+                 "pred=64", "pred=40", "pred=100000", "ct=16,march=16,pred=32"]
 
 
 @pytest.mark.parametrize("maker", ["turb_plmc", "turb_ppmc", "blast_ppmc"])
 def test_tile_variants_bitwise_equal(maker, monkeypatch):
     """Every tile shape the size rules can choose -- CT blocks of 4, 8 or 16
     planes, corrector marches of 8 or 16 faces, fused predictor blocks of 1 to
-    64 planes -- forced on one ragged grid (VLCT_TILES) gives bit for bit the
-    state and next dt of the default choice, which matches the oracle; grids
-    this small would otherwise only run the small-grid shapes."""
+    64 (column tile, plane) positions, shares that cross from one column tile
+    into the next and one block marching every tile in turn -- forced on one
+    ragged grid (VLCT_TILES) gives bit for bit the state and next dt of the
+    default choice, which matches the oracle; grids this small would
+    otherwise only run the small-grid shapes."""
     _need_gpu()
     if maker == "turb_plmc":
         g, s0 = I.turbulence((45, 38, 35))
