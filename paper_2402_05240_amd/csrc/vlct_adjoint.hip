@@ -772,6 +772,95 @@ __global__ __launch_bounds__(kBlock) void k_ad_recon(Geom g, Prims P, AdStage S)
     atomicAdd(&S.lw[5 + D][t], abn);
 }
 
+// The parabolic reversals add each cell's stencil cotangents (five cells)
+// without one atomic per term.  Along y and z a thread marches a column
+// segment of M cells and keeps the four cells still waiting for terms in LDS
+// (thread-private slots, cell c in slot c mod 5); a cell leaves with one
+// atomic add per component once the reversal two cells above it is done
+// (segments share two cells at each end, so every departure stays atomic).
+// The cell's own B_n cotangent comes from its reversal alone and is added
+// in place.
+template <int D, int RECON, int M = kAdMarch>
+__global__ __launch_bounds__(kBlock) void k_ad_recon_march(Geom g, Prims P, AdStage S)
+{
+    static_assert(D == 1 || D == 2, "columns march along y or z");
+    static_assert(RECON == VLCT_RECON_PPMC || RECON == VLCT_RECON_PPMP, "parabolic reconstructions");
+    constexpr int T = D == 1 ? 2 : 1;
+    constexpr bool kChar = RECON == VLCT_RECON_PPMC;
+    __shared__ double pend[5][7][kBlock];
+    const int nD = g.n[D];
+    const idx_t cols = (idx_t)g.n[0] * g.n[T];
+    const idx_t ncb = (cols + kBlock - 1) / kBlock;
+    const idx_t b = blockIdx.x;
+    const int seg = (int)(b / ncb);
+    const idx_t col = (b - (idx_t)seg * ncb) * kBlock + threadIdx.x;
+    if (col >= cols) return;
+    const int tid = threadIdx.x;
+    int x[3];
+    x[0] = (int)(col % g.n[0]);
+    x[T] = (int)(col / g.n[0]);
+    const int s0 = seg * M, s1 = min(s0 + M, nD);  // cells [s0, s1)
+    auto slot = [](int c) { return (c + 10) % 5; };  // c >= -2
+    auto cell_at = [&](int along) {
+        int e[3] = {x[0], x[1], x[2]};
+        e[D] = along;
+        return cell_of(g, e);
+    };
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 7; ++k) pend[slot(s0 - 2 + q)][k][tid] = 0.0;
+    for (int c = s0; c < s1; ++c) {
+        const idx_t t = cell_at(c);
+        double afm[7], afp[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            afm[k] = S.lrec[D][k][t];
+            afp[k] = S.lrec[D][7 + k][t];
+        }
+        idx_t po[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            int e[3] = {x[0], x[1], x[2]};
+            e[D] = c - 2 + q;
+            po[q] = pidx(g, e[0], e[1], e[2]);
+        }
+        W7 ad[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) ad[q] = W7{0, 0, 0, 0, 0, 0, 0};
+        double abn = 0.0;
+        ppmc_rev<kChar>(w7_at(P, D, po[0]), w7_at(P, D, po[1]), w7_at(P, D, po[2]),
+                        w7_at(P, D, po[3]), w7_at(P, D, po[4]), P.w[5 + D][po[2]], g.gamma,
+                        afm, afp, ad[0], ad[1], ad[2], ad[3], ad[4], abn);
+        double v[5][7];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            v[q][0] = ad[q].d; v[q][1] = ad[q].u; v[q][2] = ad[q].v; v[q][3] = ad[q].w;
+            v[q][4] = ad[q].p; v[q][5] = ad[q].by; v[q][6] = ad[q].bz;
+        }
+        const idx_t cm = cell_at(c - 2);
+        const int sm = slot(c - 2), s1m = slot(c - 1), s00 = slot(c), s1p = slot(c + 1),
+                  s2p = slot(c + 2);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            atomicAdd(&S.lw[lab_slot(D, k)][cm], pend[sm][k][tid] + v[0][k]);
+            pend[s1m][k][tid] += v[1][k];
+            pend[s00][k][tid] += v[2][k];
+            pend[s1p][k][tid] += v[3][k];
+            pend[s2p][k][tid] = v[4][k];
+        }
+        S.lw[5 + D][t] += abn;
+    }
+    // the cells s1 - 2 .. s1 + 1 (the last reversal was that of cell s1 - 1)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const idx_t cc = cell_at(s1 - 2 + q);
+        const int sl = slot(s1 - 2 + q);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) atomicAdd(&S.lw[lab_slot(D, k)][cc], pend[sl][k][tid]);
+    }
+}
+
 // cotangent of -(v x B)_A at cell x from the four A-edges around it
 template <int A>
 __device__ __forceinline__ double eref_cotangent(const Geom &g, const AdStage &S, const int x[3])
@@ -910,8 +999,14 @@ static void stage_adjoint(const Geom &g, double factor, const StateP &lout, cons
             g, P, st, lout, S, lacc, dt, factor);
 #define VLCT_AD_RECON(R)                                                                   \
     k_ad_recon<0, R><<<gc, kBlock, 0, s>>>(g, P, S);                                       \
-    k_ad_recon<1, R><<<gc, kBlock, 0, s>>>(g, P, S);                                       \
-    k_ad_recon<2, R><<<gc, kBlock, 0, s>>>(g, P, S);
+    if (ad_march_segment(g, 1) == 8)                                                       \
+        k_ad_recon_march<1, R, 8><<<(unsigned)ad_march_blocks(g, 1, 8), kBlock, 0, s>>>(g, P, S); \
+    else                                                                                   \
+        k_ad_recon_march<1, R><<<(unsigned)ad_march_blocks(g, 1), kBlock, 0, s>>>(g, P, S); \
+    if (ad_march_segment(g, 2) == 8)                                                       \
+        k_ad_recon_march<2, R, 8><<<(unsigned)ad_march_blocks(g, 2, 8), kBlock, 0, s>>>(g, P, S); \
+    else                                                                                   \
+        k_ad_recon_march<2, R><<<(unsigned)ad_march_blocks(g, 2), kBlock, 0, s>>>(g, P, S);
     if (recon == VLCT_RECON_PCM) {
         k_ad_faces<0><<<gc, kBlock, 0, s>>>(g, P, st, lout, S, lacc, dt, factor);
         k_ad_faces<1><<<gc, kBlock, 0, s>>>(g, P, st, lout, S, lacc, dt, factor);

@@ -145,7 +145,7 @@ inline bool grid_ok(const vlct_grid *g)
 }
 
 // Tile override for tests and tuning: the environment variable VLCT_TILES,
-// read at every call, holds comma-separated key=value pairs (ct=4|8|16 CT
+// read at every call, holds comma-separated key=value pairs (ct=4|8|16|32|64 CT
 // planes per block, march=8|16 faces per corrector march segment, pred=N
 // (column tile, plane) positions per fused predictor block, admarch=8|16 cells per adjoint march
 // segment) that replace the size-dependent choices.  Every choice computes the
@@ -216,7 +216,7 @@ inline Geom make_geom(const vlct_grid *vg)
     if (chunk < 4) chunk = 4;
     g.pred_chunk = (int)chunk;
     const int oct = tile_override("ct"), opred = tile_override("pred");
-    if (oct == 4 || oct == 8 || oct == 16) g.ct_planes = oct;
+    if (oct == 4 || oct == 8 || oct == 16 || oct == 32 || oct == 64) g.ct_planes = oct;
     if (opred >= 1) g.pred_chunk = opred;
     return g;
 }
