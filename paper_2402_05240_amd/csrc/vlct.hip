@@ -769,10 +769,11 @@ __device__ __forceinline__ void ct_body(const Geom &g, const Prims &P, const Flu
 
 // ---------------------------------------------------------------------------
 // fused predictor (Steps 2-5 in one kernel): the (column tile, plane) pairs
-// of the grid, tile-major, are dealt out to the blocks in equal runs
-// (Geom::pred_chunk), one wave of resident blocks when the grid is large
-// enough; a block marches along z through each run [k0, k1) of planes of a
-// TX x TY column tile that its share holds.  Per new plane m it
+// of the grid, in z slabs, are dealt out to the blocks in equal shares
+// (Geom::pred_slab, Geom::pred_chunk: one (slab, tile) per block, or a single
+// slab shared out evenly over one wave of resident blocks); a block marches
+// along z through each run [k0, k1) of planes of a TX x TY column tile that
+// its share holds.  Per new plane m it
 //   (A) derives the primitives of the tile plus a one-cell ring (Sec. 2.1,
 //       B_cc = face average, floors) and the reference field -(v x B),
 //   (B) solves PCM HLLD on the x- and y-faces of plane m and the z-face
@@ -815,7 +816,10 @@ __device__ __forceinline__ double edge_value(double eb_c, double eb_cm, double e
 // interior cells are written there as k_prims would derive them from
 // U^{n+1/2}; its ghost layers are left to k_prims_ghost.  Both are run-time
 // choices of one kernel, so a taped step runs the very code of a plain one.
-template <int TX, int TY>
+// ONE_RUN: block b is the single run of tile b mod ntiles in z slab
+// b / ntiles (Geom::pred_chunk == 0); else its share of Geom::pred_chunk
+// pairs in slab order (a zero chunk taken as one slab's worth).
+template <int TX, int TY, bool ONE_RUN>
 __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const StateW &out,
                                           const Prims &P, const double *dt_dev, uint32_t *status,
                                           idx_t b, uint8_t *side0, uint8_t *side1, uint8_t *side2)
@@ -843,14 +847,16 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
 
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const int ex = nx + (g.bc[0] == VLCT_BC_OUTFLOW), ey = ny + (g.bc[1] == VLCT_BC_OUTFLOW);
-    // the block's share: positions [pos0, pos1) of the sequence (column tile,
-    // plane), tile-major, planes along z; it marches each tile's run of
-    // planes in turn
-    const int ntx = (ex + TX - 1) / TX, nty = (ey + TY - 1) / TY;
-    const int npos = ntx * nty * nz;  // below 2^31 for sides up to kMaxN
-    if (b * (idx_t)g.pred_chunk >= npos) return;
-    const int pos0 = (int)b * g.pred_chunk;
-    const int pos1 = min(pos0 + g.pred_chunk, npos);
+    // the block's share: positions [pos0, pos1) of the sequence of (column
+    // tile, plane) pairs ordered by z slab of Geom::pred_slab planes (the last
+    // slab holds the remainder), then tile, then plane; it marches each run of
+    // one tile's planes in turn
+    const int ntx = (ex + TX - 1) / TX, nty = (ey + TY - 1) / TY, ntiles = ntx * nty;
+    const int npos = ntiles * nz;  // below 2^31 for sides up to kMaxN
+    const int H = g.pred_slab, nfull = nz / H, rem = nz - nfull * H;
+    if (ONE_RUN && b >= (idx_t)ntiles * (nfull + (rem > 0))) return;
+    const int chunk = g.pred_chunk > 0 ? g.pred_chunk : H;
+    if (!ONE_RUN && b * (idx_t)chunk >= npos) return;
     const double dt = 0.5 * dt_dev[0];
     const double cx = dt / g.dl[0], cy = dt / g.dl[1], cz = dt / g.dl[2];
 
@@ -860,11 +866,7 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
     const int a = t % CX, c = t / CX;
     const int tx = a - 1, ty = c - 1;
     uint32_t st = 0;
-    for (int pos = pos0; pos < pos1;) {
-        const int tile = pos / nz;
-        const int k0 = pos - tile * nz;
-        const int k1 = min(nz, k0 + (pos1 - pos));
-        pos += k1 - k0;
+    auto run = [&](const int tile, const int k0, const int k1) {
         const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
         // cell (ii, jj) of the column
         const int ii = i0 - 1 + a, jj = j0 - 1 + c;
@@ -945,7 +947,7 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
                     const int l = t - 1;
                     const W7 wl{s_wh[0][l], s_wh[1][l], s_wh[2][l], s_wh[3][l], s_wh[4][l], s_wh[6][l], s_wh[7][l]};
                     hlld(wl, wxr, bx0, g.gamma, g.gm1i, f, upw);
-    #pragma unroll
+#pragma unroll
                     for (int q = 0; q < 5; ++q) hxn[q] = f[q];
                     s_em[sm][0][t] = -f[5];
                     s_em[sm][1][t] = f[6];
@@ -956,7 +958,7 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
                     const W7 wl{s_wh[0][l], s_wh[2][l], s_wh[3][l], s_wh[1][l], s_wh[4][l], s_wh[7][l], s_wh[5][l]};
                     const W7 wr{s_wh[0][t], s_wh[2][t], s_wh[3][t], s_wh[1][t], s_wh[4][t], s_wh[7][t], s_wh[5][t]};
                     hlld(wl, wr, by0, g.gamma, g.gm1i, f, upw);
-    #pragma unroll
+#pragma unroll
                     for (int q = 0; q < 5; ++q) hyn[q] = f[q];
                     s_em[sm][2][t] = -f[5];
                     s_em[sm][3][t] = f[6];
@@ -964,7 +966,7 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
                 }
                 if (do_z && m >= k0) {
                     hlld(wz_prev, wz, bz0, g.gamma, g.gm1i, f, upw);
-    #pragma unroll
+#pragma unroll
                     for (int q = 0; q < 5; ++q) hzn[q] = f[q];
                     s_zem[0][t] = -f[5];
                     s_zem[1][t] = f[6];
@@ -982,7 +984,7 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
                 const int k = m - 1;
                 if (interior) {
                     const idx_t cc = cell_store(g, ii, jj, k);
-    #pragma unroll
+#pragma unroll
                     for (int q = 0; q < 5; ++q) u0[q] = s.u[q][cc];
                     bzb = s.b[2][face_store(g, 2, ii, jj, k)];
                     if (P.w[0]) {
@@ -1033,7 +1035,7 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
                 }
             }
             if (upd && live) {
-    #pragma unroll
+#pragma unroll
                 for (int q = 0; q < 5; ++q) {
                     s_wh[q][t] = hx[q];
                     s_wh[5 + q][t] = hy[q];
@@ -1078,7 +1080,7 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
                     u[2] = u0[2] - cx * dxmy - cy * dymy - cz * dzmy;
                     u[3] = u0[3] - cx * dxmz - cy * dymz - cz * dzmz;
                     u[4] = u0[4] - cx * dxe - cy * dye - cz * dze;
-    #pragma unroll
+#pragma unroll
                     for (int q = 0; q < 5; ++q) out.u[q][cc] = u[q];
                 }
                 if (jj < ny) {  // face x (ii - 1/2, jj, k)
@@ -1121,7 +1123,7 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
                                  + cy * (s_ex[sm][ty + 1][tx] - s_ex[sm][ty][tx]);
                 out.b[2][face_store(g, 2, ii, jj, nz)] = v;
             }
-    #pragma unroll
+#pragma unroll
             for (int q = 0; q < 5; ++q) {
                 hx[q] = hxn[q];
                 hy[q] = hyn[q];
@@ -1129,6 +1131,32 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
             }
             wz_prev = wz;
             __syncthreads();
+        }
+    };
+    if (ONE_RUN) {
+        const int tile = (int)(b % ntiles), sl = (int)(b / ntiles);
+        run(tile, sl * H, min(sl * H + H, nz));
+    } else {
+        const int pos0 = (int)b * chunk, pos1 = min(pos0 + chunk, npos);
+        const int fullpos = nfull * ntiles * H;
+        for (int pos = pos0; pos < pos1;) {
+            int tile, k0, len;
+            if (pos < fullpos) {
+                const int sl = pos / (ntiles * H), r = pos - sl * ntiles * H;
+                tile = r / H;
+                const int kk = r - tile * H;
+                k0 = sl * H + kk;
+                len = H - kk;
+            } else {
+                const int r = pos - fullpos;
+                tile = r / rem;
+                const int kk = r - tile * rem;
+                k0 = nfull * H + kk;
+                len = rem - kk;
+            }
+            const int k1 = k0 + min(len, pos1 - pos);
+            pos += k1 - k0;
+            run(tile, k0, k1);
         }
     }
     if (st && status) atomicOr(status, st);
@@ -1241,20 +1269,31 @@ constexpr int kPredThreads = PredShape<kPredTx, kPredTy>::NT;
 static_assert(kPredThreads * kPredBlocksPerCU <= 1024,
               "the resident predictor blocks of a CU hold at most two waves per SIMD");
 
-// blocks of the fused predictor: Geom::pred_chunk (tile, plane) positions each
+// blocks of the fused predictor: one per (slab, tile) (Geom::pred_chunk == 0),
+// else shares of Geom::pred_chunk (tile, plane) pairs
 __host__ __device__ __forceinline__ idx_t nblk_pred(const Geom &g)
 {
+    const idx_t nsl = (g.n[2] + g.pred_slab - 1) / g.pred_slab;
+    if (g.pred_chunk == 0) return pred_tiles(g) * nsl;
     const idx_t npos = pred_tiles(g) * g.n[2];
     return (npos + g.pred_chunk - 1) / g.pred_chunk;
 }
+// blocks of the share form (the batched step's), a zero chunk taken as one slab
+__host__ __device__ __forceinline__ idx_t nblk_pred_shares(const Geom &g)
+{
+    const idx_t npos = pred_tiles(g) * g.n[2];
+    const idx_t chunk = g.pred_chunk > 0 ? g.pred_chunk : g.pred_slab;
+    return (npos + chunk - 1) / chunk;
+}
 
+template <bool ONE_RUN>
 __global__ void __launch_bounds__(kPredThreads, kPredWavesPerSimd) k_pred(Geom g, StateP s, StateW out, Prims P,
                                                         const double *dt_dev, uint32_t *status,
                                                         uint8_t *side0, uint8_t *side1,
                                                         uint8_t *side2)
 {
-    pred_body<kPredTx, kPredTy>(g, s, out, P, dt_dev, status, xcd_block(nblk_pred(g)), side0,
-                                side1, side2);
+    pred_body<kPredTx, kPredTy, ONE_RUN>(g, s, out, P, dt_dev, status, xcd_block(nblk_pred(g)),
+                                         side0, side1, side2);
 }
 
 __global__ void __launch_bounds__(kBlock) k_prims_ghost(Geom g, StateP s, Prims P,
@@ -1362,7 +1401,8 @@ __global__ void __launch_bounds__(kPredThreads, kPredWavesPerSimd) kb_pred(const
     const StateP in = I.in;
     const StateW half = I.half;
     const Prims P = I.P;
-    pred_body<kPredTx, kPredTy>(g, in, half, P, I.dt, I.status, lb, nullptr, nullptr, nullptr);
+    pred_body<kPredTx, kPredTy, false>(g, in, half, P, I.dt, I.status, lb, nullptr, nullptr,
+                                       nullptr);
 }
 
 // ghost-layer primitives of the half-step state of every instance
@@ -1659,9 +1699,14 @@ static int launch_pred(const Geom &g, const StateP &st, const StateW &half, cons
 {
     {
         Observe o(VLCT_KERNEL_PREDICTOR, s);
-        k_pred<<<xcd_grid(nblk_pred(g)), kPredThreads, 0, s>>>(
-            g, st, half, P, dt_dev, status, side ? side[0] : nullptr, side ? side[1] : nullptr,
-            side ? side[2] : nullptr);
+        uint8_t *s0 = side ? side[0] : nullptr, *s1 = side ? side[1] : nullptr,
+                *s2 = side ? side[2] : nullptr;
+        if (g.pred_chunk == 0)
+            k_pred<true><<<xcd_grid(nblk_pred(g)), kPredThreads, 0, s>>>(g, st, half, P, dt_dev,
+                                                                        status, s0, s1, s2);
+        else
+            k_pred<false><<<xcd_grid(nblk_pred(g)), kPredThreads, 0, s>>>(g, st, half, P, dt_dev,
+                                                                         status, s0, s1, s2);
     }
     // ghost layers of the half-step primitives
     Observe o(VLCT_KERNEL_PRIMS, s);
@@ -1765,7 +1810,7 @@ static void batch_records(int count, const vlct_grid *grids, const vlct_state *i
         r.t = nullptr;
         const int cv = plan ? (plan[i] & 15) : 0, mv = plan ? (plan[i] >> 4) : 0;
         idx_t nb[kSlots] = {};
-        nb[kSlotPred] = nblk_pred(g);
+        nb[kSlotPred] = nblk_pred_shares(g);
         nb[kSlotGhost] = (ghost_cells(g) + kBlock - 1) / kBlock;
         nb[kSlotPrims] = nblk_prims(g);
         for (int d = 0; d < 3; ++d) nb[kSlotFlux0 + d] = nblk_flux(g, d);

@@ -41,7 +41,9 @@ struct Geom {
     double gamma, gm1i, cfl;
     int p[3];  // padded primitive dims n + 2G
     int ct_planes;    // z planes a CT block marches through
-    int pred_chunk;   // (column tile, plane) positions of one fused predictor block
+    int pred_slab;    // z planes per slab of the fused predictor's pair order
+    int pred_chunk;   // (column tile, plane) pairs of one fused predictor block
+                      // (0: one (slab, tile) per block)
 };
 
 __host__ __device__ __forceinline__ int map_cell(int i, int n, int bc)
@@ -147,7 +149,8 @@ inline bool grid_ok(const vlct_grid *g)
 // Tile override for tests and tuning: the environment variable VLCT_TILES,
 // read at every call, holds comma-separated key=value pairs (ct=4|8|16|32|64 CT
 // planes per block, march=8|16 faces per corrector march segment, pred=N
-// (column tile, plane) positions per fused predictor block, admarch=8|16 cells per adjoint march
+// (column tile, plane) pairs per fused predictor block in one shared slab,
+// predslab=P slabs of P planes one per predictor block, admarch=8|16 cells per adjoint march
 // segment) that replace the size-dependent choices.  Every choice computes the
 // same per-cell and per-face arithmetic; the forward results are bitwise the
 // same, the adjoint's equal to the summation order of its accumulations.
@@ -197,27 +200,52 @@ inline Geom make_geom(const vlct_grid *vg)
     g.gamma = vg->gamma;
     g.gm1i = 1.0 / (vg->gamma - 1.0);
     g.cfl = vg->cfl;
-    // CT blocks march 16 planes through a column tile of 64 x 8; a grid with
-    // fewer than 1024 such blocks (4 per CU) takes 8, and one with fewer than
-    // 256 blocks of 8 planes takes 4 (measured at 64^3 .. 256^3: 16 planes from
-    // 256^3 up, 8 at 128^3 and 192^3, 4 at 64^3)
+    // CT blocks march 32 planes through a column tile of 64 x 8, halved down to
+    // 8 while the grid has fewer than 1024 such blocks (4 per CU); one with
+    // fewer than 256 blocks of 8 planes takes 4 (measured at 64^3 .. 256^3: 32
+    // planes from 256^3 up, 8 at 128^3 and 192^3, 4 at 64^3)
     const long long cols = (long long)((g.n[0] + (g.bc[0] == VLCT_BC_OUTFLOW) + 63) / 64) *
                            ((g.n[1] + (g.bc[1] == VLCT_BC_OUTFLOW) + 7) / 8);
-    g.ct_planes = 16;
-    if (cols * ((g.n[2] + 15) / 16) < 1024) g.ct_planes = 8;
+    g.ct_planes = 32;
+    while (g.ct_planes > 8 && cols * ((g.n[2] + g.ct_planes - 1) / g.ct_planes) < 1024)
+        g.ct_planes /= 2;
     if (g.ct_planes == 8 && cols * ((g.n[2] + 7) / 8) < 256) g.ct_planes = 4;
-    // fused predictor: the (column tile, plane) positions, tile-major, split
-    // evenly over one wave of resident blocks, at least 4 planes a block (a
-    // block solves the faces of one plane beyond each end of every run of
-    // planes it marches)
-    const long long npos = pred_tiles(g) * g.n[2];
-    const long long resident = (long long)kNumCUs * kPredBlocksPerCU;
-    long long chunk = (npos + resident - 1) / resident;
+    // fused predictor (a run of p planes also solves the faces of one plane
+    // beyond each end): either one (z slab of p planes, column tile) per block,
+    // neighbouring tiles of a slab in neighbouring blocks so that they share
+    // their ring columns in L2, p minimising (waves of resident blocks) x
+    // (p + 2); or, where that leaves much of the last wave idle, the grid as
+    // one slab shared out evenly over one wave, at least 4 planes a block
+    // (measured: slabs at 64^3 and 256^3, one shared slab at 128^3)
+    const long long tiles = pred_tiles(g), resident = (long long)kNumCUs * kPredBlocksPerCU;
+    double best = -1.0;
+    for (int p = 64; p >= 4; p /= 2) {
+        const long long blocks = tiles * ((g.n[2] + p - 1) / p);
+        const double cost = (double)((blocks + resident - 1) / resident) * (p + 2);
+        if (best < 0.0 || cost < best) {
+            best = cost;
+            g.pred_slab = p;
+            g.pred_chunk = 0;  // one (slab, tile) per block
+        }
+    }
+    long long chunk = (tiles * g.n[2] + resident - 1) / resident;
     if (chunk < 4) chunk = 4;
-    g.pred_chunk = (int)chunk;
+    const double shared = (double)chunk + 2.0 * (1.0 + (double)chunk / g.n[2]);
+    if (shared < 0.9 * best) {
+        g.pred_slab = g.n[2];
+        g.pred_chunk = (int)chunk;
+    }
     const int oct = tile_override("ct"), opred = tile_override("pred");
     if (oct == 4 || oct == 8 || oct == 16 || oct == 32 || oct == 64) g.ct_planes = oct;
-    if (opred >= 1) g.pred_chunk = opred;
+    const int oslab = tile_override("predslab");
+    if (opred >= 1) {  // one shared slab, opred pairs per block
+        g.pred_slab = g.n[2];
+        g.pred_chunk = opred;
+    }
+    if (oslab >= 1) {  // slabs of oslab planes, one (slab, tile) per block
+        g.pred_slab = oslab;
+        g.pred_chunk = 0;
+    }
     return g;
 }
 

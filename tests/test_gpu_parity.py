@@ -212,16 +212,18 @@ def test_turbulence_128_hundred_steps(recon, capsys):
             assert m[f] <= max(1e-9, 10.0 * sens_max[f]), (nsteps, f, m[f], sens_max[f])
 
 
-TILE_VARIANTS = ["ct=4", "ct=8", "ct=16", "march=8", "march=16", "pred=1", "pred=3", "pred=8",
-                 "pred=64", "pred=40", "pred=100000", "ct=16,march=16,pred=32"]
+TILE_VARIANTS = ["ct=4", "ct=8", "ct=16", "ct=32", "ct=64", "march=8", "march=16", "pred=1", "pred=3", "pred=8",
+                 "pred=64", "pred=40", "pred=100000", "predslab=8", "predslab=32",
+                 "predslab=64", "ct=16,march=16,pred=32"]
 
 
 @pytest.mark.parametrize("maker", ["turb_plmc", "turb_ppmc", "blast_ppmc"])
 def test_tile_variants_bitwise_equal(maker, monkeypatch):
     """Every tile shape the size rules can choose -- CT blocks of 4, 8 or 16
-    planes, corrector marches of 8 or 16 faces, fused predictor blocks of 1 to
-    64 (column tile, plane) positions, shares that cross from one column tile
-    into the next and one block marching every tile in turn -- forced on one
+    planes (up to 64), corrector marches of 8 or 16 faces, fused predictor blocks of 1 to
+    64 (column tile, plane) pairs, shares that cross from one column tile
+    into the next, one block marching every tile in turn, and z slabs of 8,
+    32 or 64 planes with a ragged last slab -- forced on one
     ragged grid (VLCT_TILES) gives bit for bit the state and next dt of the
     default choice, which matches the oracle; grids this small would
     otherwise only run the small-grid shapes."""
