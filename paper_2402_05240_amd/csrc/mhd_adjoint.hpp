@@ -81,14 +81,20 @@ VLCT_DEV void hlld_rev(const W7 &L, const W7 &R, double bn, double gam, double g
     const double eR = R.p * gm1i + 0.5 * R.d * u2R + pbR;
     // c_f = num rq, rq = 1 / sqrt(2 rho num), num = gP + B^2 + disc; then
     // 1 / c_f = 2 rho rq and 1 / (2 rho) = num rq^2
-    FastSq qfL = fast_sq_terms(L.p, bn2, L.by, L.bz, gam);
-    FastSq qfR = fast_sq_terms(R.p, bn2, R.by, R.bz, gam);
-    const double numL = qfL.gp + qfL.b2 + qfL.disc, numR = qfR.gp + qfR.b2 + qfR.disc;
-    const double rqL = mrsqrt(2.0 * L.d * numL), rqR = mrsqrt(2.0 * R.d * numR);
-    const double cfL = numL * rqL, cfR = numR * rqR;
-    const double i2dL = numL * rqL * rqL, i2dR = numR * rqR * rqR;
-    qfL.cf2 = numL * i2dL;
-    qfR.cf2 = numR * i2dR;
+    auto fast_fwd = [&](const W7 &X, FastSq &q, double &rq) {
+        q = fast_sq_terms(X.p, bn2, X.by, X.bz, gam);
+        const double num = q.gp + q.b2 + q.disc;
+        rq = mrsqrt(2.0 * X.d * num);
+        q.cf2 = num * (num * rq * rq);
+        return num * rq;
+    };
+    double cfL, cfR;
+    {
+        FastSq q;
+        double rq;
+        cfL = fast_fwd(L, q, rq);
+        cfR = fast_fwd(R, q, rq);
+    }
     const bool cmaxR = takes_second_max(cfL, cfR);
     const double cmax = cmaxR ? cfR : cfL;
     const bool uminR = takes_second_min(L.u, R.u);
@@ -400,7 +406,6 @@ VLCT_DEV void hlld_rev(const W7 &L, const W7 &R, double bn, double gam, double g
     if (uminR) a_uR = a_uR + a_S2[0]; else a_uL = a_uL + a_S2[0];
     if (umaxR) a_uR = a_uR + a_S2[1]; else a_uL = a_uL + a_S2[1];
     const double a_cmax = a_S2[1] - a_S2[0];
-    double a_cfL = cmaxR ? 0.0 : a_cmax, a_cfR = cmaxR ? a_cmax : 0.0;
     // e = p / (g - 1) + rho u^2 / 2 + pb, pt = p + pb, pb = (bn^2 + by^2 + bz^2) / 2
     double a_pL = a_pt2[0] + a_e2[0] * gm1i, a_pR = a_pt2[1] + a_e2[1] * gm1i;
     const double a_pbL = a_pt2[0] + a_e2[0], a_pbR = a_pt2[1] + a_e2[1];
@@ -413,14 +418,25 @@ VLCT_DEV void hlld_rev(const W7 &L, const W7 &R, double bn, double gam, double g
     double a_byL = L.by * a_pbL, a_bzL = L.bz * a_pbL;
     double a_byR = R.by * a_pbR, a_bzR = R.bz * a_pbR;
     a_bn2 = a_bn2 + 0.5 * (a_pbL + a_pbR);
-    // fast speeds
-    // d c_f / d cf2 = 1 / (2 c_f) = rho rq
-    const double idcL = qfL.disc > 0.0 ? 1.0 / qfL.disc : 0.0;
-    const double idcR = qfR.disc > 0.0 ? 1.0 / qfR.disc : 0.0;
-    fast_sq_rev(qfL, i2dL, idcL, bn, L.by, L.bz, gam, a_cfL * (L.d * rqL), 0.0, a_dL, a_pL, a_bn,
-                a_byL, a_bzL);
-    fast_sq_rev(qfR, i2dR, idcR, bn, R.by, R.bz, gam, a_cfR * (R.d * rqR), 0.0, a_dR, a_pR, a_bn,
-                a_byR, a_bzR);
+    // fast speeds: only the larger one (c_max) has a cotangent; its forward
+    // terms are evaluated again here rather than kept alive through the
+    // reverse.  d c_f / d cf2 = 1 / (2 c_f) = rho rq, 1 / (2 rho) = cf2 / num
+    {
+        const W7 &Xc = cmaxR ? R : L;
+        FastSq q;
+        double rq;
+        fast_fwd(Xc, q, rq);
+        const double i2d = (q.gp + q.b2 + q.disc) * rq * rq;
+        const double idc = q.disc > 0.0 ? 1.0 / q.disc : 0.0;
+        double a_d = 0.0, a_p = 0.0, a_by = 0.0, a_bz = 0.0;
+        fast_sq_rev(q, i2d, idc, bn, Xc.by, Xc.bz, gam, a_cmax * (Xc.d * rq), 0.0, a_d, a_p, a_bn,
+                    a_by, a_bz);
+        if (cmaxR) {
+            a_dR = a_dR + a_d; a_pR = a_pR + a_p; a_byR = a_byR + a_by; a_bzR = a_bzR + a_bz;
+        } else {
+            a_dL = a_dL + a_d; a_pL = a_pL + a_p; a_byL = a_byL + a_by; a_bzL = a_bzL + a_bz;
+        }
+    }
     a_bn = a_bn + 2.0 * bn * a_bn2;
 
     // chosen-side state cotangents

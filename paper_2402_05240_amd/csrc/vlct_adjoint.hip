@@ -232,9 +232,10 @@ __device__ __forceinline__ void flux_cotangent(const Geom &g, const StateP &lout
 // the forward states (the cell primitives).  The cotangents of the face's two
 // states are stored per cell and axis (as the high state of the left cell and
 // the low state of the right cell) for the next transpose.  A reconstructing
-// stage takes k_ad_faces_row (x) and k_ad_faces_march (y, z).
+// stage takes k_ad_faces_row (x) and k_ad_faces_march (y, z).  Two waves per
+// SIMD (256 registers and a short spill) beat one wave with 280 registers.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_ad_faces(Geom g, Prims P, StateP st, StateP lout,
+__global__ __launch_bounds__(kBlock, 2) void k_ad_faces(Geom g, Prims P, StateP st, StateP lout,
                                                      AdStage S, StateW lacc,
                                                      const double *dt_dev, double factor)
 {
@@ -395,7 +396,7 @@ __host__ __device__ __forceinline__ idx_t ad_row_blocks(const Geom &g)
 }
 
 template <int RECON>
-__global__ __launch_bounds__(kBlock) void k_ad_faces_row(Geom g, Prims P, StateP st,
+__global__ __launch_bounds__(kBlock, 2) void k_ad_faces_row(Geom g, Prims P, StateP st,
                                                          StateP lout, AdStage S, StateW lacc,
                                                          const double *dt_dev, double factor)
 {
