@@ -114,23 +114,17 @@ __device__ __forceinline__ void edge_weights(const Geom &g, const AdStage &S, co
     }
 }
 
-__global__ void k_ad_fill(double *p, idx_t n)
-{
-    const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) p[t] = 0.0;
-}
-
 // lam_next = lam_out with each periodic duplicate face folded into face 0 (the
-// step writes face n as a copy of face 0); lam_in starts as lam_next (U^{n+1}
-// contains U^n with unit weight)
-__global__ void k_ad_init(Geom g, StateP lo, StateW next, StateW lin)
+// step writes face n as a copy of face 0); the half-step cotangent `half`
+// starts at zero
+__global__ void k_ad_init(Geom g, StateP lo, StateW next, StateW half)
 {
     const idx_t N = (idx_t)g.n[0] * g.n[1] * g.n[2];
     const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < N)
         for (int f = 0; f < 5; ++f) {
             next.u[f][t] = lo.u[f][t];
-            lin.u[f][t] = lo.u[f][t];
+            half.u[f][t] = 0.0;
         }
     for (int d = 0; d < 3; ++d) {
         const idx_t nf = N / g.n[d] * (g.n[d] + 1);
@@ -146,27 +140,30 @@ __global__ void k_ad_init(Geom g, StateP lo, StateW next, StateW lin)
             v += lo.b[d][face_store(g, d, q[0], q[1], q[2])];
         }
         next.b[d][t] = v;
-        lin.b[d][t] = v;
+        half.b[d][t] = 0.0;
     }
 }
 
-// acc += add (cells and faces)
-__global__ void k_ad_add(Geom g, StateW acc, StateP add)
+// out = a + b (cells and faces): lam_in starts as lam_next (U^{n+1} contains
+// U^n with unit weight) plus the half-step cotangent
+__global__ void k_ad_add(Geom g, StateW out, StateP a, StateP b)
 {
     const idx_t N = (idx_t)g.n[0] * g.n[1] * g.n[2];
     const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < N)
-        for (int f = 0; f < 5; ++f) acc.u[f][t] += add.u[f][t];
+        for (int f = 0; f < 5; ++f) out.u[f][t] = a.u[f][t] + b.u[f][t];
     for (int d = 0; d < 3; ++d) {
         const idx_t nf = N / g.n[d] * (g.n[d] + 1);
-        if (t < nf) acc.b[d][t] += add.b[d][t];
+        if (t < nf) out.b[d][t] = a.b[d][t] + b.b[d][t];
     }
 }
 
 // edge-field cotangents (curl of the face update transposed): the face update
 // is b_x -= cy (Ez(j+1) - Ez(j)) - cz (Ey(k+1) - Ey(k)) and cyclically
+// zero_lw: also clears the cell's primitive cotangents S.lw, into which the
+// reconstruction transposes that follow add
 __global__ void k_ad_edges(Geom g, StateP lout, Sides sd, AdStage S, const double *dt_dev,
-                           double factor)
+                           double factor, int zero_lw)
 {
     const idx_t N = (idx_t)g.n[0] * g.n[1] * g.n[2];
     const idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -183,6 +180,8 @@ __global__ void k_ad_edges(Geom g, StateP lout, Sides sd, AdStage S, const doubl
     S.le[1][t] = cz * (lb(0, i, j, k - 1) - lb(0, i, j, k)) + cx * (lb(2, i, j, k) - lb(2, i - 1, j, k));
     S.le[2][t] = cy * (lb(0, i, j, k) - lb(0, i, j - 1, k)) + cx * (lb(1, i - 1, j, k) - lb(1, i, j, k));
     S.wcode[t] = edge_code<0>(g, sd, x) | (edge_code<1>(g, sd, x) << 8) | (edge_code<2>(g, sd, x) << 16);
+    if (zero_lw)
+        for (int f = 0; f < 8; ++f) S.lw[f][t] = 0.0;
 }
 
 // cotangents of the 7 fluxes of the face of axis D at x (the low face of cell x)
@@ -959,22 +958,15 @@ __global__ __launch_bounds__(kBlock) void k_ad_prims(Geom g, StateP st, Prims P,
     }
 }
 
-static void fill(double *p, size_t n, hipStream_t s)
-{
-    if (n) k_ad_fill<<<nblocks(n), kBlock, 0, s>>>(p, (idx_t)n);
-}
-
 // transposes of one stage: lout is the cotangent of the stage's output state,
 // st/P/sd the stage's input state, primitives and upwind sides; the result
-// is added to lacc (the cotangent of the stage's input state).  lw_span is
-// the number of doubles of the contiguous span of the 8 primitive cotangents.
+// is added to lacc (the cotangent of the stage's input state).
 static void stage_adjoint(const Geom &g, double factor, const StateP &lout, const StateP &st,
                           const Prims &P, const Sides &sd, int recon, const AdStage &S,
-                          size_t lw_span, const StateW &lacc, const double *dt, hipStream_t s)
+                          const StateW &lacc, const double *dt, hipStream_t s)
 {
     const unsigned gc = nblocks((size_t)g.n[0] * g.n[1] * g.n[2]);
-    if (recon != VLCT_RECON_PCM) fill(S.lw[0], lw_span, s);
-    k_ad_edges<<<gc, kBlock, 0, s>>>(g, lout, sd, S, dt, factor);
+    k_ad_edges<<<gc, kBlock, 0, s>>>(g, lout, sd, S, dt, factor, recon != VLCT_RECON_PCM);
 #define VLCT_AD_FACES(R)                                                             \
     k_ad_faces_row<R><<<(unsigned)ad_row_blocks(g), kBlock, 0, s>>>(g, P, st, lout, S,     \
                                                                      lacc, dt, factor);    \
@@ -1036,7 +1028,7 @@ static void stage_adjoint(const Geom &g, double factor, const StateP &lout, cons
 // tape it also holds the recomputed fluxes, half-step state and upwind sides.
 struct AdLayout {
     size_t prims[2], half[8], flux[2][3], side[2][3], le, wcode, lw, lrec, total;
-    size_t prims_len, flux_len[3], cell_pitch, lhalf_span, lw_span;
+    size_t prims_len, flux_len[3], cell_pitch;
     size_t lnext[8], lhalf[8];
 };
 
@@ -1073,19 +1065,16 @@ static AdLayout ad_layout(const Geom &g, bool taped)
         L.lnext[f] = off;
         off += align_up(field_len(g.n, f) * 8);
     }
-    const size_t lhalf0 = off;
     for (int f = 0; f < 8; ++f) {
         L.lhalf[f] = off;
         off += align_up(field_len(g.n, f) * 8);
     }
-    L.lhalf_span = (off - lhalf0) / 8;
     L.le = off;
     off += 3 * L.cell_pitch;
     L.wcode = off;
     off += align_up(N * sizeof(uint32_t));
     L.lw = off;
     off += 8 * L.cell_pitch;
-    L.lw_span = L.cell_pitch;  // 8 arrays of cell_pitch bytes = cell_pitch doubles
     L.lrec = off;
     off += 42 * L.cell_pitch;
     L.total = off;
@@ -1156,12 +1145,11 @@ static int adjoint_core(const vlct_grid *vg, const Geom &g, const AdLayout &L, c
     // reverse: corrector stage into mu = lhalf, then lam_in += mu + predictor^T mu
     const StateW lin = as_mut(lam_in);
     const unsigned gf = nblocks((size_t)(g.n[0] + 1) * (g.n[1] + 1) * (g.n[2] + 1));
-    k_ad_init<<<gf, kBlock, 0, s>>>(g, as_const(lam_out), lnext, lin);
-    fill(lhalf.u[0], L.lhalf_span, s);
-    stage_adjoint(g, 1.0, as_const(lnext), hc, P[1], sides[1], vg->recon, S, L.lw_span, lhalf,
+    k_ad_init<<<gf, kBlock, 0, s>>>(g, as_const(lam_out), lnext, lhalf);
+    stage_adjoint(g, 1.0, as_const(lnext), hc, P[1], sides[1], vg->recon, S, lhalf,
                   dt_dev, s);
-    k_ad_add<<<gf, kBlock, 0, s>>>(g, lin, as_const(lhalf));
-    stage_adjoint(g, 0.5, as_const(lhalf), sin, P[0], sides[0], VLCT_RECON_PCM, S, L.lw_span, lin,
+    k_ad_add<<<gf, kBlock, 0, s>>>(g, lin, as_const(lnext), as_const(lhalf));
+    stage_adjoint(g, 0.5, as_const(lhalf), sin, P[0], sides[0], VLCT_RECON_PCM, S, lin,
                   dt_dev, s);
     return hipGetLastError() == hipSuccess ? VLCT_OK : VLCT_EHIP;
 }
