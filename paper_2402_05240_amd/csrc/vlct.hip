@@ -827,9 +827,18 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
     using S = PredShape<TX, TY>;
     constexpr int CX = S::CX, CY = S::CY, NC = S::NC;
     constexpr int NEZ = S::NEZ, NEX = S::NEX, NEY = S::NEY;
-    // W of the newest plane (8 primitives), later the hydro fluxes of the
-    // plane being updated (x: 0-4, y: 5-9)
+    // W of the newest plane (8 primitives) and the hydro fluxes of the plane
+    // being updated (x: 0-4, y: 5-9).  ONE_RUN keeps them apart (155 KB of
+    // LDS in all), so that the next plane's primitives can be written while
+    // the update still reads the fluxes and the barrier closing each plane
+    // goes; the share form (a run loop, more registers) keeps both in s_wh
+    // and the barrier, which measured faster there.
+    __shared__ double s_pr[ONE_RUN ? 8 : 1][ONE_RUN ? NC : 1];
     __shared__ double s_wh[10][NC];
+    auto PR = [&](int q, int c) -> double & {
+        if constexpr (ONE_RUN) return s_pr[q][c];
+        else return s_wh[q][c];
+    };
     // reference fields: x and y components of the two newest planes (slot =
     // plane & 1), z component of the newest plane
     __shared__ double s_rx[2][NC], s_ry[2][NC], s_rz[NC];
@@ -923,14 +932,14 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
                 const double me = 0.5 * (bcx * bcx + bcy * bcy + bcz * bcz);
                 double pr = (g.gamma - 1.0) * (pf[4] - ke - me);
                 if (!(pr >= kFloorP)) { pr = kFloorP; st |= kStatusPressureFloor; }
-                s_wh[0][t] = d;
-                s_wh[1][t] = vx;
-                s_wh[2][t] = vy;
-                s_wh[3][t] = vz;
-                s_wh[4][t] = pr;
-                s_wh[5][t] = bcx;
-                s_wh[6][t] = bcy;
-                s_wh[7][t] = bcz;
+                PR(0, t) = d;
+                PR(1, t) = vx;
+                PR(2, t) = vy;
+                PR(3, t) = vz;
+                PR(4, t) = pr;
+                PR(5, t) = bcx;
+                PR(6, t) = bcy;
+                PR(7, t) = bcz;
                 s_rx[sm][t] = -(vy * bcz - vz * bcy);
                 s_ry[sm][t] = -(vz * bcx - vx * bcz);
                 s_rz[t] = -(vx * bcy - vy * bcx);
@@ -940,12 +949,12 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
             double hxn[5] = {}, hyn[5] = {}, hzn[5] = {};
             W7 wz{};
             if (live) {
-                const W7 wxr{s_wh[0][t], s_wh[1][t], s_wh[2][t], s_wh[3][t], s_wh[4][t], s_wh[6][t], s_wh[7][t]};
-                wz = W7{s_wh[0][t], s_wh[3][t], s_wh[1][t], s_wh[2][t], s_wh[4][t], s_wh[5][t], s_wh[6][t]};
+                const W7 wxr{PR(0, t), PR(1, t), PR(2, t), PR(3, t), PR(4, t), PR(6, t), PR(7, t)};
+                wz = W7{PR(0, t), PR(3, t), PR(1, t), PR(2, t), PR(4, t), PR(5, t), PR(6, t)};
                 double f[7], upw;
                 if (do_x) {
                     const int l = t - 1;
-                    const W7 wl{s_wh[0][l], s_wh[1][l], s_wh[2][l], s_wh[3][l], s_wh[4][l], s_wh[6][l], s_wh[7][l]};
+                    const W7 wl{PR(0, l), PR(1, l), PR(2, l), PR(3, l), PR(4, l), PR(6, l), PR(7, l)};
                     hlld(wl, wxr, bx0, g.gamma, g.gm1i, f, upw);
 #pragma unroll
                     for (int q = 0; q < 5; ++q) hxn[q] = f[q];
@@ -955,8 +964,8 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
                 }
                 if (do_y) {
                     const int l = t - CX;
-                    const W7 wl{s_wh[0][l], s_wh[2][l], s_wh[3][l], s_wh[1][l], s_wh[4][l], s_wh[7][l], s_wh[5][l]};
-                    const W7 wr{s_wh[0][t], s_wh[2][t], s_wh[3][t], s_wh[1][t], s_wh[4][t], s_wh[7][t], s_wh[5][t]};
+                    const W7 wl{PR(0, l), PR(2, l), PR(3, l), PR(1, l), PR(4, l), PR(7, l), PR(5, l)};
+                    const W7 wr{PR(0, t), PR(2, t), PR(3, t), PR(1, t), PR(4, t), PR(7, t), PR(5, t)};
                     hlld(wl, wr, by0, g.gamma, g.gm1i, f, upw);
 #pragma unroll
                     for (int q = 0; q < 5; ++q) hyn[q] = f[q];
@@ -1130,7 +1139,11 @@ __device__ __forceinline__ void pred_body(const Geom &g, const StateP &s, const 
                 hz_lo[q] = hzn[q];
             }
             wz_prev = wz;
-            __syncthreads();
+            // ONE_RUN needs no barrier here: the next plane's (A) writes only
+            // s_pr and the reference fields, which (D) does not read, and
+            // everything (D) reads is next written after the barrier that
+            // closes (A)
+            if (!ONE_RUN) __syncthreads();
         }
     };
     if (ONE_RUN) {
