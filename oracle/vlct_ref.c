@@ -469,7 +469,10 @@ static double ppm_face(double am, double a0, double ap, double app)
             double s = sgn_pos(d2);
             lim = s * dmin(dmin(PPM_C * fabs(d2l), PPM_C * fabs(d2r)), fabs(d2));
         }
-        f = 0.5 * (a0 + ap) - lim / 3.0;
+        /* d2, d2l and d2r all equal h^2 f'' on a parabola, so the limited
+         * value is written with d2 / 6: where the limiter does not bind
+         * (lim = d2) it returns the fourth-order value f unchanged */
+        f = 0.5 * (a0 + ap) - lim / 6.0;
     }
     return f;
 }

@@ -817,13 +817,13 @@ VLCT_DEV void ppm_face_rev(double am, double a0, double ap, double app, double a
     const double f0 = (7.0 / 12.0) * (a0 + ap) - (1.0 / 12.0) * (am + app);
     double a_f0 = 0.0;
     if ((f0 - a0) * (ap - f0) < 0.0) {
-        // f = (a0 + ap) / 2 - lim / 3
+        // f = (a0 + ap) / 2 - lim / 6
         const double d2 = 3.0 * (a0 - 2.0 * f0 + ap);
         const double d2l = am - 2.0 * a0 + ap;
         const double d2r = a0 - 2.0 * ap + app;
         a_a0 = a_a0 + 0.5 * af;
         a_ap = a_ap + 0.5 * af;
-        const double a_lim = -af / 3.0;
+        const double a_lim = -af / 6.0;
         if (d2 * d2l > 0.0 && d2 * d2r > 0.0) {
             // lim = sign(d2) min(C |d2l|, C |d2r|, |d2|): all three share d2's sign
             const double A = kPpmC * fabs(d2l), Bv = kPpmC * fabs(d2r), Cv = fabs(d2);

@@ -434,7 +434,9 @@ VLCT_DEV double ppm_face(double am, double a0, double ap, double app)
         double lim = 0.0;
         if (d2 * d2l > 0.0 && d2 * d2r > 0.0)
             lim = copysign(fmin(fmin(kPpmC * fabs(d2l), kPpmC * fabs(d2r)), fabs(d2)), d2);
-        f = 0.5 * (a0 + ap) - lim * (1.0 / 3.0);
+        // all three curvature estimates are h^2 f'' on a parabola: with
+        // lim = d2 (limiter not binding) this gives back the fourth-order f
+        f = 0.5 * (a0 + ap) - lim * (1.0 / 6.0);
     }
     return f;
 }

@@ -94,9 +94,12 @@ def test_einfeldt_stays_positive(recon):
     assert p.min() > 0.0
     # the rarefaction empties the centre: density there falls well below 1
     assert rho[0, 0, N // 2] < 0.1
-    # mirror symmetry of the symmetric problem
+    # mirror symmetry of the symmetric problem, up to rounding: the sweep's
+    # arithmetic is not mirror-symmetric operation by operation, and the
+    # characteristic projections carry its rounding differences over the run
+    # (a few 1e-12 on densities of order one with PPMC)
     prof = rho[0, 0, :]
-    assert np.max(np.abs(prof - prof[::-1])) <= 1e-12
+    assert np.max(np.abs(prof - prof[::-1])) <= 1e-11
 
 
 @pytest.mark.parametrize("name", ["brio_wu", "dai_woodward", "ryu_jones_4d", "einfeldt"])

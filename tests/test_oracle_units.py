@@ -472,6 +472,89 @@ def test_ppmc_step_data_creates_no_new_extrema():
         assert np.all(fm >= lo) and np.all(fm <= hi) and np.all(fp >= lo) and np.all(fp <= hi)
 
 
+def _ppmc_along_field(s, expect_m, expect_p, seed, reps=40):
+    """Cells i-2..i+2 equal to W + eps s_j r_m, with r_m a right eigenvector
+    of the central cell: every limiter step then acts on field m alone, whose
+    characteristic values are s_j (times a constant), and the interface
+    states must be W + eps c r_m with the c expected for the scalar data s."""
+    rng = np.random.default_rng(seed)
+    for _ in range(reps):
+        W, bn = _cell_state(rng)
+        R, L, _ = ref.eigen(W, bn, GAM)
+        m = int(rng.integers(0, 7))
+        r = R[:, m] / np.abs(R[:, m]).max()
+        eps = 1e-3 * min(W[0], W[4])
+        fm, fp = ref.ppmc(np.stack([W + eps * sj * r for sj in s]), bn, GAM)
+        tol = 1e-12 * np.abs(W).max()
+        assert np.abs(fm - (W + eps * expect_m * r)).max() <= tol, (m, s)
+        assert np.abs(fp - (W + eps * expect_p * r)).max() <= tol, (m, s)
+
+
+@pytest.mark.parametrize("curv", [1.0, -1.0])
+def test_ppmc_parabola_with_extremum_in_the_cell_is_exact(curv):
+    """Cell averages of a parabola whose vertex lies inside the central cell
+    (within 1/6 of its centre, so neither face value passes a neighbour's
+    average): the extremum test fires, every curvature estimate equals the
+    parabola's, so the Colella-Sekora limiter leaves the face values alone
+    and both interfaces carry the parabola's exact values.  A limiter that
+    flattens smooth extrema, or a wrong sign or scale in the curvature ratio,
+    fails here."""
+    rng = np.random.default_rng(31)
+    for v in rng.uniform(-0.15, 0.15, 6):
+        p = lambda x: curv * (x - v) ** 2
+        avg = lambda j: curv * (((j + 0.5 - v) ** 3 - (j - 0.5 - v) ** 3) / 3.0)
+        s = [avg(j) - avg(0) for j in range(-2, 3)]
+        _ppmc_along_field(s, p(-0.5) - avg(0), p(0.5) - avg(0), seed=int(1e6 * abs(v)), reps=10)
+
+
+def test_ppmc_parabola_with_vertex_on_a_face():
+    """Cell averages of -(x - 1/2)^2, whose vertex sits on the central cell's
+    right face, are (-19, -7, -1, -1, -7)/3; relative to the cell they are
+    s = (-6, -2, 0, 0, -2).  The far (left) face must get the parabola's
+    exact value, -1, i.e. -2/3 relative to the cell average; the right
+    face, shared by two equal cells, stays at their common value.  The face
+    limiter fires at the right face (its fourth-order value lies above both
+    cells); with its recombination written so that an unbinding limiter
+    returns the fourth-order value, the curvature it passes on is the
+    parabola's.  A recombination that overshoots that value (D2/3 instead of
+    D2/6) leaves the curvature estimate of the cell at rounding level, and
+    the left face flattens for some fields and not for others."""
+    _ppmc_along_field((-6, -2, 0, 0, -2), -2.0 / 3.0, 0.0, seed=32)
+    _ppmc_along_field((-2, 0, 0, -2, -6), 0.0, -2.0 / 3.0, seed=33)
+    _ppmc_along_field((6, 2, 0, 0, 2), 2.0 / 3.0, 0.0, seed=34)
+
+
+def test_ppmc_isolated_spike_is_flattened():
+    """One cell above four equal neighbours: an extremum whose curvature
+    estimates disagree in sign (the neighbours' second differences are
+    positive, the cell's negative), which the Colella-Sekora limiter treats
+    as non-smooth: both interface values fall back to the cell average."""
+    _ppmc_along_field((0, 0, 1, 0, 0), 1.0, 1.0, seed=35)
+    _ppmc_along_field((0, 0, -1, 0, 0), -1.0, -1.0, seed=36)
+
+
+def test_ppmc_overshoot_correction():
+    """Monotone data s = (-1, -1/2, 0, 2, 4): the fourth-order face values are
+    -3/8 and 7/8, both inside their neighbour intervals, but the parabola
+    through them would turn inside the cell (|dp| >= 2 |dm|).  The
+    Colella-Woodward correction moves the steep face to twice the other's
+    offset (3/4), after which the parabola's slope vanishes at the left
+    face: 3 a = 2 a_L + a_R."""
+    _ppmc_along_field((-1, -0.5, 0, 2, 4), -0.375, 0.75, seed=37)
+    _ppmc_along_field((4, 2, 0, -0.5, -1), 0.75, -0.375, seed=38)
+
+
+def test_ppmc_face_limiter_on_a_kink():
+    """s = (-1/10, -1/10, 0, 9/10, 1): the fourth-order value of the left face,
+    -1/8, undershoots both cells sharing it, so the face limiter acts.  Its
+    curvature estimates are 3(a_{i-1} - 2 f + a_i) = 9/20, a_{i-2} - 2a_{i-1} +
+    a_i = 1/10 and a_{i-1} - 2 a_i + a_{i+1} = 4/5, all positive, so the
+    limited curvature is 1.25 x 1/10 = 1/8 and the face value is
+    (a_{i-1} + a_i)/2 - (1/8)/6 = -17/240.  The right face, 9/20, is inside
+    its interval; the overshoot correction then sets it to 2 x 17/240."""
+    _ppmc_along_field((-0.1, -0.1, 0, 0.9, 1.0), -17.0 / 240.0, 34.0 / 240.0, seed=39)
+
+
 # ---------------------------------------------------------------------------
 # primitive-variable limiting (Sec. 2.2 Step 6: skip the projections)
 # ---------------------------------------------------------------------------
