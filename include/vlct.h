@@ -231,7 +231,10 @@ size_t vlct_adjoint_workspace_bytes(const vlct_grid *g);
  * the step size.  Periodic boundaries on every axis only (else
  * VLCT_EUNSUPPORTED); every corrector reconstruction.  VLCT_EWORKSPACE if
  * ws_bytes < vlct_adjoint_workspace_bytes(g).  Stream-ordered; no
- * allocation and no host synchronisation. */
+ * allocation and no host synchronisation.  Not bit-reproducible from run to
+ * run: where a cell gathers cotangents from the reconstructions of several
+ * faces they are summed with FP64 atomics, whose order of addition varies,
+ * so two runs on the same input differ at rounding level. */
 int vlct_step_adjoint(const vlct_grid *g, const vlct_state *in, const vlct_state *lam_out,
                       const vlct_state *lam_in, const double *dt_dev, void *ws, size_t ws_bytes,
                       void *stream);
