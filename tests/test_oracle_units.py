@@ -472,11 +472,13 @@ def test_ppmc_step_data_creates_no_new_extrema():
         assert np.all(fm >= lo) and np.all(fm <= hi) and np.all(fp >= lo) and np.all(fp <= hi)
 
 
-def _ppmc_along_field(s, expect_m, expect_p, seed, reps=40):
+def _ppmc_along_field(s, expect_m, expect_p, seed, reps=40, ppmc=None):
     """Cells i-2..i+2 equal to W + eps s_j r_m, with r_m a right eigenvector
     of the central cell: every limiter step then acts on field m alone, whose
     characteristic values are s_j (times a constant), and the interface
-    states must be W + eps c r_m with the c expected for the scalar data s."""
+    states must be W + eps c r_m with the c expected for the scalar data s.
+    `ppmc` is the reconstruction under test (the oracle's by default)."""
+    ppmc = ppmc or ref.ppmc
     rng = np.random.default_rng(seed)
     for _ in range(reps):
         W, bn = _cell_state(rng)
@@ -484,7 +486,7 @@ def _ppmc_along_field(s, expect_m, expect_p, seed, reps=40):
         m = int(rng.integers(0, 7))
         r = R[:, m] / np.abs(R[:, m]).max()
         eps = 1e-3 * min(W[0], W[4])
-        fm, fp = ref.ppmc(np.stack([W + eps * sj * r for sj in s]), bn, GAM)
+        fm, fp = ppmc(np.stack([W + eps * sj * r for sj in s]), bn, GAM)
         tol = 1e-12 * np.abs(W).max()
         assert np.abs(fm - (W + eps * expect_m * r)).max() <= tol, (m, s)
         assert np.abs(fp - (W + eps * expect_p * r)).max() <= tol, (m, s)
