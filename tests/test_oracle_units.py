@@ -535,6 +535,18 @@ def test_ppmc_isolated_spike_is_flattened():
     _ppmc_along_field((0, 0, -1, 0, 0), -1.0, -1.0, seed=36)
 
 
+def test_ppmc_curvature_limiter_binding_at_a_peak():
+    """s = (-3/10, -1/10, 0, -1/10, -3/10): a peak whose curvature narrows
+    towards it.  Both fourth-order face values are -1/40, inside their
+    intervals; the extremum test fires.  The curvature of the parabola
+    through them, 6 (f_l - 2 a_i + f_r) = -3/10, exceeds 1.25 times the
+    neighbours' second differences (-1/10 each; the cell's own is -1/5), so
+    the limited curvature is -1.25/10 and both face offsets scale by
+    (1/8) / (3/10) = 5/12: both faces at -1/96."""
+    _ppmc_along_field((-0.3, -0.1, 0, -0.1, -0.3), -1.0 / 96.0, -1.0 / 96.0, seed=40)
+    _ppmc_along_field((0.3, 0.1, 0, 0.1, 0.3), 1.0 / 96.0, 1.0 / 96.0, seed=41)
+
+
 def test_ppmc_overshoot_correction():
     """Monotone data s = (-1, -1/2, 0, 2, 4): the fourth-order face values are
     -3/8 and 7/8, both inside their neighbour intervals, but the parabola

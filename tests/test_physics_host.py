@@ -119,6 +119,7 @@ def test_device_ppmc_limiter_branches(ppm_probe):
     _ppmc_along_field((-6, -2, 0, 0, -2), -2.0 / 3.0, 0.0, seed=41, ppmc=one)
     _ppmc_along_field((-2, 0, 0, -2, -6), 0.0, -2.0 / 3.0, seed=42, ppmc=one)
     _ppmc_along_field((0, 0, 1, 0, 0), 1.0, 1.0, seed=43, ppmc=one)
+    _ppmc_along_field((-0.3, -0.1, 0, -0.1, -0.3), -1.0 / 96.0, -1.0 / 96.0, seed=47, ppmc=one)
     _ppmc_along_field((-1, -0.5, 0, 2, 4), -0.375, 0.75, seed=44, ppmc=one)
     _ppmc_along_field((-0.1, -0.1, 0, 0.9, 1.0), -17.0 / 240.0, 34.0 / 240.0, seed=45, ppmc=one)
 
