@@ -472,19 +472,22 @@ def test_ppmc_step_data_creates_no_new_extrema():
         assert np.all(fm >= lo) and np.all(fm <= hi) and np.all(fp >= lo) and np.all(fp <= hi)
 
 
-def _ppmc_along_field(s, expect_m, expect_p, seed, reps=40, ppmc=None):
+def _ppmc_along_field(s, expect_m, expect_p, seed, reps=40, ppmc=None, primitive=False):
     """Cells i-2..i+2 equal to W + eps s_j r_m, with r_m a right eigenvector
     of the central cell: every limiter step then acts on field m alone, whose
     characteristic values are s_j (times a constant), and the interface
     states must be W + eps c r_m with the c expected for the scalar data s.
-    `ppmc` is the reconstruction under test (the oracle's by default)."""
-    ppmc = ppmc or ref.ppmc
+    `ppmc` is the reconstruction under test (the oracle's by default).
+    primitive: r_m is the unit vector of primitive m instead, for the
+    primitive-variable form (PPMP, the oracle's by default), whose steps act
+    on each primitive alone."""
+    ppmc = ppmc or (ref.ppmp if primitive else ref.ppmc)
     rng = np.random.default_rng(seed)
     for _ in range(reps):
         W, bn = _cell_state(rng)
         R, L, _ = ref.eigen(W, bn, GAM)
         m = int(rng.integers(0, 7))
-        r = R[:, m] / np.abs(R[:, m]).max()
+        r = np.eye(7)[m] if primitive else R[:, m] / np.abs(R[:, m]).max()
         eps = 1e-3 * min(W[0], W[4])
         fm, fp = ppmc(np.stack([W + eps * sj * r for sj in s]), bn, GAM)
         tol = 1e-12 * np.abs(W).max()
@@ -567,6 +570,31 @@ def test_ppmc_face_limiter_on_a_kink():
     (a_{i-1} + a_i)/2 - (1/8)/6 = -17/240.  The right face, 9/20, is inside
     its interval; the overshoot correction then sets it to 2 x 17/240."""
     _ppmc_along_field((-0.1, -0.1, 0, 0.9, 1.0), -17.0 / 240.0, 34.0 / 240.0, seed=39)
+
+
+def ppm_branch_cases():
+    """(s, expected low-face, expected high-face) for every limiter branch,
+    worked out in the PPMC pins above."""
+    cases = []
+    for curv in (1.0, -1.0):
+        for v in (-0.12, 0.0, 0.07):
+            p = lambda x, v=v, curv=curv: curv * (x - v) ** 2
+            avg = lambda j, v=v, curv=curv: curv * (((j + 0.5 - v) ** 3 - (j - 0.5 - v) ** 3) / 3.0)
+            cases.append(([avg(j) - avg(0) for j in range(-2, 3)], p(-0.5) - avg(0), p(0.5) - avg(0)))
+    cases += [((-6, -2, 0, 0, -2), -2.0 / 3.0, 0.0), ((-2, 0, 0, -2, -6), 0.0, -2.0 / 3.0),
+              ((0, 0, 1, 0, 0), 1.0, 1.0),
+              ((-0.3, -0.1, 0, -0.1, -0.3), -1.0 / 96.0, -1.0 / 96.0),
+              ((-1, -0.5, 0, 2, 4), -0.375, 0.75),
+              ((-0.1, -0.1, 0, 0.9, 1.0), -17.0 / 240.0, 34.0 / 240.0)]
+    return cases
+
+
+def test_ppmp_limiter_branches_per_primitive():
+    """PPMP takes the same limiter steps on each primitive alone (Sec. 2.2
+    Step 6, projections skipped): the branch pins of PPMC hold for data that
+    vary in one primitive."""
+    for q, (s, em, ep) in enumerate(ppm_branch_cases()):
+        _ppmc_along_field(s, em, ep, seed=60 + q, reps=10, primitive=True)
 
 
 # ---------------------------------------------------------------------------

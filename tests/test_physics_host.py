@@ -13,7 +13,8 @@ import numpy as np
 import pytest
 
 from oracle import ref
-from test_oracle_units import GAM, _cons_from_prim, _ppmc_along_field, _rotational_discontinuity
+from test_oracle_units import (GAM, _cons_from_prim, _ppmc_along_field, _rotational_discontinuity,
+                               ppm_branch_cases)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(os.path.dirname(HERE), "paper_2402_05240_amd", "csrc")
@@ -105,23 +106,15 @@ def ppm_probe(tmp_path_factory):
     return run
 
 
-def test_device_ppmc_limiter_branches(ppm_probe):
-    """The oracle's branch-by-branch PPMC pins, on the device header."""
+@pytest.mark.parametrize("primitive", [False, True])
+def test_device_ppm_limiter_branches(ppm_probe, primitive):
+    """The oracle's branch-by-branch PPM pins, on the device header: PPMC along
+    one characteristic field, PPMP along one primitive."""
     def one(sten, bn, gam):
-        fm, fp = ppm_probe([sten], [bn], gam)
+        fm, fp = ppm_probe([sten], [bn], gam, primitive=primitive)
         return fm[0], fp[0]
-    for curv in (1.0, -1.0):
-        for v in (-0.12, 0.0, 0.07):
-            p = lambda x: curv * (x - v) ** 2
-            avg = lambda j: curv * (((j + 0.5 - v) ** 3 - (j - 0.5 - v) ** 3) / 3.0)
-            s = [avg(j) - avg(0) for j in range(-2, 3)]
-            _ppmc_along_field(s, p(-0.5) - avg(0), p(0.5) - avg(0), seed=40, reps=8, ppmc=one)
-    _ppmc_along_field((-6, -2, 0, 0, -2), -2.0 / 3.0, 0.0, seed=41, ppmc=one)
-    _ppmc_along_field((-2, 0, 0, -2, -6), 0.0, -2.0 / 3.0, seed=42, ppmc=one)
-    _ppmc_along_field((0, 0, 1, 0, 0), 1.0, 1.0, seed=43, ppmc=one)
-    _ppmc_along_field((-0.3, -0.1, 0, -0.1, -0.3), -1.0 / 96.0, -1.0 / 96.0, seed=47, ppmc=one)
-    _ppmc_along_field((-1, -0.5, 0, 2, 4), -0.375, 0.75, seed=44, ppmc=one)
-    _ppmc_along_field((-0.1, -0.1, 0, 0.9, 1.0), -17.0 / 240.0, 34.0 / 240.0, seed=45, ppmc=one)
+    for q, (s, em, ep) in enumerate(ppm_branch_cases()):
+        _ppmc_along_field(s, em, ep, seed=80 + q, reps=8, ppmc=one, primitive=primitive)
 
 
 @pytest.mark.parametrize("primitive", [False, True])
