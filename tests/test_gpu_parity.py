@@ -164,7 +164,7 @@ def test_turbulence_128_hundred_steps(recon, capsys):
     This flow amplifies rounding differences: the oracle against itself with
     every density moved by one ulp differs (PLMC) by ~1e-15 relative L1 up to
     step 40 and by ~5e-9 (1e-3 of the scale in the worst cell) at step 100;
-    PPMC amplifies sooner.  No implementation that rounds differently from
+    PPMC by about as much.  No implementation that rounds differently from
     the oracle can meet 1e-12 there (reading R48).  The bar, per variable,
     after 40 and after 100 steps: relative L1 within max(1e-12, 10x the
     oracle's own 1-ulp sensitivity), the worst element within max(1e-9, 10x
