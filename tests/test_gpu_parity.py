@@ -152,6 +152,57 @@ def test_turbulence_multi_step(recon, nsteps):
     assert abs(nexts[-1] - nexts_ref[-1]) <= 1e-12 * nexts_ref[-1]
 
 
+def _shaped_state(n, recon, bc, seed):
+    """A state for any grid shape: smooth random low-k fields (no variation
+    along axes thinner than 9 cells) times 2% cell-to-cell noise in density
+    and pressure, Mach ~0.3 velocities, B = (0.8, 0, 0) + curl A with A
+    smooth plus noise scaled by the smallest cell (divergence-free)."""
+    g = I.Grid(n[0], n[1], n[2], 1.0 / n[0], 1.0 / n[1], 1.0 / n[2], 5.0 / 3.0, 0.4, recon, bc)
+    rng = np.random.default_rng(seed)
+    x, y, z = I._centres(g)
+    shape = (g.nz, g.ny, g.nx)
+
+    def smooth():
+        f = np.zeros(shape)
+        for _ in range(4):
+            k = rng.integers(-2, 3, 3) * (np.array(n) >= 9)
+            f = f + rng.normal() * np.cos(2 * np.pi * (k[0] * x + k[1] * y + k[2] * z)
+                                          + rng.uniform(0, 2 * np.pi))
+        return f
+    noise = lambda a: 1.0 + a * rng.uniform(-1.0, 1.0, shape)
+    rho = (1.0 + 0.1 * smooth()) * noise(0.02)
+    v = [0.3 * smooth() for _ in range(3)]
+    p = 0.6 * (1.0 + 0.1 * smooth()) * noise(0.02)
+    a = [0.05 * smooth() + 0.02 * min(g.dx, g.dy, g.dz) * rng.normal(size=shape)
+         for _ in range(3)]
+    bx, by, bz = I.curl_edge_potential(g, *a)
+    bx = bx + 0.8
+    s0 = {"rho": rho, "mx": rho * v[0], "my": rho * v[1], "mz": rho * v[2],
+          "bx": bx, "by": by, "bz": bz}
+    s0["E"] = I._cell_energy(g, rho, v[0], v[1], v[2], p, bx, by, bz)
+    return g, s0
+
+
+@pytest.mark.parametrize("shape,bc,recon", [
+    ((4096, 3, 2), (0, 0, 0), 2), ((2, 4096, 3), (0, 1, 0), 3), ((3, 2, 4096), (1, 0, 0), 2),
+    ((4096, 1, 1), (1, 1, 1), 5), ((1, 7, 5), (0, 0, 0), 2), ((6, 1, 1), (0, 0, 0), 3)])
+def test_extreme_shapes(shape, bc, recon):
+    """Sides at the limits the library accepts: one side of 4096 cells (the
+    largest) along each axis with the other two 1-3 cells thick, periodic and
+    outflow, and grids one cell thick along one or two axes (a periodic
+    stencil then wraps onto the cell itself); 10 steps element by element
+    against the oracle on its own dt sequence."""
+    _need_gpu()
+    g, s0 = _shaped_state(shape, recon, bc, 7)
+    _say("oracle: %s bc %s recon %d, 10 steps" % (shape, bc, recon))
+    orc, dts, nexts_ref, st_ref = _oracle_run(g, s0, nsteps=10)
+    _say("gpu")
+    gpu, nexts, status = _gpu_run(g, s0, dts)
+    assert status == st_ref
+    _check(g, s0, gpu, orc)
+    assert abs(nexts[-1] - nexts_ref[-1]) <= 1e-12 * nexts_ref[-1]
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("recon", [2, 3])
 def test_turbulence_128_hundred_steps(recon, capsys):
