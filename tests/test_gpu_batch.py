@@ -72,6 +72,33 @@ def test_batch_equals_single_instances(recon, nsteps):
         assert status[q] == ref_status, q
 
 
+def test_batch_extreme_shapes_equal_single_instances():
+    """Instances at the shape limits in one batch (a 4096-cell side, grids one
+    cell thick along one or two axes, outflow and periodic, next to an
+    ordinary grid): each equals its single-instance run bit for bit."""
+    _need_gpu()
+    from paper_2402_05240_amd.device import BatchStepper
+    import torch
+    from test_gpu_parity import _shaped_state
+    inst = [_shaped_state((4096, 3, 2), 2, (0, 0, 0), 7), _shaped_state((1, 7, 5), 2, (0, 0, 0), 8),
+            _shaped_state((6, 1, 1), 2, (1, 0, 0), 9), _shaped_state((11, 10, 9), 2, (0, 1, 0), 10)]
+    dts = [ref.cfl_dt(g, s) for g, s in inst]
+    _say("batch of %d extreme-shape instances" % len(inst))
+    bs = BatchStepper([g for g, _ in inst]).upload([s for _, s in inst])
+    bs.set_dt(dts)
+    for _ in range(3):
+        bs.step()
+    torch.cuda.synchronize()
+    outs = bs.download()
+    status = bs.status_bits()
+    for q, ((g, s0), dt) in enumerate(zip(inst, dts)):
+        _say("single instance %d: %s" % (q, (g.nx, g.ny, g.nz)))
+        ref_out, _, ref_status = _single(g, s0, dt, 3)
+        for f in FIELDS:
+            assert np.array_equal(outs[q][f], ref_out[f]), (q, f)
+        assert status[q] == ref_status, q
+
+
 def test_batch_instance_matches_oracle():
     _need_gpu()
     from paper_2402_05240_amd.device import BatchStepper
