@@ -281,3 +281,33 @@ def test_adjoint_complex_step_multi_segment_grid(cso, recon, admarch, monkeypatc
     _say("recon %d, 40x36x34: worst rel err against complex step %.2e" % (recon, worst))
     assert worst <= 1e-10
 
+
+
+@pytest.mark.parametrize("shape", [(16, 12, 1), (1, 9, 10), (12, 1, 11), (10, 2, 9)])
+@pytest.mark.parametrize("recon", [I.RECON_PLMC, I.RECON_PPMC])
+def test_adjoint_complex_step_thin_grids(cso, recon, shape):
+    """Periodic grids one cell thick along each axis in turn, and two cells
+    thick along y: a cell is then its own neighbour (or its neighbour's
+    neighbour), so the reversal's accumulation into the stencil cells and the
+    marches' and rows' hand-offs wrap onto the same cells.  <lam_in, delta>
+    against the complex step of the oracle along random directions, within
+    1e-10."""
+    _need_gpu()
+    from test_gpu_parity import _shaped_state
+    g, s = _shaped_state(shape, recon, (0, 0, 0), 21)
+    dt = ref.cfl_dt(g, s)
+    lam = _random_cotangent(g, 22)
+    lin = _gpu_vjp(g, s, lam, dt)
+    rng = np.random.default_rng(23)
+    worst = 0.0
+    for _ in range(3):
+        delta = {f: rng.standard_normal(g.field_shape(f)) for f in FIELDS}
+        I._periodic_face_copy(g, delta)
+        _, jv, st = cso.jvp(g, s, delta, [dt])
+        assert st == 0
+        want = sum(float(np.sum(lam[f] * jv[f])) for f in FIELDS)
+        scale = sum(float(np.sum(np.abs(lam[f] * jv[f]))) for f in FIELDS)
+        got = sum(float(np.sum(lin[f] * delta[f])) for f in FIELDS)
+        worst = max(worst, abs(got - want) / scale)
+    _say("recon %d, %s: worst rel err against complex step %.2e" % (recon, shape, worst))
+    assert worst <= 1e-10

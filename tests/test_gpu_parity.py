@@ -154,9 +154,12 @@ def test_turbulence_multi_step(recon, nsteps):
 
 def _shaped_state(n, recon, bc, seed):
     """A state for any grid shape: smooth random low-k fields (no variation
-    along axes thinner than 9 cells) times 2% cell-to-cell noise in density
-    and pressure, Mach ~0.3 velocities, B = (0.8, 0, 0) + curl A with A
-    smooth plus noise scaled by the smallest cell (divergence-free)."""
+    along axes thinner than 9 cells) with cell-to-cell noise (2% in density
+    and pressure, 0.02 in the velocities, Mach ~0.3), B = (0.8, 0, 0) +
+    curl A with A smooth plus noise scaled by the smallest cell
+    (divergence-free).  The noise leaves no two cells with equal values, so
+    no branch of the step (limiter, wave region, upwind side) sits on a tie,
+    where the step has no derivative."""
     g = I.Grid(n[0], n[1], n[2], 1.0 / n[0], 1.0 / n[1], 1.0 / n[2], 5.0 / 3.0, 0.4, recon, bc)
     rng = np.random.default_rng(seed)
     x, y, z = I._centres(g)
@@ -171,7 +174,7 @@ def _shaped_state(n, recon, bc, seed):
         return f
     noise = lambda a: 1.0 + a * rng.uniform(-1.0, 1.0, shape)
     rho = (1.0 + 0.1 * smooth()) * noise(0.02)
-    v = [0.3 * smooth() for _ in range(3)]
+    v = [0.3 * smooth() + 0.02 * rng.uniform(-1.0, 1.0, shape) for _ in range(3)]
     p = 0.6 * (1.0 + 0.1 * smooth()) * noise(0.02)
     a = [0.05 * smooth() + 0.02 * min(g.dx, g.dy, g.dz) * rng.normal(size=shape)
          for _ in range(3)]
