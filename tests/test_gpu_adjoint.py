@@ -284,7 +284,7 @@ def test_adjoint_complex_step_multi_segment_grid(cso, recon, admarch, monkeypatc
 
 
 @pytest.mark.parametrize("shape", [(16, 12, 1), (1, 9, 10), (12, 1, 11), (10, 2, 9)])
-@pytest.mark.parametrize("recon", [I.RECON_PLMC, I.RECON_PPMC])
+@pytest.mark.parametrize("recon", [I.RECON_PLMC, I.RECON_PPMC, I.RECON_PLMP, I.RECON_PPMP])
 def test_adjoint_complex_step_thin_grids(cso, recon, shape):
     """Periodic grids one cell thick along each axis in turn, and two cells
     thick along y: a cell is then its own neighbour (or its neighbour's
